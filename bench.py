@@ -1,0 +1,209 @@
+"""Benchmark: compressed vs uncompressed out-of-core 7-point stencil sweeps.
+
+Workload (the compressed out-of-core configuration): 7-point Jacobi/heat
+stencil (c0 = 0.4, c1..c6 = 0.1), FP32, 512 x 512 x 2048 cells (2 GiB per
+field, two host time levels), zero Dirichlet boundary, device budget 512 MiB,
+z-slabs of S = 64 planes, temporal block k = 4, 64 time steps per job, seeded
+Gaussian random field with power spectral density ~ |k|^-3.
+
+One bench "step" = one whole out-of-core job: oc_run(64) = 16 sweeps x 32
+slabs, every slab copied in, decoded, advanced 4 steps, encoded and copied
+back, with the host-resident state already loaded (pinned) when timing starts.
+`value` = GCell-updates/s of the compressed (R = 16 bits/value, single working
+buffer) path; the uncompressed path is timed on the same GPU beside it.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+C = (0.4, 0.1, 0.1, 0.1, 0.1, 0.1, 0.1)
+SHAPE = (2048, 512, 512)
+K, S, STEPS, BUDGET = 4, 64, 64, 512 << 20
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def rel_l2(a, b):
+    d = 0.0
+    n = 0.0
+    for z in range(0, a.shape[0], 128):   # chunked FP64 reduction
+        x = a[z:z + 128].astype(np.float64)
+        y = b[z:z + 128].astype(np.float64)
+        d += float(np.sum((x - y) ** 2))
+        n += float(np.sum(y * y))
+    return (d / n) ** 0.5
+
+
+def run_leg(oc, torch, u0, rate, steps, warmup, ref=None, timing=True):
+    o = oc.OutOfCore(SHAPE, C, k=K, rate=rate, budget=BUDGET, slab_planes=S, timing=timing)
+    try:
+        o.load(u0)
+        for _ in range(warmup):
+            o.run(STEPS)
+        times, stats = [], []
+        for _ in range(steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            o.run(STEPS)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+            stats.append(o.stats())
+        err = None
+        if ref is not None:
+            o.load(u0)
+            o.run(STEPS)
+            err = rel_l2(o.store(), ref)
+        return times, stats, err
+    finally:
+        o.close()
+
+
+def kernel_roofline(stats, rate):
+    """Per-kernel averages over the timed runs; algorithmic bytes per launch:
+    decode reads 8R B and writes 256 B per 4x4x4 block, encode the reverse,
+    the stencil reads and writes 4 B per cell update."""
+    tot = {"decode": 0.0, "encode": 0.0, "stencil": 0.0}
+    cnt = {"decode": 0, "encode": 0, "stencil": 0}
+    byt = {"decode": 0.0, "encode": 0.0, "stencil": 0.0}
+    for s in stats:
+        for k in tot:
+            tot[k] += s["ms_" + k]
+            cnt[k] += s["n_" + k]
+        byt["decode"] += s["blocks_decode"] * (8 * rate + 256)
+        byt["encode"] += s["blocks_encode"] * (256 + 8 * rate)
+        byt["stencil"] += s["cells_stencil"] * 8
+    per = {}
+    for k in tot:
+        if cnt[k]:
+            avg_ms = tot[k] / cnt[k]
+            per_launch = byt[k] / cnt[k]
+            per[k] = {"avg_ms": avg_ms, "launches": cnt[k], "bytes_per_launch": per_launch,
+                      "gbs": per_launch / (avg_ms * 1e-3) / 1e9, "total_ms": tot[k]}
+    return per
+
+
+def cpu_baseline(u0, rate):
+    """The oracle's compressed path (FP64 stencil + scalar codec) on a bounded
+    sample: the full grid for one residency sweep of k steps."""
+    import oracle
+    cores = os.cpu_count() or 1
+    t0 = time.perf_counter()
+    oracle.compressed_sweeps(u0, C, K, K, rate)
+    dt = time.perf_counter() - t0
+    cells = float(np.prod(SHAPE)) * K
+    return {"value": cells / dt / 1e9, "unit": "GCell-updates/s", "cores": cores,
+            "kind": "oracle",
+            "sample": "full 512x512x2048 grid, one sweep of k=4 steps at R=%d "
+                      "(load-encode, decode, 4 FP64 steps, encode, decode), %.1f s" % (rate, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--rate", type=int, default=16)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-error", action="store_true")
+    ap.add_argument("--extra-rates", default="8,12")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU; the multi-GPU z-sharding is a design "
+              "note only (--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2204_11315_amd import inputs, oc
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    oc.lib()
+    t0 = time.perf_counter()
+    u0 = inputs.grf_field(SHAPE, seed=2)
+    log("input ready in %.1f s" % (time.perf_counter() - t0))
+
+    ref = None
+    if not args.no_error:
+        import oracle
+        t0 = time.perf_counter()
+        ref = oracle.star7_run(u0, C, STEPS).astype(np.float32)
+        log("FP64 oracle reference (64 steps, full grid) in %.1f s" % (time.perf_counter() - t0))
+
+    cells = float(np.prod(SHAPE)) * STEPS
+    legs = {}
+    for rate in [0, args.rate] + [int(r) for r in args.extra_rates.split(",") if r]:
+        if rate in legs:
+            continue
+        steps = args.steps if rate in (0, args.rate) else 1
+        warm = args.warmup if rate in (0, args.rate) else 1
+        times, stats, err = run_leg(oc, torch, u0, rate, steps, warm, ref)
+        med = float(np.median(times))
+        st = stats[-1]
+        legs[rate] = {"gcell_per_s": cells / med / 1e9, "ms_per_job": med * 1e3,
+                      "rel_l2_vs_fp64": err, "peak_dev_bytes": st["peak_dev_bytes"],
+                      "bytes_h2d": st["bytes_h2d"], "bytes_d2h": st["bytes_d2h"],
+                      "kernels": kernel_roofline(stats, rate), "times_s": times,
+                      "ms_h2d_sum": st["ms_h2d"], "ms_d2h_sum": st["ms_d2h"]}
+        log("rate %2d: %.2f GCell/s, %.1f ms/job, err %s, dev %d MiB" % (
+            rate, legs[rate]["gcell_per_s"], med * 1e3, err, st["peak_dev_bytes"] >> 20))
+
+    main_leg = legs[args.rate]
+    base_leg = legs[0]
+    kern = main_leg["kernels"]
+    dom = max(kern, key=lambda k: kern[k]["total_ms"])
+    roof = {"bound": "hbm", "kernel": dom, "achieved": kern[dom]["gbs"], "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": kern[dom]["gbs"] / HBM_PEAK_GBS, "traffic": None,
+            "avg_launch_ms": kern[dom]["avg_ms"],
+            "bytes_per_launch": kern[dom]["bytes_per_launch"]}
+    cpu = None
+    if not args.no_cpu_baseline:
+        t0 = time.perf_counter()
+        cpu = cpu_baseline(u0, args.rate)
+        log("cpu baseline in %.1f s" % (time.perf_counter() - t0))
+
+    out = {
+        "metric": "out-of-core GCell-updates/s compressed vs uncompressed at <=1e-3 rel-L2; device mem",
+        "value": main_leg["gcell_per_s"],
+        "unit": "GCell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": main_leg["ms_per_job"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded Gaussian random field, PSD ~ |k|^-3)",
+        "config": {"workload": "7-point Jacobi 512x512x2048 FP32 out-of-core, 64 steps, k=4, "
+                               "S=64, 512 MiB budget, fixed-rate R=%d single working buffer"
+                               % args.rate,
+                   "nx": 512, "ny": 512, "nz": 2048, "steps_per_job": STEPS, "k": K,
+                   "slab_planes": S, "budget_bytes": BUDGET, "rate_bits": args.rate},
+        "uncompressed_gcell_per_s": base_leg["gcell_per_s"],
+        "speedup_vs_uncompressed": main_leg["gcell_per_s"] / base_leg["gcell_per_s"],
+        "rel_l2_vs_fp64": main_leg["rel_l2_vs_fp64"],
+        "uncompressed_rel_l2_vs_fp64": base_leg["rel_l2_vs_fp64"],
+        "peak_dev_bytes": main_leg["peak_dev_bytes"],
+        "uncompressed_peak_dev_bytes": base_leg["peak_dev_bytes"],
+        "dev_mem_reduction": 1.0 - main_leg["peak_dev_bytes"] / base_leg["peak_dev_bytes"],
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "legs": {str(r): {k: v for k, v in leg.items() if k != "times_s"} for r, leg in legs.items()},
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

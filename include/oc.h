@@ -1,0 +1,190 @@
+/*
+ * oc.h -- C ABI of the compressed out-of-core stencil library (MI355X, gfx950).
+ *
+ * Method: Shen et al., "Compression-Based Optimizations for Out-of-Core GPU
+ * Stencil Computation".  A field larger than device memory is split along z
+ * into slabs that are streamed host -> device, advanced k time steps while
+ * resident (temporal blocking: each slab carries k*r halo planes per side,
+ * Sec. 3.1 and Sec. 3.2), and streamed back (Sec. 3.1).  With compression on,
+ * the host keeps every slab compressed; the GPU decompresses after the
+ * host-to-device copy and compresses before the device-to-host copy
+ * (Sec. 1, Sec. 4.2), at a fixed user-specified rate (Sec. 5).  Three streams
+ * share one full-size working buffer plus three compressed buffers (the single
+ * working buffer method, Sec. 5); the conflict-free issue order follows
+ * Algorithm 1 with the reading of its gaps documented in the design notes.
+ *
+ * Conventions shared by every call:
+ *  - Return value: OC_OK (0) or a negative OC_ERR_* code; no exception or
+ *    signal crosses this boundary.  oc_status_str() names a code.
+ *  - Arrays are FP32, C order [nz][ny][nx] (x fastest) unless stated.
+ *  - Ownership: the caller allocates and outlives every large buffer (device
+ *    arena, host levels, input/output arrays, streams).  The library owns only
+ *    its handle, small metadata and HIP events.  The library never calls
+ *    hipMalloc/hipHostMalloc.
+ *  - "device" pointers are HIP device memory of the current device; "host"
+ *    pointers are process memory (pinned memory makes copies asynchronous).
+ *  - A handle is not thread-safe.  After OC_ERR_HIP the handle may only be
+ *    destroyed; the host level that held the last complete sweep is intact.
+ *  - Ghost cells outside the grid are zero (zero Dirichlet boundary).
+ */
+#ifndef OC_H
+#define OC_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  OC_OK = 0,
+  OC_ERR_ARG = -1,       /* null pointer, non-positive size, out-of-range parameter     */
+  OC_ERR_SHAPE = -2,     /* dims (or slab planes) not multiples of 4 with compression on */
+  OC_ERR_BUDGET = -3,    /* the plan does not fit the device arena / host level sizes    */
+  OC_ERR_HIP = -4,       /* a HIP runtime call failed (or an injected failure)            */
+  OC_ERR_NONFINITE = -5, /* the codec met an Inf/NaN value                                */
+  OC_ERR_STATE = -6,     /* call out of order (e.g. run before load)                      */
+  OC_ERR_UNSUPPORTED = -7
+};
+
+typedef struct oc_handle oc_handle;
+typedef void *oc_stream; /* a hipStream_t (e.g. torch.cuda.Stream.cuda_stream) */
+
+typedef struct { int64_t nx, ny, nz; } oc_grid;
+
+typedef enum { OC_STAR7 = 1, OC_WAVE25 = 2 } oc_kind;
+
+typedef struct {
+  int32_t kind;          /* oc_kind                                                       */
+  float c[7];            /* STAR7: c0, c_-x, c_+x, c_-y, c_+y, c_-z, c_+z                 */
+  int32_t c0_is_field;   /* STAR7: 1 = c0 varies per cell, supplied as a field to oc_load  */
+  float h, dt;           /* WAVE25: grid spacing (m) and time step (s)                    */
+  int64_t src[3];        /* WAVE25: Ricker source cell (x, y, z); outside grid = none      */
+  float f_peak, t0;      /* WAVE25: Ricker peak frequency (Hz) and delay (s)               */
+} oc_stencil;
+
+typedef struct {
+  void *dev_arena;         /* device memory the library carves all buffers from             */
+  size_t dev_budget;       /* its size in bytes; the plan must fit                          */
+  oc_stream streams[3];    /* three caller-owned streams of default priority               */
+  void *host_level[2];     /* two host buffers of >= oc_host_level_bytes() bytes each;
+                              pinned (hipHostMalloc / torch pin_memory) for overlap         */
+  size_t host_level_bytes; /* size of each host level buffer                               */
+  void *host_aux;          /* host buffer of >= oc_host_aux_bytes() bytes for the read-only
+                              field (STAR7 c0 field, WAVE25 velocity); NULL when none       */
+  size_t host_aux_bytes;   /* its size                                                      */
+  int32_t k;               /* time steps per residency (temporal blocking), >= 1           */
+  int32_t slab_planes;     /* S interior planes per slab; 0 = largest that fits the budget */
+  int32_t rate_bits;       /* 0 = uncompressed; 1..32 = fixed-rate codec bits per value    */
+  int32_t single_buffer;   /* compressed mode: 1 = one shared working buffer (Sec. 5),
+                              0 = one working buffer per stream                            */
+  int32_t timing;          /* 1 = time every kernel and copy of oc_run with HIP events
+                              (results in oc_stats; costs two event records per op)         */
+} oc_config;
+
+typedef struct {
+  double wall_s;           /* wall time of the last oc_run                                 */
+  double gcell_per_s;      /* nx*ny*nz*steps / wall_s / 1e9 of the last oc_run             */
+  uint64_t bytes_h2d, bytes_d2h;  /* bytes copied by the last oc_run                       */
+  uint64_t peak_dev_bytes; /* arena high-water mark of the plan (= device memory used)     */
+  uint64_t slab_visits;    /* slabs processed by the last oc_run                           */
+  int64_t slab_planes, halo_planes, n_slabs;  /* the plan                                  */
+  uint64_t n_ops;          /* operations issued by the last oc_run                          */
+  /* with timing on: summed durations (ms) and counts of the last oc_run's ops,
+   * each measured between events recorded on the op's own stream            */
+  double ms_decode, ms_stencil, ms_encode, ms_h2d, ms_d2h;
+  uint64_t n_decode, n_stencil, n_encode, n_h2d, n_d2h;
+  uint64_t cells_stencil;  /* cell updates done by the stencil launches (halo included)   */
+  uint64_t blocks_decode, blocks_encode;  /* 4x4x4 blocks coded                           */
+} oc_stats;
+
+/* Bytes one host level needs for this grid / stencil / rate (raw FP32 planes,
+ * or z-major compressed block layers).  WAVE25 levels hold the two pressure
+ * fields.  Returns 0 on bad arguments. */
+size_t oc_host_level_bytes(const oc_grid *g, const oc_stencil *st, int32_t rate_bits);
+/* Bytes of the read-only host field (STAR7 c0 field, WAVE25 velocity), coded
+ * like a level; 0 when the stencil has none. */
+size_t oc_host_aux_bytes(const oc_grid *g, const oc_stencil *st, int32_t rate_bits);
+
+/* Bytes of device arena the plan needs (0 = automatic slab depth is chosen as
+ * in oc_create).  Returns 0 when no plan fits `budget` (budget 0 = unlimited). */
+size_t oc_plan_bytes(const oc_grid *g, const oc_stencil *st, int32_t k, int32_t slab_planes,
+                     int32_t rate_bits, int32_t single_buffer, size_t budget);
+
+/* Plans the sweep (slab depth, halos, buffer carve-out, operation list) on the
+ * CPU and creates HIP events.  Fails with OC_ERR_BUDGET when the buffers do not
+ * fit dev_budget, OC_ERR_SHAPE when compression is on and nx, ny, nz or S are
+ * not multiples of 4. */
+int oc_create(const oc_grid *g, const oc_stencil *st, const oc_config *cfg, oc_handle **out);
+
+/* Loads the initial state (host FP32 arrays, any host memory):
+ *   STAR7:  u = field, aux = c0 field when c0_is_field (else NULL);
+ *   WAVE25: u = p^0, aux = p^{-1}, vel = velocity (m/s).
+ * With compression on, the fields are encoded on the GPU (the host keeps only
+ * codes).  Synchronous. */
+int oc_load(oc_handle *h, const float *u, const float *aux, const float *vel);
+
+/* Advances the loaded state by `steps` time steps in sweeps of k steps (the
+ * last sweep runs steps mod k when k does not divide steps).  Every sweep
+ * streams all slabs through the GPU: H2D -> (decode) -> k stencil steps ->
+ * (encode) -> D2H, pipelined over the three streams.  Synchronous: returns
+ * after the three streams have drained. */
+int oc_run(oc_handle *h, int64_t steps);
+
+/* Copies the current state out (decoding on the GPU when compressed):
+ *   STAR7: u; WAVE25: u = p^n, aux = p^{n-1} (either may be NULL). */
+int oc_store(oc_handle *h, float *u, float *aux);
+
+int oc_stats_get(const oc_handle *h, oc_stats *s);
+/* Turns the per-op timing of oc_run on (1) or off (0) after creation. */
+int oc_set_timing(oc_handle *h, int32_t on);
+int oc_destroy(oc_handle *h);
+
+/* ---- fixed-rate codec on device buffers (Sec. 4.2, Sec. 5) -------------- */
+/* Bytes of a compressed field: (nx/4)(ny/4)(nz/4) blocks of 8*rate_bits bytes.
+ * Block (bx,by,bz) sits at byte ((bz*(ny/4) + by)*(nx/4) + bx) * 8*rate_bits,
+ * so every group of 4 planes (a block layer) is one contiguous byte range. */
+size_t oc_codec_bytes(int64_t nx, int64_t ny, int64_t nz, int32_t rate_bits);
+/* Enqueues compression of d_in [nz][ny][nx] into d_out on `stream`; returns
+ * after the enqueue.  Non-finite inputs set the stream's codec error word,
+ * read by oc_codec_status. */
+int oc_codec_compress(const float *d_in, int64_t nx, int64_t ny, int64_t nz, int32_t rate_bits,
+                      void *d_out, size_t out_bytes, oc_stream stream);
+int oc_codec_decompress(const void *d_in, int64_t nx, int64_t ny, int64_t nz, int32_t rate_bits,
+                        float *d_out, oc_stream stream);
+/* Synchronizes `stream` and returns OC_ERR_NONFINITE if any compression since
+ * the last call met a non-finite value (and clears the flag), else OC_OK. */
+int oc_codec_status(oc_stream stream);
+
+/* ---- single-field device kernels (in-core building blocks) -------------- */
+/* out = A^steps in on the device, ping-ponging through `tmp` (same size);
+ * result lands in `out`.  c0f (nullable) is a device c0 field. */
+int oc_star7_incore(const float *d_in, float *d_out, float *d_tmp, int64_t nx, int64_t ny,
+                    int64_t nz, const float *c, const float *d_c0f, int64_t steps,
+                    oc_stream stream);
+
+const char *oc_status_str(int status);
+
+/* ---- test and debug hooks ----------------------------------------------- */
+/* Makes the n-th HIP call issued by the executor from now on fail with
+ * OC_ERR_HIP (n >= 1); n < 0 disables. */
+int oc_debug_fail_after(oc_handle *h, int64_t n);
+/* Builds the operation list of `sweeps` sweeps (k steps each) for the plan
+ * these arguments describe, without a GPU, and runs the happens-before checker
+ * over it: returns the number of unordered conflicting accesses plus sweeps
+ * whose write-back does not cover the level (0 = race free and complete), or a
+ * negative OC_ERR_* for a plan that cannot be made.
+ * mutate: 0 none; 1 drop the i-th wait; 2 drop the epilogue (the last slab's
+ * write-back); 3 swap op i with the next op of the same stream. */
+int64_t oc_debug_check_plan(const oc_grid *g, const oc_stencil *st, int32_t k, int32_t slab_planes,
+                            int32_t rate_bits, int32_t single_buffer, size_t budget, int64_t sweeps,
+                            int32_t mutate, int64_t i);
+/* Operations in that list; *n_waits receives the number of stream waits. */
+int64_t oc_debug_plan_ops(const oc_grid *g, const oc_stencil *st, int32_t k, int32_t slab_planes,
+                          int32_t rate_bits, int32_t single_buffer, size_t budget, int64_t sweeps,
+                          int64_t *n_waits);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

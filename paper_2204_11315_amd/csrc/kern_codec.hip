@@ -1,0 +1,424 @@
+// kern_codec.hip -- fixed-rate block codec on gfx950 (encode and decode).
+//
+// The paper compresses each chunk on the GPU before it is copied back and
+// decompresses it after it is copied in (Sec. 1, Sec. 4.2), at a fixed,
+// user-specified rate (Sec. 5).  The format is this library's own fixed-rate
+// block-transform code (block floating point, exactly invertible integer
+// lifting transform, embedded bit-plane coding with group tests); every slot
+// holds one 4x4x4 block in exactly 64*R bits, so a block's position in the
+// stream is known without any index, and every group of four planes is one
+// contiguous byte range.
+//
+// Kernel layout: one lane codes one block from start to finish.  A wave takes
+// 64 consecutive blocks along x, so the 16 row loads/stores of a block are
+// 64 x 16 B contiguous per instruction.  All per-block state lives in
+// registers: 64 coefficients, turned by an in-register 32x32 bit-matrix
+// transpose (twice) into 32 bit-plane words of 64 bits.  The embedded coder
+// emits each plane in closed form: n verbatim bits, then one "group" token
+// per newly significant coefficient (found with a count-trailing-zeros on the
+// plane word shifted by n), then a closing 0 unless all 64 are significant.
+// The decoder mirrors it, reading 64-bit windows of its slot.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "oc_kernels.h"
+
+// Sticky per-device error word: bit 0 = a non-finite value was met by the
+// encoder.  Read and cleared by the host through its symbol address.
+__device__ int g_oc_codec_err;
+
+namespace {
+
+// ---- coefficient order: ascending (i+j+k, i^2+j^2+k^2, t) ------------------
+struct SeqOrder {
+  int at[64];
+};
+constexpr SeqOrder make_seq_order() {
+  SeqOrder o{};
+  int key1[64] = {}, key2[64] = {};
+  for (int t = 0; t < 64; t++) {
+    int i = t & 3, j = (t >> 2) & 3, k = t >> 4;
+    key1[t] = i + j + k;
+    key2[t] = i * i + j * j + k * k;
+    o.at[t] = t;
+  }
+  // selection sort, compile time
+  for (int a = 0; a < 64; a++) {
+    int best = a;
+    for (int b = a + 1; b < 64; b++) {
+      int x = o.at[b], y = o.at[best];
+      bool less = key1[x] != key1[y] ? key1[x] < key1[y]
+                  : key2[x] != key2[y] ? key2[x] < key2[y] : x < y;
+      if (less) best = b;
+    }
+    int tmp = o.at[a];
+    o.at[a] = o.at[best];
+    o.at[best] = tmp;
+  }
+  return o;
+}
+constexpr SeqOrder kSeq = make_seq_order();
+
+// ---- integer lifting (wrapping, floor shifts) -----------------------------
+__device__ __forceinline__ void lift_fwd(int32_t &a, int32_t &b, int32_t &c, int32_t &d) {
+  uint32_t d0 = (uint32_t)b - (uint32_t)a;
+  uint32_t s0 = (uint32_t)a + (uint32_t)((int32_t)d0 >> 1);
+  uint32_t d1 = (uint32_t)d - (uint32_t)c;
+  uint32_t s1 = (uint32_t)c + (uint32_t)((int32_t)d1 >> 1);
+  uint32_t D = s1 - s0;
+  uint32_t S = s0 + (uint32_t)((int32_t)D >> 1);
+  a = (int32_t)S;
+  b = (int32_t)D;
+  c = (int32_t)d0;
+  d = (int32_t)d1;
+}
+__device__ __forceinline__ void lift_inv(int32_t &a, int32_t &b, int32_t &c, int32_t &d) {
+  uint32_t S = (uint32_t)a, D = (uint32_t)b, d0 = (uint32_t)c, d1 = (uint32_t)d;
+  uint32_t s0 = S - (uint32_t)((int32_t)D >> 1);
+  uint32_t s1 = D + s0;
+  uint32_t x2 = s1 - (uint32_t)((int32_t)d1 >> 1);
+  uint32_t x3 = d1 + x2;
+  uint32_t x0 = s0 - (uint32_t)((int32_t)d0 >> 1);
+  uint32_t x1 = d0 + x0;
+  a = (int32_t)x0;
+  b = (int32_t)x1;
+  c = (int32_t)x2;
+  d = (int32_t)x3;
+}
+
+__device__ __forceinline__ void xform_fwd(int32_t *q) {
+#pragma unroll
+  for (int k = 0; k < 4; k++)
+#pragma unroll
+    for (int j = 0; j < 4; j++) lift_fwd(q[16 * k + 4 * j], q[16 * k + 4 * j + 1], q[16 * k + 4 * j + 2], q[16 * k + 4 * j + 3]);
+#pragma unroll
+  for (int k = 0; k < 4; k++)
+#pragma unroll
+    for (int i = 0; i < 4; i++) lift_fwd(q[16 * k + i], q[16 * k + 4 + i], q[16 * k + 8 + i], q[16 * k + 12 + i]);
+#pragma unroll
+  for (int j = 0; j < 4; j++)
+#pragma unroll
+    for (int i = 0; i < 4; i++) lift_fwd(q[4 * j + i], q[16 + 4 * j + i], q[32 + 4 * j + i], q[48 + 4 * j + i]);
+}
+__device__ __forceinline__ void xform_inv(int32_t *q) {
+#pragma unroll
+  for (int j = 0; j < 4; j++)
+#pragma unroll
+    for (int i = 0; i < 4; i++) lift_inv(q[4 * j + i], q[16 + 4 * j + i], q[32 + 4 * j + i], q[48 + 4 * j + i]);
+#pragma unroll
+  for (int k = 0; k < 4; k++)
+#pragma unroll
+    for (int i = 0; i < 4; i++) lift_inv(q[16 * k + i], q[16 * k + 4 + i], q[16 * k + 8 + i], q[16 * k + 12 + i]);
+#pragma unroll
+  for (int k = 0; k < 4; k++)
+#pragma unroll
+    for (int j = 0; j < 4; j++) lift_inv(q[16 * k + 4 * j], q[16 * k + 4 * j + 1], q[16 * k + 4 * j + 2], q[16 * k + 4 * j + 3]);
+}
+
+// ---- 32x32 bit-matrix transpose, in place: bit c of A[r] <-> bit r of A[c] --
+__device__ __forceinline__ void bit_transpose32(uint32_t *A) {
+#pragma unroll
+  for (int r = 0; r < 16; r++) {
+    // halves: bytes {A.b0, A.b1, B.b0, B.b1} and {A.b2, A.b3, B.b2, B.b3}
+    uint32_t a = A[r], b = A[r + 16];
+    A[r] = __builtin_amdgcn_perm(b, a, 0x05040100u);
+    A[r + 16] = __builtin_amdgcn_perm(b, a, 0x07060302u);
+  }
+#pragma unroll
+  for (int r = 0; r < 32; r++) {
+    if (r & 8) continue;
+    uint32_t a = A[r], b = A[r + 8];
+    A[r] = __builtin_amdgcn_perm(b, a, 0x06020400u);
+    A[r + 8] = __builtin_amdgcn_perm(b, a, 0x07030501u);
+  }
+#pragma unroll
+  for (int r = 0; r < 32; r++) {
+    if (r & 4) continue;
+    uint32_t t = ((A[r] >> 4) ^ A[r + 4]) & 0x0F0F0F0Fu;
+    A[r] ^= t << 4;
+    A[r + 4] ^= t;
+  }
+#pragma unroll
+  for (int r = 0; r < 32; r++) {
+    if (r & 2) continue;
+    uint32_t t = ((A[r] >> 2) ^ A[r + 2]) & 0x33333333u;
+    A[r] ^= t << 2;
+    A[r + 2] ^= t;
+  }
+#pragma unroll
+  for (int r = 0; r < 32; r++) {
+    if (r & 1) continue;
+    uint32_t t = ((A[r] >> 1) ^ A[r + 1]) & 0x55555555u;
+    A[r] ^= t << 1;
+    A[r + 1] ^= t;
+  }
+}
+
+__device__ __forceinline__ uint64_t lowmask64(int n) {
+  return n >= 64 ? ~0ull : ((1ull << n) - 1ull);
+}
+
+// ---- bit writer over one slot of NW dwords ----------------------------------
+struct BitWriter {
+  uint32_t *slot;
+  int NW;    // dwords in the slot
+  uint64_t acc;
+  int nacc;  // valid bits in acc (< 32 between calls)
+  int widx;  // dwords already stored
+  __device__ __forceinline__ int pos() const { return 32 * widx + nacc; }
+  __device__ __forceinline__ void put(uint32_t v, int len) {  // len <= 32, v < 2^len
+    acc |= (uint64_t)v << nacc;
+    nacc += len;
+    if (nacc >= 32) {
+      if (widx < NW) slot[widx] = (uint32_t)acc;
+      widx++;
+      acc >>= 32;
+      nacc -= 32;
+    }
+  }
+  __device__ __forceinline__ void put64(uint64_t v, int len) {  // len <= 64
+    if (len > 32) {
+      put((uint32_t)v, 32);
+      put((uint32_t)(v >> 32), len - 32);
+    } else {
+      put((uint32_t)v, len);
+    }
+  }
+  __device__ __forceinline__ void finish() {
+    if (widx < NW) {
+      slot[widx] = (uint32_t)acc;
+      widx++;
+    }
+    for (; widx < NW; widx++) slot[widx] = 0u;
+  }
+};
+
+// ---- bit reader over one slot of NW dwords ----------------------------------
+struct BitReader {
+  const uint32_t *slot;
+  int NW;
+  uint64_t win;  // dwords wi, wi+1
+  int wi, off;   // bit position = 32*wi + off, 0 <= off < 32
+  __device__ __forceinline__ uint32_t fetch(int i) const { return i < NW ? slot[i] : 0u; }
+  __device__ __forceinline__ void init(const uint32_t *s, int nw) {
+    slot = s;
+    NW = nw;
+    wi = 0;
+    off = 0;
+    win = (uint64_t)fetch(0) | ((uint64_t)fetch(1) << 32);
+  }
+  __device__ __forceinline__ int pos() const { return 32 * wi + off; }
+  __device__ __forceinline__ void advance(int len) {  // off + len < 64
+    off += len;
+    if (off >= 32) {
+      off -= 32;
+      wi++;
+      win = (win >> 32) | ((uint64_t)fetch(wi + 1) << 32);
+    }
+  }
+  __device__ __forceinline__ uint32_t get(int len) {  // 1 <= len <= 32
+    uint32_t v = (uint32_t)(win >> off) & (uint32_t)(len >= 32 ? 0xFFFFFFFFu : ((1u << len) - 1u));
+    advance(len);
+    return v;
+  }
+  __device__ __forceinline__ uint64_t get64(int len) {  // 0 <= len <= 64
+    if (len == 0) return 0;
+    if (len > 32) {
+      uint64_t lo = get(32);
+      return lo | ((uint64_t)get(len - 32) << 32);
+    }
+    return get(len);
+  }
+  // Consumes a run of zeros and the 1 ending it; returns the run length, or
+  // -1 if no 1 appears within `limit` bits (the stream was cut by the budget).
+  __device__ __forceinline__ int zero_run(int limit) {
+    int run = 0;
+    for (;;) {
+      uint32_t w = (uint32_t)(win >> off);
+      if (w) {
+        int c = __builtin_ctz(w);
+        if (run + c >= limit) return -1;
+        advance(c + 1);
+        return run + c;
+      }
+      run += 32;
+      advance(32);
+      if (run >= limit) return -1;
+    }
+  }
+};
+
+// ---- encoder ------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_encode(const float *__restrict__ in, int64_t nx, int64_t ny,
+                                                int64_t nbx, int64_t nby, int64_t nblocks, int R,
+                                                uint32_t *__restrict__ out) {
+  const int NW = 2 * R;        // dwords per slot
+  const int BITS = 64 * R;     // slot bits
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nblocks) return;
+  const int64_t bx = b % nbx;
+  const int64_t by = (b / nbx) % nby;
+  const int64_t bz = b / (nbx * nby);
+  const float *base = in + ((4 * bz) * ny + 4 * by) * nx + 4 * bx;
+
+  // load and take the block apart into sign / exponent / mantissa
+  uint32_t raw[64];
+#pragma unroll
+  for (int k = 0; k < 4; k++)
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+      float4 v = *reinterpret_cast<const float4 *>(base + (k * ny + j) * nx);
+      raw[16 * k + 4 * j + 0] = __float_as_uint(v.x);
+      raw[16 * k + 4 * j + 1] = __float_as_uint(v.y);
+      raw[16 * k + 4 * j + 2] = __float_as_uint(v.z);
+      raw[16 * k + 4 * j + 3] = __float_as_uint(v.w);
+    }
+  uint32_t Eb = 1;
+  bool bad = false;
+#pragma unroll
+  for (int t = 0; t < 64; t++) {
+    uint32_t E = (raw[t] >> 23) & 255u;
+    bad |= (E == 255u);
+    Eb = max(Eb, max(E, 1u));
+  }
+  if (bad) atomicOr(&g_oc_codec_err, 1);
+  int32_t q[64];
+#pragma unroll
+  for (int t = 0; t < 64; t++) {
+    uint32_t E = (raw[t] >> 23) & 255u;
+    uint32_t M = E ? ((raw[t] & 0x7FFFFFu) | 0x800000u) : (raw[t] & 0x7FFFFFu);
+    uint32_t sh = Eb - max(E, 1u);
+    uint32_t mag = sh >= 27u ? 0u : ((M << 3) >> sh);
+    q[t] = (raw[t] >> 31) ? -(int32_t)mag : (int32_t)mag;
+  }
+  xform_fwd(q);
+  // reorder + negabinary, split in halves for the plane transpose
+  uint32_t lo[32], hi[32];
+#pragma unroll
+  for (int p = 0; p < 32; p++) {
+    lo[p] = ((uint32_t)q[kSeq.at[p]] + 0xAAAAAAAAu) ^ 0xAAAAAAAAu;
+    hi[p] = ((uint32_t)q[kSeq.at[p + 32]] + 0xAAAAAAAAu) ^ 0xAAAAAAAAu;
+  }
+  bit_transpose32(lo);
+  bit_transpose32(hi);
+
+  BitWriter w;
+  w.NW = NW;
+  w.slot = out + b * NW;
+  w.acc = 0;
+  w.nacc = 0;
+  w.widx = 0;
+  w.put(Eb, 8);
+  int n = 0;
+#pragma unroll
+  for (int p = 31; p >= 0; p--) {
+    if (w.pos() < BITS) {
+      const uint64_t x = (uint64_t)lo[p] | ((uint64_t)hi[p] << 32);
+      w.put64(x & lowmask64(n), n);
+      if (n < 64) {
+        uint64_t rest = x >> n;
+        while (rest && w.pos() < BITS) {
+          int tz = __builtin_ctzll(rest);
+          w.put(1u, 1);                      // group test: something left
+          w.put64(1ull << tz, tz + 1);       // tz zeros, then the set bit
+          n += tz + 1;
+          rest = (tz + 1 < 64) ? (rest >> (tz + 1)) : 0ull;
+        }
+        if (n < 64) w.put(0u, 1);            // group test: nothing left
+      }
+    }
+  }
+  w.finish();
+}
+
+// ---- decoder ------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_decode(const uint32_t *__restrict__ in, int64_t nx, int64_t ny,
+                                                int64_t nbx, int64_t nby, int64_t nblocks, int R,
+                                                float *__restrict__ out) {
+  const int NW = 2 * R;
+  const int BITS = 64 * R;
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nblocks) return;
+  const int64_t bx = b % nbx;
+  const int64_t by = (b / nbx) % nby;
+  const int64_t bz = b / (nbx * nby);
+
+  BitReader r;
+  r.init(in + b * NW, NW);
+  const int Eb = (int)r.get(8);
+  uint32_t lo[32], hi[32];
+  int n = 0;
+  bool done = false;
+#pragma unroll
+  for (int p = 31; p >= 0; p--) {
+    uint64_t x = 0;
+    if (!done) {
+      x = r.get64(n);
+      while (n < 64) {
+        if (r.pos() >= BITS) { done = true; break; }
+        if (!r.get(1)) break;
+        int run = r.zero_run(64 - n);
+        if (run < 0) { done = true; break; }
+        x |= 1ull << (n + run);
+        n += run + 1;
+      }
+      if (r.pos() >= BITS) done = true;
+    }
+    lo[p] = (uint32_t)x;
+    hi[p] = (uint32_t)(x >> 32);
+  }
+  bit_transpose32(lo);
+  bit_transpose32(hi);
+  int32_t q[64];
+#pragma unroll
+  for (int p = 0; p < 32; p++) {
+    q[kSeq.at[p]] = (int32_t)((lo[p] ^ 0xAAAAAAAAu) - 0xAAAAAAAAu);
+    q[kSeq.at[p + 32]] = (int32_t)((hi[p] ^ 0xAAAAAAAAu) - 0xAAAAAAAAu);
+  }
+  xform_inv(q);
+  float *base = out + ((4 * bz) * ny + 4 * by) * nx + 4 * bx;
+  const int e = Eb - 153;
+#pragma unroll
+  for (int k = 0; k < 4; k++)
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+      float4 v;
+      v.x = ldexpf((float)q[16 * k + 4 * j + 0], e);
+      v.y = ldexpf((float)q[16 * k + 4 * j + 1], e);
+      v.z = ldexpf((float)q[16 * k + 4 * j + 2], e);
+      v.w = ldexpf((float)q[16 * k + 4 * j + 3], e);
+      *reinterpret_cast<float4 *>(base + (k * ny + j) * nx) = v;
+    }
+}
+
+}  // namespace
+
+namespace oc {
+
+hipError_t launch_encode(const float *d_in, int64_t nx, int64_t ny, int64_t nlayers, int rate,
+                         void *d_out, hipStream_t s) {
+  if (rate < 1 || rate > 32) return hipErrorInvalidValue;
+  const int64_t nbx = nx / 4, nby = ny / 4, nb = nbx * nby * nlayers;
+  if (nb <= 0) return hipSuccess;
+  dim3 grid((unsigned)((nb + 255) / 256));
+  hipLaunchKernelGGL(k_encode, grid, dim3(256), 0, s, d_in, nx, ny, nbx, nby, nb, rate,
+                     (uint32_t *)d_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_decode(const void *d_in, int64_t nx, int64_t ny, int64_t nlayers, int rate,
+                         float *d_out, hipStream_t s) {
+  if (rate < 1 || rate > 32) return hipErrorInvalidValue;
+  const int64_t nbx = nx / 4, nby = ny / 4, nb = nbx * nby * nlayers;
+  if (nb <= 0) return hipSuccess;
+  dim3 grid((unsigned)((nb + 255) / 256));
+  hipLaunchKernelGGL(k_decode, grid, dim3(256), 0, s, (const uint32_t *)d_in, nx, ny, nbx, nby, nb,
+                     rate, d_out);
+  return hipGetLastError();
+}
+
+hipError_t codec_error_word(int **dev_ptr) {
+  return hipGetSymbolAddress((void **)dev_ptr, HIP_SYMBOL(g_oc_codec_err));
+}
+
+}  // namespace oc

@@ -1,0 +1,589 @@
+// oc_api.cpp -- the C ABI (include/oc.h) and the executor that maps the
+// planner's operation list one-to-one onto HIP calls.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/oc.h"
+#include "oc_kernels.h"
+#include "oc_plan.h"
+
+struct oc_handle {
+  oc::Plan plan;
+  oc_grid g;
+  oc_stencil st;
+  oc_config cfg;
+  hipStream_t s[3];
+  std::vector<hipEvent_t> ev;
+  uint8_t *arena = nullptr;
+  uint8_t *host[3] = {nullptr, nullptr, nullptr};  // level 0, level 1, aux
+  int cur = 0;            // host level holding the current state
+  bool loaded = false;
+  bool broken = false;
+  int64_t time_index = 0; // time steps applied since load
+  oc_stats stats{};
+  int64_t fail_after = -1;
+  int64_t hip_calls = 0;
+  hipError_t last_hip = hipSuccess;
+  // per-op timing (oc_config.timing)
+  bool timing = false;
+  std::vector<hipEvent_t> tev;
+  // cached operation list
+  std::vector<oc::Op> ops;
+  int64_t ops_key[4] = {-1, -1, -1, -1};
+};
+
+namespace {
+
+thread_local hipError_t g_last_hip = hipSuccess;
+
+// Every HIP call of the executor goes through here so that a test can inject a
+// failure at the n-th call.
+struct Exec {
+  oc_handle *h;
+  int st = OC_OK;
+  bool ok(hipError_t e) {
+    if (st != OC_OK) return false;
+    if (h && h->fail_after > 0) {
+      h->hip_calls++;
+      if (h->hip_calls >= h->fail_after) {
+        h->fail_after = -1;
+        e = hipErrorUnknown;
+      }
+    }
+    if (e != hipSuccess) {
+      g_last_hip = e;
+      if (h) h->last_hip = e;
+      st = OC_ERR_HIP;
+      return false;
+    }
+    return true;
+  }
+};
+
+oc::Star7Coef coef_of(const oc_stencil &s) {
+  return oc::Star7Coef{s.c[0], s.c[1], s.c[2], s.c[3], s.c[4], s.c[5], s.c[6]};
+}
+
+oc::PlanInput plan_input(const oc_grid *g, const oc_stencil *st, int k, int slab_planes, int rate,
+                         int single_buffer, size_t budget) {
+  oc::PlanInput in;
+  in.nx = g->nx;
+  in.ny = g->ny;
+  in.nz = g->nz;
+  in.kind = st->kind;
+  in.k = k;
+  in.slab_planes = slab_planes;
+  in.rate = rate;
+  in.single_buffer = single_buffer != 0;
+  in.c0_field = st->kind == OC_STAR7 && st->c0_is_field;
+  in.budget = budget;
+  return in;
+}
+
+void drain(oc_handle *h) {
+  for (int i = 0; i < 3; i++) (void)hipStreamSynchronize(h->s[i]);
+}
+
+enum TimedKind { T_DEC, T_STENCIL, T_ENC, T_H2D, T_D2H, T_NONE };
+
+TimedKind timed_kind(const oc::Op &o) {
+  switch (o.type) {
+    case oc::OP_DEC: return o.z_hi < 0 ? T_NONE : T_DEC;
+    case oc::OP_STAR7:
+    case oc::OP_WAVE: return T_STENCIL;
+    case oc::OP_ENC: return T_ENC;
+    case oc::OP_H2D: return T_H2D;
+    case oc::OP_D2H: return T_D2H;
+    default: return T_NONE;
+  }
+}
+
+int issue(oc_handle *h, const std::vector<oc::Op> &ops) {
+  Exec x{h};
+  const oc::Plan &p = h->plan;
+  const oc::Star7Coef c = coef_of(h->st);
+  uint64_t h2d = 0, d2h = 0, cells = 0, bdec = 0, benc = 0;
+  const uint64_t blocks_per_layer = (uint64_t)(p.in.nx / 4) * (uint64_t)(p.in.ny / 4);
+  // timing: a pair of events around every timed op, recorded on its stream
+  std::vector<std::pair<int, size_t>> timed;  // (kind, first event index)
+  if (h->timing) {
+    size_t need = 0;
+    for (const oc::Op &o : ops) need += timed_kind(o) != T_NONE ? 2 : 0;
+    while (h->tev.size() < need && x.st == OC_OK) {
+      hipEvent_t e = nullptr;
+      if (x.ok(hipEventCreate(&e))) h->tev.push_back(e);
+    }
+  }
+  size_t tnext = 0;
+  for (const oc::Op &o : ops) {
+    hipStream_t s = o.stream >= 0 ? h->s[o.stream] : nullptr;
+    const TimedKind tk = h->timing ? timed_kind(o) : T_NONE;
+    if (tk != T_NONE) {
+      timed.push_back({(int)tk, tnext});
+      x.ok(hipEventRecord(h->tev[tnext], s));
+    }
+    switch (o.type) {
+      case oc::OP_H2D:
+        x.ok(hipMemcpyAsync(h->arena + o.dev_dst, h->host[o.host_id] + o.host_off, (size_t)o.bytes,
+                            hipMemcpyHostToDevice, s));
+        h2d += (uint64_t)o.bytes;
+        break;
+      case oc::OP_D2H:
+        x.ok(hipMemcpyAsync(h->host[o.host_id] + o.host_off, h->arena + o.dev_src, (size_t)o.bytes,
+                            hipMemcpyDeviceToHost, s));
+        d2h += (uint64_t)o.bytes;
+        break;
+      case oc::OP_DEC:
+        if (o.z_hi < 0) {
+          x.ok(hipMemcpyAsync(h->arena + o.dev_dst, h->arena + o.dev_src, (size_t)o.bytes,
+                              hipMemcpyDeviceToDevice, s));
+        } else {
+          x.ok(oc::launch_decode(h->arena + o.dev_src, p.in.nx, p.in.ny, o.z_hi, p.in.rate,
+                                 (float *)(h->arena + o.dev_dst), s));
+          bdec += blocks_per_layer * (uint64_t)o.z_hi;
+        }
+        break;
+      case oc::OP_ENC:
+        x.ok(oc::launch_encode((const float *)(h->arena + o.dev_src), p.in.nx, p.in.ny, o.z_hi,
+                               p.in.rate, h->arena + o.dev_dst, s));
+        benc += blocks_per_layer * (uint64_t)o.z_hi;
+        break;
+      case oc::OP_STAR7:
+        x.ok(oc::launch_star7((const float *)(h->arena + o.dev_src), (float *)(h->arena + o.dev_dst),
+                              o.dev_src2 >= 0 ? (const float *)(h->arena + o.dev_src2) : nullptr,
+                              p.in.nx, p.in.ny, o.z_lo, o.z_hi, o.gz0, p.in.nz, c, s));
+        cells += (uint64_t)(o.z_hi - o.z_lo) * (uint64_t)p.in.nx * (uint64_t)p.in.ny;
+        break;
+      case oc::OP_WAVE:
+        x.st = OC_ERR_UNSUPPORTED;
+        break;
+      case oc::OP_REC:
+        x.ok(hipEventRecord(h->ev[o.ev], s));
+        break;
+      case oc::OP_WAIT:
+        x.ok(hipStreamWaitEvent(s, h->ev[o.ev], 0));
+        break;
+      case oc::OP_SYNC:
+        for (int i = 0; i < 3; i++) x.ok(hipStreamSynchronize(h->s[i]));
+        break;
+    }
+    if (tk != T_NONE) {
+      x.ok(hipEventRecord(h->tev[tnext + 1], s));
+      tnext += 2;
+    }
+    if (x.st != OC_OK) break;
+  }
+  h->stats.bytes_h2d = h2d;
+  h->stats.bytes_d2h = d2h;
+  h->stats.cells_stencil = cells;
+  h->stats.blocks_decode = bdec;
+  h->stats.blocks_encode = benc;
+  double ms[5] = {0, 0, 0, 0, 0};
+  uint64_t n[5] = {0, 0, 0, 0, 0};
+  if (x.st == OC_OK && h->timing) {
+    for (const auto &t : timed) {
+      float e = 0.f;
+      if (!x.ok(hipEventElapsedTime(&e, h->tev[t.second], h->tev[t.second + 1]))) break;
+      ms[t.first] += e;
+      n[t.first]++;
+    }
+  }
+  h->stats.ms_decode = ms[T_DEC];
+  h->stats.ms_stencil = ms[T_STENCIL];
+  h->stats.ms_encode = ms[T_ENC];
+  h->stats.ms_h2d = ms[T_H2D];
+  h->stats.ms_d2h = ms[T_D2H];
+  h->stats.n_decode = n[T_DEC];
+  h->stats.n_stencil = n[T_STENCIL];
+  h->stats.n_encode = n[T_ENC];
+  h->stats.n_h2d = n[T_H2D];
+  h->stats.n_d2h = n[T_D2H];
+  if (x.st != OC_OK) {
+    drain(h);
+    h->broken = true;
+  }
+  return x.st;
+}
+
+int codec_check_and_clear() {
+  int *w = nullptr;
+  if (oc::codec_error_word(&w) != hipSuccess || !w) return OC_ERR_HIP;
+  int v = 0;
+  if (hipMemcpy(&v, w, sizeof v, hipMemcpyDeviceToHost) != hipSuccess) return OC_ERR_HIP;
+  if (v) {
+    int z = 0;
+    if (hipMemcpy(w, &z, sizeof z, hipMemcpyHostToDevice) != hipSuccess) return OC_ERR_HIP;
+    return OC_ERR_NONFINITE;
+  }
+  return OC_OK;
+}
+
+bool grid_ok(const oc_grid *g) {
+  return g && g->nx > 0 && g->ny > 0 && g->nz > 0 && g->nx <= (1 << 30) && g->ny <= (1 << 30) &&
+         g->nz <= (1 << 30);
+}
+
+// Encodes (or copies) `planes` planes of host field `src` into host store
+// `dst` at plane z0 via the device working buffers; synchronous on stream 0.
+int load_field(oc_handle *h, const float *src, uint8_t *dst, bool coded) {
+  const oc::Plan &p = h->plan;
+  Exec x{h};
+  hipStream_t s = h->s[0];
+  const size_t pb = p.plane_bytes;
+  if (!coded) {
+    // raw: a plain host copy of the whole field
+    std::memcpy(dst, src, pb * (size_t)p.in.nz);
+    return OC_OK;
+  }
+  const int64_t chunk = std::max<int64_t>(4, p.P / 4 * 4);
+  uint8_t *work = h->arena + p.off_work[0][0];
+  uint8_t *stage = h->arena + p.off_stage[0];
+  for (int64_t z = 0; z < p.in.nz; z += chunk) {
+    int64_t n = std::min<int64_t>(chunk, p.in.nz - z);
+    x.ok(hipMemcpyAsync(work, (const uint8_t *)src + (size_t)z * pb, (size_t)n * pb,
+                        hipMemcpyHostToDevice, s));
+    x.ok(oc::launch_encode((const float *)work, p.in.nx, p.in.ny, n / 4, p.in.rate, stage, s));
+    x.ok(hipMemcpyAsync(dst + (size_t)(z / 4) * p.layer_bytes, stage, (size_t)(n / 4) * p.layer_bytes,
+                        hipMemcpyDeviceToHost, s));
+    x.ok(hipStreamSynchronize(s));
+    if (x.st) break;
+  }
+  if (x.st) return x.st;
+  return codec_check_and_clear();
+}
+
+int store_field(oc_handle *h, const uint8_t *src, float *dst, bool coded) {
+  const oc::Plan &p = h->plan;
+  Exec x{h};
+  hipStream_t s = h->s[0];
+  const size_t pb = p.plane_bytes;
+  if (!coded) {
+    std::memcpy(dst, src, pb * (size_t)p.in.nz);
+    return OC_OK;
+  }
+  const int64_t chunk = std::max<int64_t>(4, p.P / 4 * 4);
+  uint8_t *work = h->arena + p.off_work[0][0];
+  uint8_t *stage = h->arena + p.off_stage[0];
+  for (int64_t z = 0; z < p.in.nz; z += chunk) {
+    int64_t n = std::min<int64_t>(chunk, p.in.nz - z);
+    x.ok(hipMemcpyAsync(stage, src + (size_t)(z / 4) * p.layer_bytes, (size_t)(n / 4) * p.layer_bytes,
+                        hipMemcpyHostToDevice, s));
+    x.ok(oc::launch_decode(stage, p.in.nx, p.in.ny, n / 4, p.in.rate, (float *)work, s));
+    x.ok(hipMemcpyAsync((uint8_t *)dst + (size_t)z * pb, work, (size_t)n * pb, hipMemcpyDeviceToHost, s));
+    x.ok(hipStreamSynchronize(s));
+    if (x.st) break;
+  }
+  return x.st;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *oc_status_str(int st) {
+  switch (st) {
+    case OC_OK: return "ok";
+    case OC_ERR_ARG: return "invalid argument";
+    case OC_ERR_SHAPE: return "shape not block aligned (multiples of 4 needed with compression)";
+    case OC_ERR_BUDGET: return "plan does not fit the device budget or host buffers";
+    case OC_ERR_HIP: return hipGetErrorString(g_last_hip);
+    case OC_ERR_NONFINITE: return "non-finite value met by the codec";
+    case OC_ERR_STATE: return "call out of order";
+    case OC_ERR_UNSUPPORTED: return "unsupported combination";
+    default: return "unknown status";
+  }
+}
+
+size_t oc_codec_bytes(int64_t nx, int64_t ny, int64_t nz, int32_t rate_bits) {
+  if (nx <= 0 || ny <= 0 || nz <= 0 || rate_bits < 1 || rate_bits > 32) return 0;
+  if (nx % 4 || ny % 4 || nz % 4) return 0;
+  return (size_t)(nx / 4) * (size_t)(ny / 4) * (size_t)(nz / 4) * 8u * (size_t)rate_bits;
+}
+
+int oc_codec_compress(const float *d_in, int64_t nx, int64_t ny, int64_t nz, int32_t rate_bits,
+                      void *d_out, size_t out_bytes, oc_stream stream) {
+  if (!d_in || !d_out || nx <= 0 || ny <= 0 || nz <= 0 || rate_bits < 1 || rate_bits > 32)
+    return OC_ERR_ARG;
+  if (nx % 4 || ny % 4 || nz % 4) return OC_ERR_SHAPE;
+  if (out_bytes < oc_codec_bytes(nx, ny, nz, rate_bits)) return OC_ERR_ARG;
+  hipError_t e = oc::launch_encode(d_in, nx, ny, nz / 4, rate_bits, d_out, (hipStream_t)stream);
+  if (e != hipSuccess) {
+    g_last_hip = e;
+    return OC_ERR_HIP;
+  }
+  return OC_OK;
+}
+
+int oc_codec_decompress(const void *d_in, int64_t nx, int64_t ny, int64_t nz, int32_t rate_bits,
+                        float *d_out, oc_stream stream) {
+  if (!d_in || !d_out || nx <= 0 || ny <= 0 || nz <= 0 || rate_bits < 1 || rate_bits > 32)
+    return OC_ERR_ARG;
+  if (nx % 4 || ny % 4 || nz % 4) return OC_ERR_SHAPE;
+  hipError_t e = oc::launch_decode(d_in, nx, ny, nz / 4, rate_bits, d_out, (hipStream_t)stream);
+  if (e != hipSuccess) {
+    g_last_hip = e;
+    return OC_ERR_HIP;
+  }
+  return OC_OK;
+}
+
+int oc_codec_status(oc_stream stream) {
+  hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+  if (e != hipSuccess) {
+    g_last_hip = e;
+    return OC_ERR_HIP;
+  }
+  return codec_check_and_clear();
+}
+
+int oc_star7_incore(const float *d_in, float *d_out, float *d_tmp, int64_t nx, int64_t ny,
+                    int64_t nz, const float *c, const float *d_c0f, int64_t steps,
+                    oc_stream stream) {
+  if (!d_in || !d_out || !c || nx <= 0 || ny <= 0 || nz <= 0 || steps < 0) return OC_ERR_ARG;
+  if (steps > 1 && !d_tmp) return OC_ERR_ARG;
+  if (nx > (1 << 30) || ny > (1 << 30) || nz > (1 << 30)) return OC_ERR_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  oc::Star7Coef cf{c[0], c[1], c[2], c[3], c[4], c[5], c[6]};
+  hipError_t e = hipSuccess;
+  if (steps == 0) {
+    e = hipMemcpyAsync(d_out, d_in, (size_t)(nx * ny * nz) * 4u, hipMemcpyDeviceToDevice, s);
+  } else {
+    float *X = (steps % 2 == 1) ? d_out : d_tmp;
+    float *Y = (steps % 2 == 1) ? d_tmp : d_out;
+    const float *src = d_in;
+    for (int64_t i = 1; i <= steps && e == hipSuccess; i++) {
+      float *dst = (i % 2 == 1) ? X : Y;
+      e = oc::launch_star7(src, dst, d_c0f, nx, ny, 0, nz, 0, nz, cf, s);
+      src = dst;
+    }
+  }
+  if (e != hipSuccess) {
+    g_last_hip = e;
+    return OC_ERR_HIP;
+  }
+  return OC_OK;
+}
+
+size_t oc_host_level_bytes(const oc_grid *g, const oc_stencil *st, int32_t rate_bits) {
+  if (!grid_ok(g) || !st) return 0;
+  oc::Plan p;
+  if (oc::make_plan(plan_input(g, st, 1, 4, rate_bits, 1, 0), &p) != oc::ST_OK) return 0;
+  return p.host_level_bytes;
+}
+
+size_t oc_host_aux_bytes(const oc_grid *g, const oc_stencil *st, int32_t rate_bits) {
+  if (!grid_ok(g) || !st) return 0;
+  oc::Plan p;
+  if (oc::make_plan(plan_input(g, st, 1, 4, rate_bits, 1, 0), &p) != oc::ST_OK) return 0;
+  return p.host_aux_bytes;
+}
+
+size_t oc_plan_bytes(const oc_grid *g, const oc_stencil *st, int32_t k, int32_t slab_planes,
+                     int32_t rate_bits, int32_t single_buffer, size_t budget) {
+  if (!grid_ok(g) || !st) return 0;
+  oc::Plan p;
+  if (oc::make_plan(plan_input(g, st, k, slab_planes, rate_bits, single_buffer, budget), &p) !=
+      oc::ST_OK)
+    return 0;
+  return p.arena_bytes;
+}
+
+int oc_create(const oc_grid *g, const oc_stencil *st, const oc_config *cfg, oc_handle **out) {
+  if (!grid_ok(g) || !st || !cfg || !out) return OC_ERR_ARG;
+  *out = nullptr;
+  if (st->kind != OC_STAR7 && st->kind != OC_WAVE25) return OC_ERR_ARG;
+  if (st->kind == OC_WAVE25) return OC_ERR_UNSUPPORTED;
+  oc::Plan p;
+  int r = oc::make_plan(plan_input(g, st, cfg->k, cfg->slab_planes, cfg->rate_bits,
+                                   cfg->single_buffer, cfg->dev_budget),
+                        &p);
+  if (r != oc::ST_OK) return r;
+  if (!cfg->dev_arena || p.arena_bytes > cfg->dev_budget) return OC_ERR_BUDGET;
+  if (!cfg->host_level[0] || !cfg->host_level[1] || cfg->host_level_bytes < p.host_level_bytes)
+    return OC_ERR_BUDGET;
+  if (p.host_aux_bytes && (!cfg->host_aux || cfg->host_aux_bytes < p.host_aux_bytes))
+    return OC_ERR_BUDGET;
+  for (int i = 0; i < 3; i++)
+    if (!cfg->streams[i]) return OC_ERR_ARG;
+  oc_handle *h = new (std::nothrow) oc_handle();
+  if (!h) return OC_ERR_ARG;
+  h->plan = p;
+  h->g = *g;
+  h->st = *st;
+  h->cfg = *cfg;
+  for (int i = 0; i < 3; i++) h->s[i] = (hipStream_t)cfg->streams[i];
+  h->timing = cfg->timing != 0;
+  h->arena = (uint8_t *)cfg->dev_arena;
+  h->host[0] = (uint8_t *)cfg->host_level[0];
+  h->host[1] = (uint8_t *)cfg->host_level[1];
+  h->host[2] = (uint8_t *)cfg->host_aux;
+  oc::EventIds ids{(int)p.slabs.size()};
+  h->ev.assign((size_t)ids.count(), nullptr);
+  for (auto &e : h->ev) {
+    hipError_t err = hipEventCreateWithFlags(&e, hipEventDisableTiming);
+    if (err != hipSuccess) {
+      g_last_hip = err;
+      for (auto &f : h->ev)
+        if (f) (void)hipEventDestroy(f);
+      delete h;
+      return OC_ERR_HIP;
+    }
+  }
+  h->stats.peak_dev_bytes = p.arena_bytes;
+  h->stats.slab_planes = p.S;
+  h->stats.halo_planes = p.halo;
+  h->stats.n_slabs = (int64_t)p.slabs.size();
+  *out = h;
+  return OC_OK;
+}
+
+int oc_load(oc_handle *h, const float *u, const float *aux, const float *vel) {
+  (void)vel;
+  if (!h || !u) return OC_ERR_ARG;
+  if (h->broken) return OC_ERR_STATE;
+  const oc::Plan &p = h->plan;
+  if (p.in.c0_field && !aux) return OC_ERR_ARG;
+  h->cur = 0;
+  int r = load_field(h, u, h->host[0], p.coded);
+  if (r) {
+    h->broken = r == OC_ERR_HIP;
+    return r;
+  }
+  if (p.in.c0_field) std::memcpy(h->host[2], aux, (size_t)p.host_aux_bytes);
+  h->loaded = true;
+  h->time_index = 0;
+  return OC_OK;
+}
+
+int oc_run(oc_handle *h, int64_t steps) {
+  if (!h || steps < 0) return OC_ERR_ARG;
+  if (h->broken || !h->loaded) return OC_ERR_STATE;
+  if (steps == 0) return OC_OK;
+  const oc::Plan &p = h->plan;
+  const int64_t k = p.in.k;
+  const int64_t sweeps = (steps + k - 1) / k;
+  const int steps_last = (int)(steps - (sweeps - 1) * k);
+  int64_t key[4] = {sweeps, steps_last, h->cur, h->time_index};
+  if (std::memcmp(key, h->ops_key, sizeof key) != 0) {
+    oc::build_ops(p, sweeps, steps_last, h->cur, h->time_index, &h->ops);
+    std::memcpy(h->ops_key, key, sizeof key);
+  }
+  auto t0 = std::chrono::steady_clock::now();
+  int r = issue(h, h->ops);
+  auto t1 = std::chrono::steady_clock::now();
+  if (r) return r;
+  int cr = p.coded ? codec_check_and_clear() : OC_OK;
+  h->cur = (int)((h->cur + sweeps) & 1);
+  h->time_index += steps;
+  double wall = std::chrono::duration<double>(t1 - t0).count();
+  h->stats.wall_s = wall;
+  h->stats.gcell_per_s =
+      (double)p.in.nx * (double)p.in.ny * (double)p.in.nz * (double)steps / wall / 1e9;
+  h->stats.slab_visits = (uint64_t)(sweeps * (int64_t)p.slabs.size());
+  h->stats.n_ops = h->ops.size();
+  return cr;
+}
+
+int oc_store(oc_handle *h, float *u, float *aux) {
+  (void)aux;
+  if (!h || !u) return OC_ERR_ARG;
+  if (h->broken || !h->loaded) return OC_ERR_STATE;
+  return store_field(h, h->host[h->cur], u, h->plan.coded);
+}
+
+int oc_stats_get(const oc_handle *h, oc_stats *s) {
+  if (!h || !s) return OC_ERR_ARG;
+  *s = h->stats;
+  return OC_OK;
+}
+
+int oc_set_timing(oc_handle *h, int32_t on) {
+  if (!h) return OC_ERR_ARG;
+  h->timing = on != 0;
+  return OC_OK;
+}
+
+int oc_destroy(oc_handle *h) {
+  if (!h) return OC_ERR_ARG;
+  drain(h);
+  for (auto &e : h->ev)
+    if (e) (void)hipEventDestroy(e);
+  for (auto &e : h->tev)
+    if (e) (void)hipEventDestroy(e);
+  delete h;
+  return OC_OK;
+}
+
+int oc_debug_fail_after(oc_handle *h, int64_t n) {
+  if (!h) return OC_ERR_ARG;
+  h->fail_after = n >= 1 ? n : -1;
+  h->hip_calls = 0;
+  return OC_OK;
+}
+
+int64_t oc_debug_plan_ops(const oc_grid *g, const oc_stencil *st, int32_t k, int32_t slab_planes,
+                          int32_t rate_bits, int32_t single_buffer, size_t budget, int64_t sweeps,
+                          int64_t *n_waits) {
+  if (!grid_ok(g) || !st || sweeps < 1) return OC_ERR_ARG;
+  oc::Plan p;
+  int r = oc::make_plan(plan_input(g, st, k, slab_planes, rate_bits, single_buffer, budget), &p);
+  if (r != oc::ST_OK) return r;
+  std::vector<oc::Op> ops;
+  oc::build_ops(p, sweeps, p.in.k, 0, 0, &ops);
+  if (n_waits) {
+    int64_t w = 0;
+    for (const auto &o : ops) w += o.type == oc::OP_WAIT;
+    *n_waits = w;
+  }
+  return (int64_t)ops.size();
+}
+
+int64_t oc_debug_check_plan(const oc_grid *g, const oc_stencil *st, int32_t k, int32_t slab_planes,
+                            int32_t rate_bits, int32_t single_buffer, size_t budget, int64_t sweeps,
+                            int32_t mutate, int64_t i) {
+  if (!grid_ok(g) || !st || sweeps < 1) return OC_ERR_ARG;
+  oc::Plan p;
+  int r = oc::make_plan(plan_input(g, st, k, slab_planes, rate_bits, single_buffer, budget), &p);
+  if (r != oc::ST_OK) return r;
+  std::vector<oc::Op> ops;
+  oc::build_ops(p, sweeps, p.in.k, 0, 0, &ops);
+  if (mutate == 1) {  // drop the i-th wait
+    int64_t seen = 0;
+    bool dropped = false;
+    for (size_t j = 0; j < ops.size(); j++)
+      if (ops[j].type == oc::OP_WAIT && seen++ == i) {
+        ops.erase(ops.begin() + (ptrdiff_t)j);
+        dropped = true;
+        break;
+      }
+    if (!dropped) return OC_ERR_ARG;
+  } else if (mutate == 2) {  // drop the epilogue: everything after the last kernel
+    size_t last = 0;
+    for (size_t j = 0; j < ops.size(); j++)
+      if (ops[j].type == oc::OP_STAR7 || ops[j].type == oc::OP_WAVE) last = j;
+    ops.erase(ops.begin() + (ptrdiff_t)last + 1, ops.end() - 1);
+  } else if (mutate == 3) {  // swap op i with the next op of the same stream
+    if (i < 0 || (size_t)i >= ops.size() || ops[(size_t)i].stream < 0) return OC_ERR_ARG;
+    for (size_t j = (size_t)i + 1; j < ops.size(); j++)
+      if (ops[j].stream == ops[(size_t)i].stream) {
+        std::swap(ops[(size_t)i], ops[j]);
+        break;
+      }
+  } else if (mutate != 0) {
+    return OC_ERR_ARG;
+  }
+  std::string why;
+  int64_t bad = oc::check_ops(p, ops, &why);
+  if (bad && getenv("OC_CHECK_VERBOSE")) fprintf(stderr, "oc plan check: %s\n", why.c_str());
+  return bad;
+}
+
+}  // extern "C"

@@ -1,0 +1,29 @@
+// oc_kernels.h -- launchers of the gfx950 kernels (internal to the library).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace oc {
+
+// Fixed-rate codec over `nlayers` block layers (4 planes each) of an
+// [4*nlayers][ny][nx] FP32 array; coded layers are contiguous.
+hipError_t launch_encode(const float *d_in, int64_t nx, int64_t ny, int64_t nlayers, int rate,
+                         void *d_out, hipStream_t s);
+hipError_t launch_decode(const void *d_in, int64_t nx, int64_t ny, int64_t nlayers, int rate,
+                         float *d_out, hipStream_t s);
+// Device address of the codec's sticky error word.
+hipError_t codec_error_word(int **dev_ptr);
+
+struct Star7Coef {
+  float c0, cmx, cpx, cmy, cpy, cmz, cpz;
+};
+
+// One 7-point step on a slab buffer of `planes` planes whose local plane 0 is
+// global plane gz0: writes local planes [z_lo, z_hi) of out from in.  Cells
+// outside the global grid [0,nx) x [0,ny) x [0,nz) read as zero.  c0f
+// (nullable) is the per-cell c0 slab with the same local indexing.
+hipError_t launch_star7(const float *in, float *out, const float *c0f, int64_t nx, int64_t ny,
+                        int64_t z_lo, int64_t z_hi, int64_t gz0, int64_t nz, const Star7Coef &c,
+                        hipStream_t s);
+
+}  // namespace oc

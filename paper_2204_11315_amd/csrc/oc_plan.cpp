@@ -1,0 +1,551 @@
+// oc_plan.cpp -- slab planner, arena carve-out, operation list, and the
+// happens-before checker over that list.  Host-only C++.
+//
+// Out-of-core decomposition (Sec. 3.1): the z extent is cut into slabs of S
+// interior planes; each residency loads S + 2*halo planes so that k time steps
+// can run on the GPU before the slab goes back (temporal blocking, Sec. 3.1 and
+// Sec. 3.2: more steps per residency means more halo).  With a coded host
+// store the halo is rounded up to whole 4-plane block layers.
+//
+// Issue order (Sec. 5, Algorithm 1): slabs are taken in order over all sweeps,
+// stream s = g mod 3 for the g-th slab.  Before the g-th slab is started, the
+// (g-1)-th is finished on its own stream: encode into its staging buffer,
+// record "working buffer free", copy back.  The g-th slab is copied in, waits
+// for that event (single working buffer only), decoded and stepped k times.
+// Three gaps of the printed algorithm are closed here: the stream index
+// advances every iteration, the last slab is finished after the loop, and the
+// first slab does not wait on an event that was never recorded.  The paper
+// updates its host chunks in place, which with temporal-blocking halos needs
+// region sharing or separate compression of the overlap (Sec. 3.1, Sec. 4.1);
+// instead the host keeps two levels that alternate as source and destination
+// by sweep, with per-slab copy events ordering the cross-sweep reuse:
+//   copy-in of slab j in sweep t waits for the copy-back of every slab of
+//   sweep t-1 whose interior it reads (halo overlap), and the copy-back of
+//   slab j in sweep t waits for every copy-in of sweep t-1 that read the planes
+//   it overwrites.
+#include "oc_plan.h"
+
+#include <algorithm>
+#include <cstdio>
+
+namespace oc {
+
+int stencil_radius(int kind) { return kind == KIND_WAVE25 ? 4 : 1; }
+
+size_t coded_layer_bytes(int64_t nx, int64_t ny, int rate) {
+  return (size_t)(nx / 4) * (size_t)(ny / 4) * 8u * (size_t)rate;
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Carves the arena for a given S; returns total bytes.
+static size_t carve(Plan *p) {
+  const PlanInput &in = p->in;
+  p->P = p->S + 2 * p->halo;
+  p->work_bytes = align256((size_t)p->P * p->plane_bytes);
+  size_t off = 0;
+  for (int s = 0; s < p->n_work_sets; s++)
+    for (int b = 0; b < p->n_work_bufs; b++) {
+      p->off_work[s][b] = off;
+      off += p->work_bytes;
+    }
+  for (int s = p->n_work_sets; s < 3; s++)
+    for (int b = 0; b < p->n_work_bufs; b++) p->off_work[s][b] = p->off_work[0][b];
+  p->stage_bytes = 0;
+  if (p->coded) {
+    int fields_in = p->n_rw + (p->ro_coded ? 1 : 0);
+    p->stage_bytes = align256((size_t)(p->P / 4) * p->layer_bytes * (size_t)fields_in);
+    for (int s = 0; s < 3; s++) {
+      p->off_stage[s] = off;
+      off += p->stage_bytes;
+    }
+  }
+  // STAR7 with a raw c0 field in single-buffer mode: the c0 slab is copied in
+  // per stream (it is read-only, so no copy back), then moved to the shared
+  // set after the working-buffer wait.
+  if (in.kind == KIND_STAR7 && in.c0_field && p->n_work_sets == 1) {
+    for (int s = 0; s < 3; s++) {
+      p->off_ro_stage[s] = off;
+      off += p->work_bytes;
+    }
+  }
+  (void)in;
+  return off;
+}
+
+int make_plan(const PlanInput &in, Plan *out) {
+  Plan p;
+  p.in = in;
+  if (in.nx <= 0 || in.ny <= 0 || in.nz <= 0 || in.k < 1 || in.rate < 0 || in.rate > 32 ||
+      in.slab_planes < 0 || (in.kind != KIND_STAR7 && in.kind != KIND_WAVE25))
+    return ST_ARG;
+  if (in.kind == KIND_WAVE25 && in.c0_field) return ST_ARG;
+  p.r = stencil_radius(in.kind);
+  p.coded = in.rate > 0;
+  if (p.coded && (in.nx % 4 || in.ny % 4 || in.nz % 4)) return ST_SHAPE;
+  if (p.coded && in.slab_planes % 4) return ST_SHAPE;
+  if (in.nx > (int64_t)1 << 30 || in.ny > (int64_t)1 << 30 || in.nz > (int64_t)1 << 30)
+    return ST_ARG;
+  p.n_rw = in.kind == KIND_WAVE25 ? 2 : 1;
+  p.has_ro = in.kind == KIND_WAVE25 || in.c0_field;
+  p.ro_coded = p.coded && in.kind == KIND_WAVE25;
+  p.plane_bytes = (size_t)in.nx * (size_t)in.ny * 4u;
+  p.layer_bytes = p.coded ? coded_layer_bytes(in.nx, in.ny, in.rate) : 0;
+  int64_t h = (int64_t)in.k * p.r;
+  p.halo = p.coded ? (h + 3) / 4 * 4 : h;
+  // working buffers: STAR7 a, b (+ c0 slab); WAVE25 v, pa, pb
+  p.n_work_bufs = in.kind == KIND_WAVE25 ? 3 : (in.c0_field ? 3 : 2);
+  // uncompressed runs always use one set per stream (Fig. 5a); compressed runs
+  // use one shared set (Sec. 5) unless asked otherwise (Fig. 5b).
+  p.n_work_sets = (p.coded && in.single_buffer) ? 1 : 3;
+
+  const int64_t step = p.coded ? 4 : 1;
+  if (in.slab_planes > 0) {
+    p.S = std::min<int64_t>(in.slab_planes, p.coded ? (in.nz + 3) / 4 * 4 : in.nz);
+    p.arena_bytes = carve(&p);
+    if (in.budget && p.arena_bytes > in.budget) return ST_BUDGET;
+  } else {
+    // largest S (multiple of `step`, at most nz) whose carve-out fits
+    int64_t best = 0;
+    int64_t lo = step, hi = (in.nz + step - 1) / step * step;
+    while (lo <= hi) {
+      int64_t mid = (lo + hi) / 2 / step * step;
+      if (mid < lo) mid = lo;
+      p.S = mid;
+      size_t need = carve(&p);
+      if (!in.budget || need <= in.budget) {
+        best = mid;
+        lo = mid + step;
+      } else {
+        hi = mid - step;
+      }
+    }
+    if (!best) return ST_BUDGET;
+    p.S = best;
+    p.arena_bytes = carve(&p);
+  }
+  // slabs
+  for (int64_t z0 = 0; z0 < in.nz; z0 += p.S) {
+    Slab s;
+    s.z0 = z0;
+    s.z1 = std::min<int64_t>(z0 + p.S, in.nz);
+    s.gz0 = z0 - p.halo;
+    s.l0 = std::max<int64_t>(0, z0 - p.halo);
+    s.l1 = std::min<int64_t>(in.nz, s.z1 + p.halo);
+    s.planes = (s.z1 - s.z0) + 2 * p.halo;
+    p.slabs.push_back(s);
+  }
+  // host storage
+  int64_t cells = in.nx * in.ny * in.nz;
+  p.host_field_bytes = p.coded ? (size_t)(in.nz / 4) * p.layer_bytes : (size_t)cells * 4u;
+  p.host_level_bytes = p.host_field_bytes * (size_t)p.n_rw;
+  p.host_aux_bytes = 0;
+  if (in.kind == KIND_WAVE25) p.host_aux_bytes = p.host_field_bytes;
+  if (in.c0_field) p.host_aux_bytes = (size_t)cells * 4u;
+  *out = p;
+  return ST_OK;
+}
+
+// ---------------------------------------------------------------------------
+// operation list
+// ---------------------------------------------------------------------------
+namespace {
+
+struct Builder {
+  const Plan &p;
+  std::vector<Op> *ops;
+  EventIds ev;
+  // Vector clocks of the streams and of each event's last record, used to
+  // leave out waits that stream order and earlier waits already imply.
+  int64_t vc[3][3] = {};
+  std::vector<std::array<int64_t, 3>> evc;
+  Builder(const Plan &pl, std::vector<Op> *o) : p(pl), ops(o) {
+    ev.n_slabs = (int)pl.slabs.size();
+    evc.assign((size_t)ev.count(), {-1, -1, -1});
+  }
+  Op blank(OpType t, int stream) {
+    Op o{};
+    o.type = t;
+    o.stream = (int8_t)stream;
+    o.host_id = -1;
+    o.ev = -1;
+    o.dev_src = o.dev_src2 = o.dev_dst = -1;
+    return o;
+  }
+  void push(const Op &o) {
+    if (o.type == OP_SYNC) {
+      for (int q = 0; q < 3; q++) {
+        int64_t m = 0;
+        for (int s = 0; s < 3; s++) m = std::max(m, vc[s][q]);
+        for (int s = 0; s < 3; s++) vc[s][q] = m;
+      }
+    } else if (o.type != OP_REC && o.type != OP_WAIT) {
+      vc[o.stream][o.stream]++;
+    }
+    ops->push_back(o);
+  }
+  void rec(int s, int e) {
+    Op o = blank(OP_REC, s);
+    o.ev = e;
+    for (int q = 0; q < 3; q++) evc[(size_t)e][q] = vc[s][q];
+    push(o);
+  }
+  void wait(int s, int e) {
+    const auto &c = evc[(size_t)e];
+    bool implied = true;
+    for (int q = 0; q < 3; q++) implied &= c[q] <= vc[s][q];
+    if (implied) return;
+    Op o = blank(OP_WAIT, s);
+    o.ev = e;
+    for (int q = 0; q < 3; q++) vc[s][q] = std::max(vc[s][q], c[q]);
+    push(o);
+  }
+  // indices of slabs whose loaded range intersects [a, b)
+  void readers_of(int64_t a, int64_t b, std::vector<int> *out) const {
+    out->clear();
+    for (size_t j = 0; j < p.slabs.size(); j++)
+      if (p.slabs[j].l0 < b && a < p.slabs[j].l1) out->push_back((int)j);
+  }
+  // indices of slabs whose interior intersects [a, b)
+  void writers_of(int64_t a, int64_t b, std::vector<int> *out) const {
+    out->clear();
+    for (size_t j = 0; j < p.slabs.size(); j++)
+      if (p.slabs[j].z0 < b && a < p.slabs[j].z1) out->push_back((int)j);
+  }
+  size_t work(int set, int b) const { return p.off_work[p.n_work_sets == 1 ? 0 : set][b]; }
+};
+
+}  // namespace
+
+void build_ops(const Plan &p, int64_t sweeps, int steps_last, int src, int64_t step0,
+               std::vector<Op> *ops) {
+  ops->clear();
+  Builder B(p, ops);
+  const int ns = (int)p.slabs.size();
+  const int64_t total = sweeps * ns;
+  const bool swb = p.n_work_sets == 1;
+  const bool wave = p.in.kind == KIND_WAVE25;
+  std::vector<int> nb;
+  // state of the slab in flight that still has to be finished
+  struct Pending { int64_t g; int stream, final_buf_a, final_buf_b; int sweep, slab; };
+  Pending pend{-1, 0, 0, 0, 0, 0};
+
+  auto finish = [&](const Pending &q) {
+    const Slab &sl = p.slabs[q.slab];
+    const int s = q.stream;
+    const int dst = (src + q.sweep + 1) & 1;
+    const int64_t lz = p.halo;   // local index of the first interior plane
+    const int64_t nz_int = sl.z1 - sl.z0;
+    // fields to send back: STAR7 u; WAVE25 p^n (field 0) and p^{n-1} (field 1)
+    int nf = p.n_rw;
+    int bufs[2] = {q.final_buf_a, q.final_buf_b};
+    if (p.coded) {
+      for (int f = 0; f < nf; f++) {
+        Op o = B.blank(OP_ENC, s);
+        o.dev_src = (int64_t)(B.work(s, bufs[f]) + (size_t)lz * p.plane_bytes);
+        o.dev_dst = (int64_t)(p.off_stage[s] + (size_t)f * (size_t)(nz_int / 4) * p.layer_bytes);
+        o.z_hi = nz_int / 4;
+        o.planes = nz_int;
+        o.slab = q.slab;
+        o.sweep = q.sweep;
+        B.push(o);
+      }
+      if (swb) B.rec(s, B.ev.fl(s));
+    }
+    // copy-back may overwrite planes read by copy-ins of the previous sweep
+    if (q.sweep > 0) {
+      B.readers_of(sl.z0, sl.z1, &nb);
+      for (int j : nb) B.wait(s, B.ev.h2d((q.sweep - 1) & 1, j));
+    }
+    for (int f = 0; f < nf; f++) {
+      Op o = B.blank(OP_D2H, s);
+      o.host_id = (int8_t)dst;
+      if (p.coded) {
+        o.dev_src = (int64_t)(p.off_stage[s] + (size_t)f * (size_t)(nz_int / 4) * p.layer_bytes);
+        o.host_off = (int64_t)((size_t)f * p.host_field_bytes + (size_t)(sl.z0 / 4) * p.layer_bytes);
+        o.bytes = (int64_t)((size_t)(nz_int / 4) * p.layer_bytes);
+      } else {
+        o.dev_src = (int64_t)(B.work(s, bufs[f]) + (size_t)lz * p.plane_bytes);
+        o.host_off = (int64_t)((size_t)f * p.host_field_bytes + (size_t)sl.z0 * p.plane_bytes);
+        o.bytes = (int64_t)((size_t)nz_int * p.plane_bytes);
+      }
+      o.slab = q.slab;
+      o.sweep = q.sweep;
+      B.push(o);
+    }
+    B.rec(s, B.ev.d2h(q.sweep & 1, q.slab));
+  };
+
+  for (int64_t g = 0; g < total; g++) {
+    const int t = (int)(g / ns), j = (int)(g % ns);
+    const int s = (int)(g % 3);
+    const Slab &sl = p.slabs[j];
+    const int srcl = (src + t) & 1;
+    const int ks = (t == sweeps - 1) ? steps_last : p.in.k;
+    if (pend.g >= 0) finish(pend);
+    // copy-in reads planes written by copy-backs of the previous sweep
+    if (t > 0) {
+      B.writers_of(sl.l0, sl.l1, &nb);
+      for (int jj : nb) B.wait(s, B.ev.d2h((t - 1) & 1, jj));
+    }
+    const int64_t loc0 = sl.l0 - sl.gz0;  // local plane of the first loaded plane
+    const int64_t nload = sl.l1 - sl.l0;
+    // buffer roles: STAR7 a=0, b=1, c0=2; WAVE25 v=0, pa=1 (p^{n-1}), pb=2 (p^n)
+    const int bv = 0, bpa = 1, bpb = 2;
+    // fields copied in: host field index -> working buffer
+    struct In { int host_id; size_t host_base; int buf; bool coded; };
+    In fin[3];
+    int nin = 0;
+    if (wave) {
+      fin[nin++] = {srcl, 0, bpb, p.coded};                   // p^n
+      fin[nin++] = {srcl, p.host_field_bytes, bpa, p.coded};  // p^{n-1}
+      fin[nin++] = {HOST_AUX, 0, bv, p.ro_coded};             // velocity
+    } else {
+      fin[nin++] = {srcl, 0, 0, p.coded};
+      if (p.in.c0_field) fin[nin++] = {HOST_AUX, 0, 2, false};
+    }
+    int ncoded = 0;
+    for (int f = 0; f < nin; f++) {
+      Op o = B.blank(OP_H2D, s);
+      o.host_id = (int8_t)fin[f].host_id;
+      if (fin[f].coded) {
+        o.dev_dst = (int64_t)(p.off_stage[s] + (size_t)ncoded * (size_t)(nload / 4) * p.layer_bytes);
+        o.host_off = (int64_t)(fin[f].host_base + (size_t)(sl.l0 / 4) * p.layer_bytes);
+        o.bytes = (int64_t)((size_t)(nload / 4) * p.layer_bytes);
+        ncoded++;
+      } else if (swb && fin[f].buf == 2 && !wave) {
+        // raw c0 slab into the per-stream staging; moved after the wait
+        o.dev_dst = (int64_t)(p.off_ro_stage[s] + (size_t)loc0 * p.plane_bytes);
+        o.host_off = (int64_t)((size_t)sl.l0 * p.plane_bytes);
+        o.bytes = (int64_t)((size_t)nload * p.plane_bytes);
+      } else {
+        o.dev_dst = (int64_t)(B.work(s, fin[f].buf) + (size_t)loc0 * p.plane_bytes);
+        o.host_off = (int64_t)(fin[f].host_base + (size_t)sl.l0 * p.plane_bytes);
+        o.bytes = (int64_t)((size_t)nload * p.plane_bytes);
+      }
+      o.slab = j;
+      o.sweep = t;
+      B.push(o);
+    }
+    B.rec(s, B.ev.h2d(t & 1, j));
+    if (swb && g > 0) B.wait(s, B.ev.fl((int)((g - 1) % 3)));
+    // decode coded fields into the working buffers
+    ncoded = 0;
+    for (int f = 0; f < nin; f++) {
+      if (fin[f].coded) {
+        Op o = B.blank(OP_DEC, s);
+        o.dev_src = (int64_t)(p.off_stage[s] + (size_t)ncoded * (size_t)(nload / 4) * p.layer_bytes);
+        o.dev_dst = (int64_t)(B.work(s, fin[f].buf) + (size_t)loc0 * p.plane_bytes);
+        o.z_hi = nload / 4;
+        o.planes = nload;
+        o.slab = j;
+        o.sweep = t;
+        B.push(o);
+        ncoded++;
+      } else if (swb && fin[f].buf == 2 && !wave) {
+        // device-to-device move of the c0 slab, expressed as a decode-free copy
+        Op o = B.blank(OP_DEC, s);
+        o.dev_src = (int64_t)(p.off_ro_stage[s] + (size_t)loc0 * p.plane_bytes);
+        o.dev_dst = (int64_t)(B.work(s, 2) + (size_t)loc0 * p.plane_bytes);
+        o.z_hi = -1;  // raw move marker
+        o.planes = nload;
+        o.bytes = (int64_t)((size_t)nload * p.plane_bytes);
+        o.slab = j;
+        o.sweep = t;
+        B.push(o);
+      }
+    }
+    // k steps inside the slab
+    const int64_t dom_lo = std::max<int64_t>(0, -sl.gz0);
+    const int64_t dom_hi = std::min<int64_t>(sl.planes, p.in.nz - sl.gz0);
+    const int64_t nz_int = sl.z1 - sl.z0;
+    int cur_a = 0, cur_b = 1;   // STAR7 ping-pong
+    int wa = bpa, wb = bpb;     // WAVE25: wa holds p^{n-1}, wb holds p^n
+    for (int st = 1; st <= ks; st++) {
+      const int64_t grow = (int64_t)(ks - st) * p.r;
+      int64_t zlo = std::max<int64_t>(p.halo - grow, dom_lo);
+      int64_t zhi = std::min<int64_t>(p.halo + nz_int + grow, dom_hi);
+      Op o = B.blank(wave ? OP_WAVE : OP_STAR7, s);
+      if (wave) {
+        o.dev_src = (int64_t)B.work(s, wb);        // p^n
+        o.dev_dst = (int64_t)B.work(s, wa);        // p^{n-1} -> p^{n+1}
+        o.dev_src2 = (int64_t)B.work(s, bv);       // velocity
+        o.step = step0 + (int64_t)t * p.in.k + (st - 1);
+        std::swap(wa, wb);
+      } else {
+        o.dev_src = (int64_t)B.work(s, cur_a);
+        o.dev_dst = (int64_t)B.work(s, cur_b);
+        o.dev_src2 = p.in.c0_field ? (int64_t)B.work(s, 2) : -1;
+        std::swap(cur_a, cur_b);
+      }
+      o.z_lo = zlo;
+      o.z_hi = zhi;
+      o.gz0 = sl.gz0;
+      o.planes = sl.planes;
+      o.slab = j;
+      o.sweep = t;
+      B.push(o);
+    }
+    pend.g = g;
+    pend.stream = s;
+    pend.sweep = t;
+    pend.slab = j;
+    if (wave) {
+      pend.final_buf_a = wb;  // p^n
+      pend.final_buf_b = wa;  // p^{n-1}
+    } else {
+      pend.final_buf_a = cur_a;
+      pend.final_buf_b = cur_a;
+    }
+  }
+  if (pend.g >= 0) finish(pend);   // epilogue: the last slab goes back too
+  B.push(B.blank(OP_SYNC, -1));
+}
+
+// ---------------------------------------------------------------------------
+// happens-before checker
+// ---------------------------------------------------------------------------
+namespace {
+
+struct Access {
+  int res;          // 0 = device arena, 1 + host id = host store
+  int64_t lo, hi;   // byte range
+  bool write;
+};
+
+void accesses(const Plan &p, const Op &o, std::vector<Access> *a) {
+  a->clear();
+  auto dev = [&](int64_t off, int64_t bytes, bool w) {
+    if (off >= 0 && bytes > 0) a->push_back({0, off, off + bytes, w});
+  };
+  switch (o.type) {
+    case OP_H2D:
+      a->push_back({1 + o.host_id, o.host_off, o.host_off + o.bytes, false});
+      dev(o.dev_dst, o.bytes, true);
+      break;
+    case OP_D2H:
+      dev(o.dev_src, o.bytes, false);
+      a->push_back({1 + o.host_id, o.host_off, o.host_off + o.bytes, true});
+      break;
+    case OP_DEC:
+      if (o.z_hi < 0) {
+        dev(o.dev_src, o.bytes, false);
+        dev(o.dev_dst, o.bytes, true);
+      } else {
+        dev(o.dev_src, (int64_t)((size_t)o.z_hi * p.layer_bytes), false);
+        dev(o.dev_dst, (int64_t)((size_t)o.z_hi * 4 * p.plane_bytes), true);
+      }
+      break;
+    case OP_ENC:
+      dev(o.dev_src, (int64_t)((size_t)o.z_hi * 4 * p.plane_bytes), false);
+      dev(o.dev_dst, (int64_t)((size_t)o.z_hi * p.layer_bytes), true);
+      break;
+    case OP_STAR7:
+    case OP_WAVE: {
+      // reads planes [z_lo - r, z_hi + r) of the source (and the aux buffer),
+      // writes [z_lo, z_hi) of the destination; WAVE also reads the destination
+      int64_t pb = (int64_t)p.plane_bytes;
+      int64_t rlo = std::max<int64_t>(0, o.z_lo - p.r), rhi = std::min<int64_t>(o.planes, o.z_hi + p.r);
+      dev(o.dev_src + rlo * pb, (rhi - rlo) * pb, false);
+      if (o.dev_src2 >= 0) dev(o.dev_src2 + o.z_lo * pb, (o.z_hi - o.z_lo) * pb, false);
+      if (o.type == OP_WAVE) dev(o.dev_dst + o.z_lo * pb, (o.z_hi - o.z_lo) * pb, false);
+      dev(o.dev_dst + o.z_lo * pb, (o.z_hi - o.z_lo) * pb, true);
+      break;
+    }
+    default:
+      break;
+  }
+}
+
+}  // namespace
+
+int64_t check_ops(const Plan &p, const std::vector<Op> &ops, std::string *why) {
+  const int NS = 3;
+  // vector clock per stream, and the clock captured by each event's last record
+  std::vector<std::vector<int64_t>> vc(NS, std::vector<int64_t>(NS, 0));
+  std::vector<std::vector<int64_t>> evc(EventIds{(int)p.slabs.size()}.count(),
+                                        std::vector<int64_t>(NS, -1));
+  std::vector<int> ev_recorded(evc.size(), 0);
+  struct Stamp { int stream; int64_t clock; std::vector<int64_t> vc; size_t op; };
+  std::vector<std::pair<Stamp, Access>> hist;
+  std::vector<Access> acc;
+  int64_t bad = 0;
+  for (size_t i = 0; i < ops.size(); i++) {
+    const Op &o = ops[i];
+    if (o.type == OP_SYNC) {
+      std::vector<int64_t> m(NS, 0);
+      for (int s = 0; s < NS; s++)
+        for (int q = 0; q < NS; q++) m[q] = std::max(m[q], vc[s][q]);
+      for (int s = 0; s < NS; s++) vc[s] = m;
+      continue;
+    }
+    const int s = o.stream;
+    if (o.type == OP_REC) {
+      evc[o.ev] = vc[s];
+      ev_recorded[o.ev] = 1;
+      continue;
+    }
+    if (o.type == OP_WAIT) {
+      if (!ev_recorded[o.ev]) {
+        bad++;
+        if (why && why->empty()) *why = "wait on an event never recorded, op " + std::to_string(i);
+        continue;
+      }
+      for (int q = 0; q < NS; q++) vc[s][q] = std::max(vc[s][q], evc[o.ev][q]);
+      continue;
+    }
+    vc[s][s]++;
+    Stamp st{s, vc[s][s], vc[s], i};
+    accesses(p, o, &acc);
+    for (const Access &a : acc) {
+      for (const auto &h : hist) {
+        const Access &b = h.second;
+        if (b.res != a.res || b.hi <= a.lo || a.hi <= b.lo || (!a.write && !b.write)) continue;
+        // ordered iff the earlier op's own clock is covered by this op's clock
+        bool ordered = st.vc[h.first.stream] >= h.first.clock;
+        if (!ordered) {
+          bad++;
+          if (why && why->empty()) {
+            char buf[256];
+            snprintf(buf, sizeof buf,
+                     "ops %zu (stream %d, type %d) and %zu (stream %d, type %d) conflict on "
+                     "resource %d [%lld,%lld)",
+                     h.first.op, h.first.stream, (int)ops[h.first.op].type, i, s, (int)o.type,
+                     a.res, (long long)std::max(a.lo, b.lo), (long long)std::min(a.hi, b.hi));
+            *why = buf;
+          }
+        }
+      }
+    }
+    for (const Access &a : acc) hist.push_back({st, a});
+  }
+  // every sweep must write back its whole destination level exactly once
+  {
+    int max_sweep = -1;
+    for (const Op &o : ops) max_sweep = std::max(max_sweep, (int)o.sweep);
+    for (int t = 0; t <= max_sweep; t++) {
+      std::vector<std::pair<int64_t, int64_t>> rs;
+      for (const Op &o : ops)
+        if (o.type == OP_D2H && o.sweep == t) rs.push_back({o.host_off, o.host_off + o.bytes});
+      std::sort(rs.begin(), rs.end());
+      int64_t at = 0;
+      for (const auto &r : rs) {
+        if (r.first != at) break;
+        at = r.second;
+      }
+      if (at != (int64_t)p.host_level_bytes) {
+        bad++;
+        if (why && why->empty())
+          *why = "sweep " + std::to_string(t) + " does not write back its whole level";
+      }
+    }
+  }
+  // everything must have been synchronised at the end
+  if (ops.empty() || ops.back().type != OP_SYNC) {
+    bad++;
+    if (why && why->empty()) *why = "operation list does not end with a host sync";
+  }
+  return bad;
+}
+
+}  // namespace oc

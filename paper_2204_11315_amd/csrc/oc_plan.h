@@ -1,0 +1,120 @@
+// oc_plan.h -- slab planner, buffer carve-out and operation list (host only).
+//
+// The schedule is data: the planner emits a flat list of operations (copies,
+// kernels, event records and waits) that the executor maps one-to-one onto HIP
+// calls, and that the happens-before checker analyses on the CPU.  No HIP
+// header is needed here.
+#pragma once
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace oc {
+
+enum Kind { KIND_STAR7 = 1, KIND_WAVE25 = 2 };
+
+// Storage ids of host memory an operation may touch.
+enum HostStore { HOST_LEVEL0 = 0, HOST_LEVEL1 = 1, HOST_AUX = 2 };
+
+enum OpType : uint8_t {
+  OP_H2D,    // host store -> device arena           (host_id, host_off, dev_dst, bytes)
+  OP_D2H,    // device arena -> host store           (dev_src, host_id, host_off, bytes)
+  OP_DEC,    // codec decode: dev_src codes -> dev_dst planes (layers)
+  OP_ENC,    // codec encode: dev_src planes -> dev_dst codes (layers)
+  OP_STAR7,  // one 7-point step: dev_src -> dev_dst, local planes [z_lo, z_hi)
+  OP_WAVE,   // one 25-point leapfrog step (dev_src = p^n, dev_dst = p^{n-1} -> p^{n+1})
+  OP_REC,    // record event ev on stream
+  OP_WAIT,   // stream waits for the latest record of ev
+  OP_SYNC    // host waits for every stream (end of a run)
+};
+
+struct Op {
+  OpType type;
+  int8_t stream;
+  int8_t host_id;
+  int32_t ev;
+  int64_t dev_src, dev_src2, dev_dst;  // arena byte offsets (-1 = none)
+  int64_t host_off, bytes;
+  int64_t z_lo, z_hi;   // STAR7/WAVE: local planes updated; DEC/ENC: number of layers in z_hi
+  int64_t gz0;          // global z of local plane 0 of the slab buffer
+  int64_t planes;       // planes of the slab buffer (extent for the hazard model)
+  int64_t step;         // WAVE: global time index n of p^n (source term)
+  int32_t slab, sweep;  // bookkeeping (tests, stats)
+};
+
+struct Slab {
+  int64_t z0, z1;   // interior global planes [z0, z1)
+  int64_t l0, l1;   // loaded global planes [l0, l1) (clipped to the domain)
+  int64_t gz0;      // global z of local plane 0 (= z0 - halo), may be negative
+  int64_t planes;   // buffer planes used = (z1 - z0) + 2 * halo
+};
+
+struct PlanInput {
+  int64_t nx = 0, ny = 0, nz = 0;
+  int kind = KIND_STAR7;
+  int k = 1;            // steps per residency
+  int slab_planes = 0;  // 0 = automatic
+  int rate = 0;         // 0 = raw
+  bool single_buffer = true;
+  bool c0_field = false;  // STAR7: a per-cell c0 slab rides along (raw)
+  size_t budget = 0;      // 0 = unlimited
+};
+
+struct Plan {
+  PlanInput in;
+  int r = 1;               // stencil radius
+  int64_t S = 0;           // interior planes per slab
+  int64_t halo = 0;        // loaded halo planes per side (k*r rounded up to 4 when coded)
+  int64_t P = 0;           // buffer planes = S + 2*halo
+  bool coded = false;
+  int n_rw = 1;            // read-write fields per level (STAR7 1, WAVE25 2)
+  bool has_ro = false;     // read-only field streamed with every slab
+  bool ro_coded = false;   // read-only field kept coded on the host
+  size_t plane_bytes = 0;  // nx*ny*4
+  size_t layer_bytes = 0;  // coded bytes of 4 planes
+  int n_work_sets = 1;     // working-buffer sets (1 shared or 3 per stream)
+  // arena carve-out (byte offsets)
+  size_t work_bytes = 0;   // one working buffer (P planes)
+  size_t off_work[3][4] = {};   // [set][buffer]: STAR7 a, b, c0 ; WAVE25 v, pa, pb
+  int n_work_bufs = 2;
+  size_t stage_bytes = 0;  // one coded staging buffer
+  size_t off_stage[3] = {};
+  size_t off_ro_stage[3] = {};  // STAR7 raw c0 slab per stream
+  size_t arena_bytes = 0;
+  std::vector<Slab> slabs;
+  // host storage
+  size_t host_field_bytes = 0;  // one field on the host (raw or coded)
+  size_t host_level_bytes = 0;  // n_rw fields
+  size_t host_aux_bytes = 0;
+};
+
+// Status codes mirror include/oc.h.
+constexpr int ST_OK = 0, ST_ARG = -1, ST_SHAPE = -2, ST_BUDGET = -3;
+
+int stencil_radius(int kind);
+size_t coded_layer_bytes(int64_t nx, int64_t ny, int rate);
+// Builds the plan; returns a status.
+int make_plan(const PlanInput &in, Plan *out);
+
+// Event numbering for a plan with n slabs.
+struct EventIds {
+  int n_slabs;
+  int fl(int s) const { return s; }                                   // working buffer free
+  int h2d(int parity, int j) const { return 3 + parity * n_slabs + j; }
+  int d2h(int parity, int j) const { return 3 + 2 * n_slabs + parity * n_slabs + j; }
+  int count() const { return 3 + 4 * n_slabs; }
+};
+
+// Operation list of `sweeps` consecutive sweeps starting from host level `src`
+// (0 or 1).  steps_last = steps of the final sweep (<= k).  step0 = global
+// time index at the start (WAVE25 source term).
+void build_ops(const Plan &p, int64_t sweeps, int steps_last, int src, int64_t step0,
+               std::vector<Op> *ops);
+
+// Happens-before checker: number of pairs of conflicting accesses that are not
+// ordered by stream order, event record/wait or host sync.  `why` (optional)
+// receives a description of the first one.
+int64_t check_ops(const Plan &p, const std::vector<Op> &ops, std::string *why);
+
+}  // namespace oc

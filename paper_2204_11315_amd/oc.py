@@ -1,0 +1,339 @@
+"""ctypes binding of the C ABI in include/oc.h (argument marshalling only).
+
+Every step of the compute path runs in the HIP library `liboc.so`; torch is
+used only to own device memory (the arena), pinned host memory (the host
+levels) and streams.  If the library has not been built, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liboc.so")
+
+OC_OK, OC_ERR_ARG, OC_ERR_SHAPE, OC_ERR_BUDGET = 0, -1, -2, -3
+OC_ERR_HIP, OC_ERR_NONFINITE, OC_ERR_STATE, OC_ERR_UNSUPPORTED = -4, -5, -6, -7
+OC_STAR7, OC_WAVE25 = 1, 2
+
+C_CONFIG1 = (0.4, 0.1, 0.1, 0.1, 0.1, 0.1, 0.1)
+
+
+class OCError(RuntimeError):
+    def __init__(self, status: int, what: str, msg: str = ""):
+        self.status = status
+        super().__init__("%s failed: %s (%d)%s" % (what, msg, status, ""))
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int64), ("ny", ctypes.c_int64), ("nz", ctypes.c_int64)]
+
+
+class Stencil(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("c", ctypes.c_float * 7), ("c0_is_field", ctypes.c_int32),
+                ("h", ctypes.c_float), ("dt", ctypes.c_float), ("src", ctypes.c_int64 * 3),
+                ("f_peak", ctypes.c_float), ("t0", ctypes.c_float)]
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("dev_arena", ctypes.c_void_p), ("dev_budget", ctypes.c_size_t),
+                ("streams", ctypes.c_void_p * 3), ("host_level", ctypes.c_void_p * 2),
+                ("host_level_bytes", ctypes.c_size_t), ("host_aux", ctypes.c_void_p),
+                ("host_aux_bytes", ctypes.c_size_t), ("k", ctypes.c_int32),
+                ("slab_planes", ctypes.c_int32), ("rate_bits", ctypes.c_int32),
+                ("single_buffer", ctypes.c_int32), ("timing", ctypes.c_int32)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("wall_s", ctypes.c_double), ("gcell_per_s", ctypes.c_double),
+                ("bytes_h2d", ctypes.c_uint64), ("bytes_d2h", ctypes.c_uint64),
+                ("peak_dev_bytes", ctypes.c_uint64), ("slab_visits", ctypes.c_uint64),
+                ("slab_planes", ctypes.c_int64), ("halo_planes", ctypes.c_int64),
+                ("n_slabs", ctypes.c_int64), ("n_ops", ctypes.c_uint64),
+                ("ms_decode", ctypes.c_double), ("ms_stencil", ctypes.c_double),
+                ("ms_encode", ctypes.c_double), ("ms_h2d", ctypes.c_double),
+                ("ms_d2h", ctypes.c_double), ("n_decode", ctypes.c_uint64),
+                ("n_stencil", ctypes.c_uint64), ("n_encode", ctypes.c_uint64),
+                ("n_h2d", ctypes.c_uint64), ("n_d2h", ctypes.c_uint64),
+                ("cells_stencil", ctypes.c_uint64), ("blocks_decode", ctypes.c_uint64),
+                ("blocks_encode", ctypes.c_uint64)]
+
+
+_lock = threading.Lock()
+_lib = None
+
+_P = ctypes.c_void_p
+_I32 = ctypes.c_int32
+_I64 = ctypes.c_int64
+_SZ = ctypes.c_size_t
+_SIGS = {
+    "oc_status_str": (ctypes.c_char_p, [ctypes.c_int]),
+    "oc_host_level_bytes": (_SZ, [_P, _P, _I32]),
+    "oc_host_aux_bytes": (_SZ, [_P, _P, _I32]),
+    "oc_plan_bytes": (_SZ, [_P, _P, _I32, _I32, _I32, _I32, _SZ]),
+    "oc_create": (ctypes.c_int, [_P, _P, _P, _P]),
+    "oc_load": (ctypes.c_int, [_P, _P, _P, _P]),
+    "oc_run": (ctypes.c_int, [_P, _I64]),
+    "oc_store": (ctypes.c_int, [_P, _P, _P]),
+    "oc_stats_get": (ctypes.c_int, [_P, _P]),
+    "oc_destroy": (ctypes.c_int, [_P]),
+    "oc_codec_bytes": (_SZ, [_I64, _I64, _I64, _I32]),
+    "oc_codec_compress": (ctypes.c_int, [_P, _I64, _I64, _I64, _I32, _P, _SZ, _P]),
+    "oc_codec_decompress": (ctypes.c_int, [_P, _I64, _I64, _I64, _I32, _P, _P]),
+    "oc_codec_status": (ctypes.c_int, [_P]),
+    "oc_star7_incore": (ctypes.c_int, [_P, _P, _P, _I64, _I64, _I64, _P, _P, _I64, _P]),
+    "oc_debug_fail_after": (ctypes.c_int, [_P, _I64]),
+    "oc_set_timing": (ctypes.c_int, [_P, _I32]),
+    "oc_debug_check_plan": (_I64, [_P, _P, _I32, _I32, _I32, _I32, _SZ, _I64, _I32, _I64]),
+    "oc_debug_plan_ops": (_I64, [_P, _P, _I32, _I32, _I32, _I32, _SZ, _I64, _P]),
+}
+EXPORTED = tuple(_SIGS)
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise OCError(OC_ERR_STATE, "load",
+                              "HIP library %s is missing; build it with __graft_entry__.build()"
+                              % LIB_PATH)
+            L = ctypes.CDLL(LIB_PATH)
+            for name, (res, args) in _SIGS.items():
+                fn = getattr(L, name)
+                fn.restype = res
+                fn.argtypes = args
+            _lib = L
+        return _lib
+
+
+def status_str(st: int) -> str:
+    return lib().oc_status_str(int(st)).decode()
+
+
+def _check(st: int, what: str):
+    if st != OC_OK:
+        raise OCError(st, what, status_str(st))
+
+
+def _ref(x):
+    return ctypes.cast(ctypes.byref(x), ctypes.c_void_p)
+
+
+def make_grid(shape) -> Grid:
+    nz, ny, nx = (int(v) for v in shape)
+    return Grid(nx, ny, nz)
+
+
+def make_star7(c=C_CONFIG1, c0_field: bool = False) -> Stencil:
+    st = Stencil()
+    st.kind = OC_STAR7
+    for i, v in enumerate(c):
+        st.c[i] = float(v)
+    st.c0_is_field = 1 if c0_field else 0
+    return st
+
+
+# ---- planner queries (no GPU needed) --------------------------------------
+def host_level_bytes(shape, stencil: Stencil, rate: int) -> int:
+    g = make_grid(shape)
+    return int(lib().oc_host_level_bytes(_ref(g), _ref(stencil), int(rate)))
+
+
+def host_aux_bytes(shape, stencil: Stencil, rate: int) -> int:
+    g = make_grid(shape)
+    return int(lib().oc_host_aux_bytes(_ref(g), _ref(stencil), int(rate)))
+
+
+def plan_bytes(shape, stencil: Stencil, k: int, slab_planes: int, rate: int,
+               single_buffer: bool = True, budget: int = 0) -> int:
+    g = make_grid(shape)
+    return int(lib().oc_plan_bytes(_ref(g), _ref(stencil), int(k), int(slab_planes), int(rate),
+                                   1 if single_buffer else 0, int(budget)))
+
+
+def check_plan(shape, stencil: Stencil, k: int, slab_planes: int, rate: int, sweeps: int,
+               single_buffer: bool = True, budget: int = 0, mutate: int = 0, i: int = 0) -> int:
+    g = make_grid(shape)
+    return int(lib().oc_debug_check_plan(_ref(g), _ref(stencil), int(k), int(slab_planes),
+                                         int(rate), 1 if single_buffer else 0, int(budget),
+                                         int(sweeps), int(mutate), int(i)))
+
+
+def plan_ops(shape, stencil: Stencil, k: int, slab_planes: int, rate: int, sweeps: int,
+             single_buffer: bool = True, budget: int = 0):
+    g = make_grid(shape)
+    nw = ctypes.c_int64(0)
+    n = int(lib().oc_debug_plan_ops(_ref(g), _ref(stencil), int(k), int(slab_planes), int(rate),
+                                    1 if single_buffer else 0, int(budget), int(sweeps),
+                                    _ref(nw)))
+    return n, int(nw.value)
+
+
+def codec_bytes(shape, rate: int) -> int:
+    nz, ny, nx = shape
+    return int(lib().oc_codec_bytes(int(nx), int(ny), int(nz), int(rate)))
+
+
+# ---- device-buffer entry points (need torch + a GPU) -----------------------
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_handle(stream):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dev(t, dtype, what):
+    torch = _torch()
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == dtype and t.is_contiguous()):
+        raise ValueError("%s must be a contiguous CUDA tensor of %s" % (what, dtype))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def compress(d_in, rate: int, out=None, stream=None):
+    """Fixed-rate encode of a [nz][ny][nx] float32 CUDA tensor; returns uint8 codes."""
+    torch = _torch()
+    nz, ny, nx = d_in.shape
+    nbytes = codec_bytes(d_in.shape, rate)
+    if nbytes == 0:
+        raise OCError(OC_ERR_SHAPE, "compress", "dims must be multiples of 4, rate 1..32")
+    if out is None:
+        out = torch.empty(nbytes, dtype=torch.uint8, device=d_in.device)
+    _check(lib().oc_codec_compress(_dev(d_in, torch.float32, "d_in"), nx, ny, nz, int(rate),
+                                   _dev(out, torch.uint8, "out"), out.numel(),
+                                   _stream_handle(stream)), "oc_codec_compress")
+    return out
+
+
+def decompress(d_codes, shape, rate: int, out=None, stream=None):
+    torch = _torch()
+    nz, ny, nx = shape
+    if d_codes.numel() < codec_bytes(shape, rate):
+        raise ValueError("code buffer too small")
+    if out is None:
+        out = torch.empty((nz, ny, nx), dtype=torch.float32, device=d_codes.device)
+    _check(lib().oc_codec_decompress(_dev(d_codes, torch.uint8, "d_codes"), nx, ny, nz, int(rate),
+                                     _dev(out, torch.float32, "out"), _stream_handle(stream)),
+           "oc_codec_decompress")
+    return out
+
+
+def codec_status(stream=None) -> int:
+    return int(lib().oc_codec_status(_stream_handle(stream)))
+
+
+def star7_incore(d_in, c, steps: int, c0f=None, stream=None):
+    """A^steps on a device field; returns a new CUDA tensor."""
+    torch = _torch()
+    nz, ny, nx = d_in.shape
+    out = torch.empty_like(d_in)
+    tmp = torch.empty_like(d_in) if steps > 1 else None
+    cc = (ctypes.c_float * 7)(*[float(v) for v in c])
+    _check(lib().oc_star7_incore(_dev(d_in, torch.float32, "d_in"), _dev(out, torch.float32, "out"),
+                                 None if tmp is None else ctypes.c_void_p(tmp.data_ptr()),
+                                 nx, ny, nz, ctypes.cast(cc, ctypes.c_void_p),
+                                 None if c0f is None else _dev(c0f, torch.float32, "c0f"),
+                                 int(steps), _stream_handle(stream)), "oc_star7_incore")
+    return out
+
+
+class OutOfCore:
+    """Out-of-core time stepping of a host-resident field (7-point star).
+
+    shape = (nz, ny, nx).  budget = bytes of device memory the library may use
+    (one torch allocation).  rate = 0 keeps raw FP32 on the host; 1..32 keeps
+    fixed-rate codes.  k = steps per residency; slab_planes = S (0 = auto).
+    """
+
+    def __init__(self, shape, c=C_CONFIG1, k: int = 4, rate: int = 0, budget: int = 512 << 20,
+                 slab_planes: int = 0, single_buffer: bool = True, c0_field: bool = False,
+                 timing: bool = False, device=None):
+        torch = _torch()
+        self.shape = tuple(int(v) for v in shape)
+        self.rate = int(rate)
+        self.k = int(k)
+        self.stencil = make_star7(c, c0_field)
+        self.grid = make_grid(self.shape)
+        self.device = torch.device(device if device is not None else "cuda")
+        need = plan_bytes(self.shape, self.stencil, k, slab_planes, rate, single_buffer, budget)
+        if need == 0:
+            raise OCError(OC_ERR_BUDGET, "plan", "no slab depth fits the budget")
+        self.arena = torch.empty(int(budget), dtype=torch.uint8, device=self.device)
+        self.streams = [torch.cuda.Stream(device=self.device) for _ in range(3)]
+        lb = host_level_bytes(self.shape, self.stencil, rate)
+        self.levels = [torch.empty(lb, dtype=torch.uint8, pin_memory=True) for _ in range(2)]
+        ab = host_aux_bytes(self.shape, self.stencil, rate)
+        self.aux = torch.empty(ab, dtype=torch.uint8, pin_memory=True) if ab else None
+        cfg = Config()
+        cfg.dev_arena = self.arena.data_ptr()
+        cfg.dev_budget = int(budget)
+        for i, s in enumerate(self.streams):
+            cfg.streams[i] = s.cuda_stream
+        cfg.host_level[0] = self.levels[0].data_ptr()
+        cfg.host_level[1] = self.levels[1].data_ptr()
+        cfg.host_level_bytes = lb
+        cfg.host_aux = self.aux.data_ptr() if self.aux is not None else None
+        cfg.host_aux_bytes = ab
+        cfg.k = int(k)
+        cfg.slab_planes = int(slab_planes)
+        cfg.rate_bits = int(rate)
+        cfg.single_buffer = 1 if single_buffer else 0
+        cfg.timing = 1 if timing else 0
+        self.cfg = cfg
+        h = ctypes.c_void_p()
+        torch.cuda.synchronize(self.device)
+        _check(lib().oc_create(_ref(self.grid), _ref(self.stencil), _ref(cfg), ctypes.byref(h)),
+               "oc_create")
+        self.h = h
+
+    def _host_f32(self, a):
+        a = np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+        if a.shape != self.shape:
+            raise ValueError("expected shape %s, got %s" % (self.shape, a.shape))
+        return a
+
+    def load(self, u, c0=None):
+        u = self._host_f32(u)
+        c0a = None if c0 is None else self._host_f32(c0)
+        _check(lib().oc_load(self.h, ctypes.c_void_p(u.ctypes.data),
+                             None if c0a is None else ctypes.c_void_p(c0a.ctypes.data), None),
+               "oc_load")
+
+    def run(self, steps: int):
+        _check(lib().oc_run(self.h, int(steps)), "oc_run")
+
+    def store(self) -> np.ndarray:
+        out = np.empty(self.shape, dtype=np.float32)
+        _check(lib().oc_store(self.h, ctypes.c_void_p(out.ctypes.data), None), "oc_store")
+        return out
+
+    def stats(self) -> dict:
+        s = Stats()
+        _check(lib().oc_stats_get(self.h, _ref(s)), "oc_stats_get")
+        return {name: getattr(s, name) for name, _ in Stats._fields_}
+
+    def set_timing(self, on: bool):
+        _check(lib().oc_set_timing(self.h, 1 if on else 0), "oc_set_timing")
+
+    def fail_after(self, n: int):
+        _check(lib().oc_debug_fail_after(self.h, int(n)), "oc_debug_fail_after")
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().oc_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,60 @@
+"""GPU 7-point stencil parity against the FP64 oracle (through the C ABI).
+
+FP32 kernel vs FP64 definition: relative L2 <= 1e-5 (the bar for the
+uncompressed path); the closed-form decay of a sine mode within 1e-6.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2204_11315_amd import inputs, oc
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+C = (0.4, 0.1, 0.1, 0.1, 0.1, 0.1, 0.1)
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def test_config1_incore_vs_fp64():
+    u0 = inputs.modes_field((64, 64, 64), seed=1)
+    got = oc.star7_incore(_dev(u0), C, 8).cpu().numpy()
+    want = oracle.star7_run(u0, C, 8)
+    assert rel_l2(got, want) <= 1e-5
+
+
+@pytest.mark.parametrize("m", [(1, 1, 1), (4, 4, 4), (1, 2, 3)])
+def test_sine_mode_closed_form(m):
+    shape = (64, 64, 64)
+    phi = inputs.single_mode(shape, m)
+    lam = 0.4 + 0.2 * sum(np.cos(np.pi * mi / 65) for mi in m)
+    got = oc.star7_incore(_dev(phi), C, 8).cpu().numpy()
+    assert rel_l2(got, lam ** 8 * phi) <= 1e-6
+
+
+def test_ragged_shape_asymmetric_coefficients_and_c0_field():
+    shape = (37, 29, 70)          # not multiples of the 64 x 4 x 8 tile
+    rng = np.random.default_rng(3)
+    u0 = rng.standard_normal(shape).astype(np.float32)
+    c = (0.3, 0.05, 0.15, 0.07, 0.13, 0.11, 0.09)
+    got = oc.star7_incore(_dev(u0), c, 5).cpu().numpy()
+    assert rel_l2(got, oracle.star7_run(u0, c, 5)) <= 1e-5
+    c0f = inputs.c0_field(shape)
+    got = oc.star7_incore(_dev(u0), c, 5, c0f=_dev(c0f)).cpu().numpy()
+    assert rel_l2(got, oracle.star7_run(u0, c, 5, c0f)) <= 1e-5
+
+
+def test_zero_and_one_step():
+    u0 = np.random.default_rng(4).standard_normal((8, 8, 8)).astype(np.float32)
+    assert np.array_equal(oc.star7_incore(_dev(u0), C, 0).cpu().numpy(), u0)
+    got = oc.star7_incore(_dev(u0), C, 1).cpu().numpy()
+    assert rel_l2(got, oracle.star7_run(u0, C, 1)) <= 1e-6
