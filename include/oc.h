@@ -80,6 +80,9 @@ typedef struct {
                               0 = one working buffer per stream                            */
   int32_t timing;          /* 1 = time every kernel and copy of oc_run with HIP events
                               (results in oc_stats; costs two event records per op)         */
+  int32_t ring_slots;      /* staging buffers in the copy ring, 2..8; 0 = 3 (Sec. 5)       */
+  int32_t prefetch;        /* slabs copied in ahead of the kernels, 1..ring_slots-1;
+                              0 = ring_slots - 1                                           */
 } oc_config;
 
 typedef struct {
@@ -106,10 +109,11 @@ size_t oc_host_level_bytes(const oc_grid *g, const oc_stencil *st, int32_t rate_
  * like a level; 0 when the stencil has none. */
 size_t oc_host_aux_bytes(const oc_grid *g, const oc_stencil *st, int32_t rate_bits);
 
-/* Bytes of device arena the plan needs (0 = automatic slab depth is chosen as
- * in oc_create).  Returns 0 when no plan fits `budget` (budget 0 = unlimited). */
-size_t oc_plan_bytes(const oc_grid *g, const oc_stencil *st, int32_t k, int32_t slab_planes,
-                     int32_t rate_bits, int32_t single_buffer, size_t budget);
+/* Bytes of device arena the plan for (g, st, cfg) needs; only the plan fields
+ * of cfg are read (k, slab_planes, rate_bits, single_buffer, ring_slots,
+ * prefetch; dev_budget caps the automatic slab depth, 0 = unlimited).
+ * Returns 0 when no plan fits. */
+size_t oc_plan_bytes(const oc_grid *g, const oc_stencil *st, const oc_config *cfg);
 
 /* Plans the sweep (slab depth, halos, buffer carve-out, operation list) on the
  * CPU and creates HIP events.  Fails with OC_ERR_BUDGET when the buffers do not
@@ -170,19 +174,17 @@ const char *oc_status_str(int status);
  * OC_ERR_HIP (n >= 1); n < 0 disables. */
 int oc_debug_fail_after(oc_handle *h, int64_t n);
 /* Builds the operation list of `sweeps` sweeps (k steps each) for the plan
- * these arguments describe, without a GPU, and runs the happens-before checker
+ * of (g, st, cfg) (plan fields only, as oc_plan_bytes), without a GPU, and runs the happens-before checker
  * over it: returns the number of unordered conflicting accesses plus sweeps
  * whose write-back does not cover the level (0 = race free and complete), or a
  * negative OC_ERR_* for a plan that cannot be made.
  * mutate: 0 none; 1 drop the i-th wait; 2 drop the epilogue (the last slab's
  * write-back); 3 swap op i with the next op of the same stream. */
-int64_t oc_debug_check_plan(const oc_grid *g, const oc_stencil *st, int32_t k, int32_t slab_planes,
-                            int32_t rate_bits, int32_t single_buffer, size_t budget, int64_t sweeps,
-                            int32_t mutate, int64_t i);
+int64_t oc_debug_check_plan(const oc_grid *g, const oc_stencil *st, const oc_config *cfg,
+                            int64_t sweeps, int32_t mutate, int64_t i);
 /* Operations in that list; *n_waits receives the number of stream waits. */
-int64_t oc_debug_plan_ops(const oc_grid *g, const oc_stencil *st, int32_t k, int32_t slab_planes,
-                          int32_t rate_bits, int32_t single_buffer, size_t budget, int64_t sweeps,
-                          int64_t *n_waits);
+int64_t oc_debug_plan_ops(const oc_grid *g, const oc_stencil *st, const oc_config *cfg,
+                          int64_t sweeps, int64_t *n_waits);
 
 #ifdef __cplusplus
 }

@@ -24,6 +24,9 @@ struct oc_handle {
   std::vector<hipEvent_t> ev;
   uint8_t *arena = nullptr;
   uint8_t *host[3] = {nullptr, nullptr, nullptr};  // level 0, level 1, aux
+  // device view of each host store when it is pinned and mapped (copy-backs
+  // then run as a small kernel), else nullptr (copy-backs use hipMemcpyAsync)
+  uint8_t *host_dev[3] = {nullptr, nullptr, nullptr};
   int cur = 0;            // host level holding the current state
   bool loaded = false;
   bool broken = false;
@@ -72,20 +75,30 @@ oc::Star7Coef coef_of(const oc_stencil &s) {
   return oc::Star7Coef{s.c[0], s.c[1], s.c[2], s.c[3], s.c[4], s.c[5], s.c[6]};
 }
 
-oc::PlanInput plan_input(const oc_grid *g, const oc_stencil *st, int k, int slab_planes, int rate,
-                         int single_buffer, size_t budget) {
+oc::PlanInput plan_input(const oc_grid *g, const oc_stencil *st, const oc_config *c) {
   oc::PlanInput in;
   in.nx = g->nx;
   in.ny = g->ny;
   in.nz = g->nz;
   in.kind = st->kind;
-  in.k = k;
-  in.slab_planes = slab_planes;
-  in.rate = rate;
-  in.single_buffer = single_buffer != 0;
+  in.k = c->k;
+  in.slab_planes = c->slab_planes;
+  in.rate = c->rate_bits;
+  in.single_buffer = c->single_buffer != 0;
   in.c0_field = st->kind == OC_STAR7 && st->c0_is_field;
-  in.budget = budget;
+  in.budget = c->dev_budget;
+  in.slots = c->ring_slots ? c->ring_slots : 3;
+  in.prefetch = c->prefetch ? c->prefetch : -1;
   return in;
+}
+
+oc_config level_query_config(int32_t rate_bits) {
+  oc_config c{};
+  c.k = 1;
+  c.slab_planes = 4;
+  c.rate_bits = rate_bits;
+  c.single_buffer = 1;
+  return c;
 }
 
 void drain(oc_handle *h) {
@@ -137,8 +150,12 @@ int issue(oc_handle *h, const std::vector<oc::Op> &ops) {
         h2d += (uint64_t)o.bytes;
         break;
       case oc::OP_D2H:
-        x.ok(hipMemcpyAsync(h->host[o.host_id] + o.host_off, h->arena + o.dev_src, (size_t)o.bytes,
-                            hipMemcpyDeviceToHost, s));
+        if (h->host_dev[o.host_id])
+          x.ok(oc::launch_copy_to_host(h->host_dev[o.host_id] + o.host_off, h->arena + o.dev_src,
+                                       (size_t)o.bytes, s));
+        else
+          x.ok(hipMemcpyAsync(h->host[o.host_id] + o.host_off, h->arena + o.dev_src,
+                              (size_t)o.bytes, hipMemcpyDeviceToHost, s));
         d2h += (uint64_t)o.bytes;
         break;
       case oc::OP_DEC:
@@ -224,6 +241,18 @@ int codec_check_and_clear() {
     return OC_ERR_NONFINITE;
   }
   return OC_OK;
+}
+
+// Device address of pinned, mapped host memory, or nullptr.
+uint8_t *mapped_host(void *p) {
+  if (!p) return nullptr;
+  hipPointerAttribute_t a;
+  if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  if (a.type != hipMemoryTypeHost || !a.devicePointer) return nullptr;
+  return (uint8_t *)a.devicePointer;
 }
 
 bool grid_ok(const oc_grid *g) {
@@ -375,24 +404,23 @@ int oc_star7_incore(const float *d_in, float *d_out, float *d_tmp, int64_t nx, i
 size_t oc_host_level_bytes(const oc_grid *g, const oc_stencil *st, int32_t rate_bits) {
   if (!grid_ok(g) || !st) return 0;
   oc::Plan p;
-  if (oc::make_plan(plan_input(g, st, 1, 4, rate_bits, 1, 0), &p) != oc::ST_OK) return 0;
+  oc_config c = level_query_config(rate_bits);
+  if (oc::make_plan(plan_input(g, st, &c), &p) != oc::ST_OK) return 0;
   return p.host_level_bytes;
 }
 
 size_t oc_host_aux_bytes(const oc_grid *g, const oc_stencil *st, int32_t rate_bits) {
   if (!grid_ok(g) || !st) return 0;
   oc::Plan p;
-  if (oc::make_plan(plan_input(g, st, 1, 4, rate_bits, 1, 0), &p) != oc::ST_OK) return 0;
+  oc_config c = level_query_config(rate_bits);
+  if (oc::make_plan(plan_input(g, st, &c), &p) != oc::ST_OK) return 0;
   return p.host_aux_bytes;
 }
 
-size_t oc_plan_bytes(const oc_grid *g, const oc_stencil *st, int32_t k, int32_t slab_planes,
-                     int32_t rate_bits, int32_t single_buffer, size_t budget) {
-  if (!grid_ok(g) || !st) return 0;
+size_t oc_plan_bytes(const oc_grid *g, const oc_stencil *st, const oc_config *cfg) {
+  if (!grid_ok(g) || !st || !cfg) return 0;
   oc::Plan p;
-  if (oc::make_plan(plan_input(g, st, k, slab_planes, rate_bits, single_buffer, budget), &p) !=
-      oc::ST_OK)
-    return 0;
+  if (oc::make_plan(plan_input(g, st, cfg), &p) != oc::ST_OK) return 0;
   return p.arena_bytes;
 }
 
@@ -402,9 +430,7 @@ int oc_create(const oc_grid *g, const oc_stencil *st, const oc_config *cfg, oc_h
   if (st->kind != OC_STAR7 && st->kind != OC_WAVE25) return OC_ERR_ARG;
   if (st->kind == OC_WAVE25) return OC_ERR_UNSUPPORTED;
   oc::Plan p;
-  int r = oc::make_plan(plan_input(g, st, cfg->k, cfg->slab_planes, cfg->rate_bits,
-                                   cfg->single_buffer, cfg->dev_budget),
-                        &p);
+  int r = oc::make_plan(plan_input(g, st, cfg), &p);
   if (r != oc::ST_OK) return r;
   if (!cfg->dev_arena || p.arena_bytes > cfg->dev_budget) return OC_ERR_BUDGET;
   if (!cfg->host_level[0] || !cfg->host_level[1] || cfg->host_level_bytes < p.host_level_bytes)
@@ -425,6 +451,7 @@ int oc_create(const oc_grid *g, const oc_stencil *st, const oc_config *cfg, oc_h
   h->host[0] = (uint8_t *)cfg->host_level[0];
   h->host[1] = (uint8_t *)cfg->host_level[1];
   h->host[2] = (uint8_t *)cfg->host_aux;
+  for (int i = 0; i < 3; i++) h->host_dev[i] = mapped_host(h->host[i]);
   oc::EventIds ids{(int)p.slabs.size()};
   h->ev.assign((size_t)ids.count(), nullptr);
   for (auto &e : h->ev) {
@@ -529,12 +556,11 @@ int oc_debug_fail_after(oc_handle *h, int64_t n) {
   return OC_OK;
 }
 
-int64_t oc_debug_plan_ops(const oc_grid *g, const oc_stencil *st, int32_t k, int32_t slab_planes,
-                          int32_t rate_bits, int32_t single_buffer, size_t budget, int64_t sweeps,
-                          int64_t *n_waits) {
-  if (!grid_ok(g) || !st || sweeps < 1) return OC_ERR_ARG;
+int64_t oc_debug_plan_ops(const oc_grid *g, const oc_stencil *st, const oc_config *cfg,
+                          int64_t sweeps, int64_t *n_waits) {
+  if (!grid_ok(g) || !st || !cfg || sweeps < 1) return OC_ERR_ARG;
   oc::Plan p;
-  int r = oc::make_plan(plan_input(g, st, k, slab_planes, rate_bits, single_buffer, budget), &p);
+  int r = oc::make_plan(plan_input(g, st, cfg), &p);
   if (r != oc::ST_OK) return r;
   std::vector<oc::Op> ops;
   oc::build_ops(p, sweeps, p.in.k, 0, 0, &ops);
@@ -546,12 +572,11 @@ int64_t oc_debug_plan_ops(const oc_grid *g, const oc_stencil *st, int32_t k, int
   return (int64_t)ops.size();
 }
 
-int64_t oc_debug_check_plan(const oc_grid *g, const oc_stencil *st, int32_t k, int32_t slab_planes,
-                            int32_t rate_bits, int32_t single_buffer, size_t budget, int64_t sweeps,
-                            int32_t mutate, int64_t i) {
-  if (!grid_ok(g) || !st || sweeps < 1) return OC_ERR_ARG;
+int64_t oc_debug_check_plan(const oc_grid *g, const oc_stencil *st, const oc_config *cfg,
+                            int64_t sweeps, int32_t mutate, int64_t i) {
+  if (!grid_ok(g) || !st || !cfg || sweeps < 1) return OC_ERR_ARG;
   oc::Plan p;
-  int r = oc::make_plan(plan_input(g, st, k, slab_planes, rate_bits, single_buffer, budget), &p);
+  int r = oc::make_plan(plan_input(g, st, cfg), &p);
   if (r != oc::ST_OK) return r;
   std::vector<oc::Op> ops;
   oc::build_ops(p, sweeps, p.in.k, 0, 0, &ops);

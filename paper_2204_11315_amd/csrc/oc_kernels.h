@@ -26,4 +26,8 @@ hipError_t launch_star7(const float *in, float *out, const float *c0f, int64_t n
                         int64_t z_lo, int64_t z_hi, int64_t gz0, int64_t nz, const Star7Coef &c,
                         hipStream_t s);
 
+// Copies `bytes` from device memory into host memory that the device can
+// address (pinned, mapped); a small grid so that it overlaps other kernels.
+hipError_t launch_copy_to_host(void *dst, const void *src, size_t bytes, hipStream_t s);
+
 }  // namespace oc

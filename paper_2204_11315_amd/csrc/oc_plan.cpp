@@ -7,22 +7,27 @@
 // Sec. 3.2: more steps per residency means more halo).  With a coded host
 // store the halo is rounded up to whole 4-plane block layers.
 //
-// Issue order (Sec. 5, Algorithm 1): slabs are taken in order over all sweeps,
-// stream s = g mod 3 for the g-th slab.  Before the g-th slab is started, the
-// (g-1)-th is finished on its own stream: encode into its staging buffer,
-// record "working buffer free", copy back.  The g-th slab is copied in, waits
-// for that event (single working buffer only), decoded and stepped k times.
-// Three gaps of the printed algorithm are closed here: the stream index
-// advances every iteration, the last slab is finished after the loop, and the
-// first slab does not wait on an event that was never recorded.  The paper
-// updates its host chunks in place, which with temporal-blocking halos needs
-// region sharing or separate compression of the overlap (Sec. 3.1, Sec. 4.1);
-// instead the host keeps two levels that alternate as source and destination
-// by sweep, with per-slab copy events ordering the cross-sweep reuse:
+// Issue order (Sec. 5, Algorithm 1 and Fig. 4): three streams overlap the
+// copy-in, the kernels and the copy-back.  Here each stream has one role --
+// stream 0 copies in, stream 1 runs every kernel (decode, k stencil steps,
+// encode), stream 2 copies back -- and the g-th slab uses slot g mod 3 of a
+// ring of three coded staging buffers.  Events link the roles: "slot landed"
+// (copy-in -> kernels), "slot coded" (kernels -> copy-back) and "slot free"
+// (copy-back -> next copy-in into that slot).  Because all kernels run on one
+// stream, the single shared working buffer (Sec. 5) is ordered by stream
+// order alone; the paper's "wait for the cyclically prior stream" edge
+// (Fig. 7) becomes that stream order.  Giving each DMA direction its own
+// stream keeps a copy-back from queueing in front of an unrelated copy-in.
+// The paper updates its host chunks in place, which with temporal-blocking
+// halos needs region sharing or separate compression of the overlap
+// (Sec. 3.1, Sec. 4.1); instead the host keeps two levels that alternate as
+// source and destination by sweep, with per-slab copy events ordering the
+// cross-sweep reuse:
 //   copy-in of slab j in sweep t waits for the copy-back of every slab of
 //   sweep t-1 whose interior it reads (halo overlap), and the copy-back of
 //   slab j in sweep t waits for every copy-in of sweep t-1 that read the planes
 //   it overwrites.
+// Waits already implied by stream order and earlier waits are left out.
 #include "oc_plan.h"
 
 #include <algorithm>
@@ -49,22 +54,22 @@ static size_t carve(Plan *p) {
       p->off_work[s][b] = off;
       off += p->work_bytes;
     }
-  for (int s = p->n_work_sets; s < 3; s++)
+  for (int s = p->n_work_sets; s < kMaxSlots; s++)
     for (int b = 0; b < p->n_work_bufs; b++) p->off_work[s][b] = p->off_work[0][b];
   p->stage_bytes = 0;
   if (p->coded) {
     int fields_in = p->n_rw + (p->ro_coded ? 1 : 0);
     p->stage_bytes = align256((size_t)(p->P / 4) * p->layer_bytes * (size_t)fields_in);
-    for (int s = 0; s < 3; s++) {
+    for (int s = 0; s < p->slots; s++) {
       p->off_stage[s] = off;
       off += p->stage_bytes;
     }
   }
   // STAR7 with a raw c0 field in single-buffer mode: the c0 slab is copied in
-  // per stream (it is read-only, so no copy back), then moved to the shared
-  // set after the working-buffer wait.
+  // per ring slot (it is read-only, so no copy back), then moved into the
+  // shared set on the kernel stream.
   if (in.kind == KIND_STAR7 && in.c0_field && p->n_work_sets == 1) {
-    for (int s = 0; s < 3; s++) {
+    for (int s = 0; s < p->slots; s++) {
       p->off_ro_stage[s] = off;
       off += p->work_bytes;
     }
@@ -80,6 +85,9 @@ int make_plan(const PlanInput &in, Plan *out) {
       in.slab_planes < 0 || (in.kind != KIND_STAR7 && in.kind != KIND_WAVE25))
     return ST_ARG;
   if (in.kind == KIND_WAVE25 && in.c0_field) return ST_ARG;
+  if (in.slots < 2 || in.slots > kMaxSlots || in.prefetch >= in.slots) return ST_ARG;
+  p.slots = in.slots;
+  p.prefetch = in.prefetch < 0 ? in.slots - 1 : in.prefetch;
   p.r = stencil_radius(in.kind);
   p.coded = in.rate > 0;
   if (p.coded && (in.nx % 4 || in.ny % 4 || in.nz % 4)) return ST_SHAPE;
@@ -95,9 +103,10 @@ int make_plan(const PlanInput &in, Plan *out) {
   p.halo = p.coded ? (h + 3) / 4 * 4 : h;
   // working buffers: STAR7 a, b (+ c0 slab); WAVE25 v, pa, pb
   p.n_work_bufs = in.kind == KIND_WAVE25 ? 3 : (in.c0_field ? 3 : 2);
-  // uncompressed runs always use one set per stream (Fig. 5a); compressed runs
-  // use one shared set (Sec. 5) unless asked otherwise (Fig. 5b).
-  p.n_work_sets = (p.coded && in.single_buffer) ? 1 : 3;
+  // uncompressed runs keep one working set per ring slot (three, as the three
+  // per-stream buffers of Fig. 5a); compressed runs share one set (Sec. 5)
+  // unless asked otherwise (three, Fig. 5b).
+  p.n_work_sets = (p.coded && in.single_buffer) ? 1 : p.slots;
 
   const int64_t step = p.coded ? 4 : 1;
   if (in.slab_planes > 0) {
@@ -190,15 +199,31 @@ struct Builder {
     for (int q = 0; q < 3; q++) evc[(size_t)e][q] = vc[s][q];
     push(o);
   }
-  void wait(int s, int e) {
-    const auto &c = evc[(size_t)e];
-    bool implied = true;
-    for (int q = 0; q < 3; q++) implied &= c[q] <= vc[s][q];
-    if (implied) return;
-    Op o = blank(OP_WAIT, s);
-    o.ev = e;
-    for (int q = 0; q < 3; q++) vc[s][q] = std::max(vc[s][q], c[q]);
-    push(o);
+  void wait(int s, int e) { wait_all(s, {e}); }
+  // Waits for every event of `es`, leaving out those already implied by the
+  // stream's clock or by another event of the set.
+  void wait_all(int s, const std::vector<int> &es) {
+    for (size_t a = 0; a < es.size(); a++) {
+      const auto &c = evc[(size_t)es[a]];
+      bool implied = true;
+      for (int q = 0; q < 3; q++) implied &= c[q] <= vc[s][q];
+      for (size_t b = 0; b < es.size() && !implied; b++) {
+        if (b == a) continue;
+        const auto &d = evc[(size_t)es[b]];
+        bool le = true, eq = true;
+        for (int q = 0; q < 3; q++) {
+          le &= c[q] <= d[q];
+          eq &= c[q] == d[q];
+        }
+        implied = le && (!eq || b < a);   // equal clocks: keep the first
+      }
+      if (implied) continue;
+      Op o = blank(OP_WAIT, s);
+      o.ev = es[a];
+      push(o);
+    }
+    for (int e : es)
+      for (int q = 0; q < 3; q++) vc[s][q] = std::max(vc[s][q], evc[(size_t)e][q]);
   }
   // indices of slabs whose loaded range intersects [a, b)
   void readers_of(int64_t a, int64_t b, std::vector<int> *out) const {
@@ -225,180 +250,212 @@ void build_ops(const Plan &p, int64_t sweeps, int steps_last, int src, int64_t s
   const int64_t total = sweeps * ns;
   const bool swb = p.n_work_sets == 1;
   const bool wave = p.in.kind == KIND_WAVE25;
+  const int NQ = p.slots;
   std::vector<int> nb;
-  // state of the slab in flight that still has to be finished
-  struct Pending { int64_t g; int stream, final_buf_a, final_buf_b; int sweep, slab; };
-  Pending pend{-1, 0, 0, 0, 0, 0};
+  // buffer roles: STAR7 a=0, b=1, c0=2; WAVE25 v=0, pa=1 (p^{n-1}), pb=2 (p^n)
+  const int bv = 0, bpa = 1, bpb = 2;
 
-  auto finish = [&](const Pending &q) {
-    const Slab &sl = p.slabs[q.slab];
-    const int s = q.stream;
-    const int dst = (src + q.sweep + 1) & 1;
-    const int64_t lz = p.halo;   // local index of the first interior plane
-    const int64_t nz_int = sl.z1 - sl.z0;
-    // fields to send back: STAR7 u; WAVE25 p^n (field 0) and p^{n-1} (field 1)
-    int nf = p.n_rw;
-    int bufs[2] = {q.final_buf_a, q.final_buf_b};
-    if (p.coded) {
-      for (int f = 0; f < nf; f++) {
-        Op o = B.blank(OP_ENC, s);
-        o.dev_src = (int64_t)(B.work(s, bufs[f]) + (size_t)lz * p.plane_bytes);
-        o.dev_dst = (int64_t)(p.off_stage[s] + (size_t)f * (size_t)(nz_int / 4) * p.layer_bytes);
-        o.z_hi = nz_int / 4;
-        o.planes = nz_int;
-        o.slab = q.slab;
-        o.sweep = q.sweep;
-        B.push(o);
-      }
-      if (swb) B.rec(s, B.ev.fl(s));
-    }
-    // copy-back may overwrite planes read by copy-ins of the previous sweep
-    if (q.sweep > 0) {
-      B.readers_of(sl.z0, sl.z1, &nb);
-      for (int j : nb) B.wait(s, B.ev.h2d((q.sweep - 1) & 1, j));
-    }
-    for (int f = 0; f < nf; f++) {
-      Op o = B.blank(OP_D2H, s);
-      o.host_id = (int8_t)dst;
-      if (p.coded) {
-        o.dev_src = (int64_t)(p.off_stage[s] + (size_t)f * (size_t)(nz_int / 4) * p.layer_bytes);
-        o.host_off = (int64_t)((size_t)f * p.host_field_bytes + (size_t)(sl.z0 / 4) * p.layer_bytes);
-        o.bytes = (int64_t)((size_t)(nz_int / 4) * p.layer_bytes);
-      } else {
-        o.dev_src = (int64_t)(B.work(s, bufs[f]) + (size_t)lz * p.plane_bytes);
-        o.host_off = (int64_t)((size_t)f * p.host_field_bytes + (size_t)sl.z0 * p.plane_bytes);
-        o.bytes = (int64_t)((size_t)nz_int * p.plane_bytes);
-      }
-      o.slab = q.slab;
-      o.sweep = q.sweep;
-      B.push(o);
-    }
-    B.rec(s, B.ev.d2h(q.sweep & 1, q.slab));
+  struct Geo {
+    int t, j, q, srcl, dstl, ks;
+    int64_t loc0, nload, nz_int;
+    const Slab *sl;
   };
-
-  for (int64_t g = 0; g < total; g++) {
-    const int t = (int)(g / ns), j = (int)(g % ns);
-    const int s = (int)(g % 3);
-    const Slab &sl = p.slabs[j];
-    const int srcl = (src + t) & 1;
-    const int ks = (t == sweeps - 1) ? steps_last : p.in.k;
-    if (pend.g >= 0) finish(pend);
-    // copy-in reads planes written by copy-backs of the previous sweep
-    if (t > 0) {
-      B.writers_of(sl.l0, sl.l1, &nb);
-      for (int jj : nb) B.wait(s, B.ev.d2h((t - 1) & 1, jj));
-    }
-    const int64_t loc0 = sl.l0 - sl.gz0;  // local plane of the first loaded plane
-    const int64_t nload = sl.l1 - sl.l0;
-    // buffer roles: STAR7 a=0, b=1, c0=2; WAVE25 v=0, pa=1 (p^{n-1}), pb=2 (p^n)
-    const int bv = 0, bpa = 1, bpb = 2;
-    // fields copied in: host field index -> working buffer
-    struct In { int host_id; size_t host_base; int buf; bool coded; };
-    In fin[3];
+  auto geo = [&](int64_t g) {
+    Geo x;
+    x.t = (int)(g / ns);
+    x.j = (int)(g % ns);
+    x.q = (int)(g % NQ);
+    x.sl = &p.slabs[x.j];
+    x.srcl = (src + x.t) & 1;
+    x.dstl = (src + x.t + 1) & 1;
+    x.ks = (x.t == sweeps - 1) ? steps_last : p.in.k;
+    x.loc0 = x.sl->l0 - x.sl->gz0;   // local plane of the first loaded plane
+    x.nload = x.sl->l1 - x.sl->l0;
+    x.nz_int = x.sl->z1 - x.sl->z0;
+    return x;
+  };
+  // fields copied in: (host store, base offset, working buffer, coded?)
+  struct In { int host_id; size_t host_base; int buf; bool coded; };
+  auto inputs = [&](const Geo &x, In *fin) {
     int nin = 0;
     if (wave) {
-      fin[nin++] = {srcl, 0, bpb, p.coded};                   // p^n
-      fin[nin++] = {srcl, p.host_field_bytes, bpa, p.coded};  // p^{n-1}
-      fin[nin++] = {HOST_AUX, 0, bv, p.ro_coded};             // velocity
+      fin[nin++] = {x.srcl, 0, bpb, p.coded};                   // p^n
+      fin[nin++] = {x.srcl, p.host_field_bytes, bpa, p.coded};  // p^{n-1}
+      fin[nin++] = {HOST_AUX, 0, bv, p.ro_coded};               // velocity
     } else {
-      fin[nin++] = {srcl, 0, 0, p.coded};
+      fin[nin++] = {x.srcl, 0, 0, p.coded};
       if (p.in.c0_field) fin[nin++] = {HOST_AUX, 0, 2, false};
     }
+    return nin;
+  };
+  const bool c0_staged = swb && !wave && p.in.c0_field;  // raw c0 rides in a per-slot stage
+
+  // ---- copy-in stream: slab g into slot g mod NQ -----------------------------
+  auto issue_in = [&](int64_t g) {
+    const Geo x = geo(g);
+    In fin[3];
+    const int nin = inputs(x, fin);
+    std::vector<int> w;
+    if (g >= NQ) w.push_back(B.ev.free(x.q));        // slot's previous copy-back done
+    if (x.t > 0) {                                   // planes written by last sweep's copy-backs
+      B.writers_of(x.sl->l0, x.sl->l1, &nb);
+      for (int jj : nb) w.push_back(B.ev.d2h((x.t - 1) & 1, jj));
+    }
+    B.wait_all(S_IN, w);
     int ncoded = 0;
     for (int f = 0; f < nin; f++) {
-      Op o = B.blank(OP_H2D, s);
+      Op o = B.blank(OP_H2D, S_IN);
       o.host_id = (int8_t)fin[f].host_id;
       if (fin[f].coded) {
-        o.dev_dst = (int64_t)(p.off_stage[s] + (size_t)ncoded * (size_t)(nload / 4) * p.layer_bytes);
-        o.host_off = (int64_t)(fin[f].host_base + (size_t)(sl.l0 / 4) * p.layer_bytes);
-        o.bytes = (int64_t)((size_t)(nload / 4) * p.layer_bytes);
+        o.dev_dst = (int64_t)(p.off_stage[x.q] + (size_t)ncoded * (size_t)(x.nload / 4) * p.layer_bytes);
+        o.host_off = (int64_t)(fin[f].host_base + (size_t)(x.sl->l0 / 4) * p.layer_bytes);
+        o.bytes = (int64_t)((size_t)(x.nload / 4) * p.layer_bytes);
         ncoded++;
-      } else if (swb && fin[f].buf == 2 && !wave) {
-        // raw c0 slab into the per-stream staging; moved after the wait
-        o.dev_dst = (int64_t)(p.off_ro_stage[s] + (size_t)loc0 * p.plane_bytes);
-        o.host_off = (int64_t)((size_t)sl.l0 * p.plane_bytes);
-        o.bytes = (int64_t)((size_t)nload * p.plane_bytes);
+      } else if (c0_staged && fin[f].buf == 2) {
+        o.dev_dst = (int64_t)(p.off_ro_stage[x.q] + (size_t)x.loc0 * p.plane_bytes);
+        o.host_off = (int64_t)((size_t)x.sl->l0 * p.plane_bytes);
+        o.bytes = (int64_t)((size_t)x.nload * p.plane_bytes);
       } else {
-        o.dev_dst = (int64_t)(B.work(s, fin[f].buf) + (size_t)loc0 * p.plane_bytes);
-        o.host_off = (int64_t)(fin[f].host_base + (size_t)sl.l0 * p.plane_bytes);
-        o.bytes = (int64_t)((size_t)nload * p.plane_bytes);
+        o.dev_dst = (int64_t)(B.work(x.q, fin[f].buf) + (size_t)x.loc0 * p.plane_bytes);
+        o.host_off = (int64_t)(fin[f].host_base + (size_t)x.sl->l0 * p.plane_bytes);
+        o.bytes = (int64_t)((size_t)x.nload * p.plane_bytes);
       }
-      o.slab = j;
-      o.sweep = t;
+      o.slab = x.j;
+      o.sweep = x.t;
       B.push(o);
     }
-    B.rec(s, B.ev.h2d(t & 1, j));
-    if (swb && g > 0) B.wait(s, B.ev.fl((int)((g - 1) % 3)));
-    // decode coded fields into the working buffers
-    ncoded = 0;
+    B.rec(S_IN, B.ev.in(x.q));
+    B.rec(S_IN, B.ev.h2d(x.t & 1, x.j));
+  };
+
+  // ---- kernel stream: decode, k steps, encode -------------------------------
+  // returns the working buffers holding the results (STAR7 u; WAVE25 p^n, p^{n-1})
+  auto issue_compute = [&](int64_t g, int *res) {
+    const Geo x = geo(g);
+    In fin[3];
+    const int nin = inputs(x, fin);
+    B.wait(S_COMPUTE, B.ev.in(x.q));
+    int ncoded = 0;
     for (int f = 0; f < nin; f++) {
       if (fin[f].coded) {
-        Op o = B.blank(OP_DEC, s);
-        o.dev_src = (int64_t)(p.off_stage[s] + (size_t)ncoded * (size_t)(nload / 4) * p.layer_bytes);
-        o.dev_dst = (int64_t)(B.work(s, fin[f].buf) + (size_t)loc0 * p.plane_bytes);
-        o.z_hi = nload / 4;
-        o.planes = nload;
-        o.slab = j;
-        o.sweep = t;
+        Op o = B.blank(OP_DEC, S_COMPUTE);
+        o.dev_src = (int64_t)(p.off_stage[x.q] + (size_t)ncoded * (size_t)(x.nload / 4) * p.layer_bytes);
+        o.dev_dst = (int64_t)(B.work(x.q, fin[f].buf) + (size_t)x.loc0 * p.plane_bytes);
+        o.z_hi = x.nload / 4;
+        o.planes = x.nload;
+        o.slab = x.j;
+        o.sweep = x.t;
         B.push(o);
         ncoded++;
-      } else if (swb && fin[f].buf == 2 && !wave) {
-        // device-to-device move of the c0 slab, expressed as a decode-free copy
-        Op o = B.blank(OP_DEC, s);
-        o.dev_src = (int64_t)(p.off_ro_stage[s] + (size_t)loc0 * p.plane_bytes);
-        o.dev_dst = (int64_t)(B.work(s, 2) + (size_t)loc0 * p.plane_bytes);
-        o.z_hi = -1;  // raw move marker
-        o.planes = nload;
-        o.bytes = (int64_t)((size_t)nload * p.plane_bytes);
-        o.slab = j;
-        o.sweep = t;
+      } else if (c0_staged && fin[f].buf == 2) {
+        Op o = B.blank(OP_DEC, S_COMPUTE);   // device-to-device move (raw marker z_hi < 0)
+        o.dev_src = (int64_t)(p.off_ro_stage[x.q] + (size_t)x.loc0 * p.plane_bytes);
+        o.dev_dst = (int64_t)(B.work(x.q, 2) + (size_t)x.loc0 * p.plane_bytes);
+        o.z_hi = -1;
+        o.planes = x.nload;
+        o.bytes = (int64_t)((size_t)x.nload * p.plane_bytes);
+        o.slab = x.j;
+        o.sweep = x.t;
         B.push(o);
       }
     }
-    // k steps inside the slab
-    const int64_t dom_lo = std::max<int64_t>(0, -sl.gz0);
-    const int64_t dom_hi = std::min<int64_t>(sl.planes, p.in.nz - sl.gz0);
-    const int64_t nz_int = sl.z1 - sl.z0;
+    const int64_t dom_lo = std::max<int64_t>(0, -x.sl->gz0);
+    const int64_t dom_hi = std::min<int64_t>(x.sl->planes, p.in.nz - x.sl->gz0);
     int cur_a = 0, cur_b = 1;   // STAR7 ping-pong
     int wa = bpa, wb = bpb;     // WAVE25: wa holds p^{n-1}, wb holds p^n
-    for (int st = 1; st <= ks; st++) {
-      const int64_t grow = (int64_t)(ks - st) * p.r;
-      int64_t zlo = std::max<int64_t>(p.halo - grow, dom_lo);
-      int64_t zhi = std::min<int64_t>(p.halo + nz_int + grow, dom_hi);
-      Op o = B.blank(wave ? OP_WAVE : OP_STAR7, s);
+    for (int st = 1; st <= x.ks; st++) {
+      const int64_t grow = (int64_t)(x.ks - st) * p.r;
+      Op o = B.blank(wave ? OP_WAVE : OP_STAR7, S_COMPUTE);
       if (wave) {
-        o.dev_src = (int64_t)B.work(s, wb);        // p^n
-        o.dev_dst = (int64_t)B.work(s, wa);        // p^{n-1} -> p^{n+1}
-        o.dev_src2 = (int64_t)B.work(s, bv);       // velocity
-        o.step = step0 + (int64_t)t * p.in.k + (st - 1);
+        o.dev_src = (int64_t)B.work(x.q, wb);     // p^n
+        o.dev_dst = (int64_t)B.work(x.q, wa);     // p^{n-1} -> p^{n+1}
+        o.dev_src2 = (int64_t)B.work(x.q, bv);    // velocity
+        o.step = step0 + (int64_t)x.t * p.in.k + (st - 1);
         std::swap(wa, wb);
       } else {
-        o.dev_src = (int64_t)B.work(s, cur_a);
-        o.dev_dst = (int64_t)B.work(s, cur_b);
-        o.dev_src2 = p.in.c0_field ? (int64_t)B.work(s, 2) : -1;
+        o.dev_src = (int64_t)B.work(x.q, cur_a);
+        o.dev_dst = (int64_t)B.work(x.q, cur_b);
+        o.dev_src2 = p.in.c0_field ? (int64_t)B.work(x.q, 2) : -1;
         std::swap(cur_a, cur_b);
       }
-      o.z_lo = zlo;
-      o.z_hi = zhi;
-      o.gz0 = sl.gz0;
-      o.planes = sl.planes;
-      o.slab = j;
-      o.sweep = t;
+      o.z_lo = std::max<int64_t>(p.halo - grow, dom_lo);
+      o.z_hi = std::min<int64_t>(p.halo + x.nz_int + grow, dom_hi);
+      o.gz0 = x.sl->gz0;
+      o.planes = x.sl->planes;
+      o.slab = x.j;
+      o.sweep = x.t;
       B.push(o);
     }
-    pend.g = g;
-    pend.stream = s;
-    pend.sweep = t;
-    pend.slab = j;
-    if (wave) {
-      pend.final_buf_a = wb;  // p^n
-      pend.final_buf_b = wa;  // p^{n-1}
-    } else {
-      pend.final_buf_a = cur_a;
-      pend.final_buf_b = cur_a;
+    res[0] = wave ? wb : cur_a;
+    res[1] = wave ? wa : cur_a;
+    if (p.coded) {
+      for (int f = 0; f < p.n_rw; f++) {
+        Op o = B.blank(OP_ENC, S_COMPUTE);
+        o.dev_src = (int64_t)(B.work(x.q, res[f]) + (size_t)p.halo * p.plane_bytes);
+        o.dev_dst = (int64_t)(p.off_stage[x.q] + (size_t)f * (size_t)(x.nz_int / 4) * p.layer_bytes);
+        o.z_hi = x.nz_int / 4;
+        o.planes = x.nz_int;
+        o.slab = x.j;
+        o.sweep = x.t;
+        B.push(o);
+      }
     }
+    B.rec(S_COMPUTE, B.ev.out(x.q));
+  };
+
+  // ---- copy-back stream ---------------------------------------------------------
+  auto issue_out = [&](int64_t g, const int *res) {
+    const Geo x = geo(g);
+    std::vector<int> w{B.ev.out(x.q)};
+    if (x.t > 0) {   // planes read by last sweep's copy-ins of this level
+      B.readers_of(x.sl->z0, x.sl->z1, &nb);
+      for (int jj : nb) w.push_back(B.ev.h2d((x.t - 1) & 1, jj));
+    }
+    B.wait_all(S_OUT, w);
+    for (int f = 0; f < p.n_rw; f++) {
+      Op o = B.blank(OP_D2H, S_OUT);
+      o.host_id = (int8_t)x.dstl;
+      if (p.coded) {
+        o.dev_src = (int64_t)(p.off_stage[x.q] + (size_t)f * (size_t)(x.nz_int / 4) * p.layer_bytes);
+        o.host_off = (int64_t)((size_t)f * p.host_field_bytes + (size_t)(x.sl->z0 / 4) * p.layer_bytes);
+        o.bytes = (int64_t)((size_t)(x.nz_int / 4) * p.layer_bytes);
+      } else {
+        o.dev_src = (int64_t)(B.work(x.q, res[f]) + (size_t)p.halo * p.plane_bytes);
+        o.host_off = (int64_t)((size_t)f * p.host_field_bytes + (size_t)x.sl->z0 * p.plane_bytes);
+        o.bytes = (int64_t)((size_t)x.nz_int * p.plane_bytes);
+      }
+      o.slab = x.j;
+      o.sweep = x.t;
+      B.push(o);
+    }
+    B.rec(S_OUT, B.ev.free(x.q));
+    B.rec(S_OUT, B.ev.d2h(x.t & 1, x.j));
+  };
+
+  // Copy-ins run up to `prefetch` slabs ahead and are issued before the
+  // copy-back of the slab being computed, so a copy-back that still waits for
+  // its kernels never sits in front of a copy-in that could already run.  A
+  // copy-in of sweep t is issued only after the copy-backs of sweep t-1 it
+  // depends on have been issued (with few slabs per sweep that limits the
+  // look-ahead), since a wait can only name an event already recorded.
+  const int L = p.prefetch;
+  int64_t next_in = 0, outs_issued = 0;
+  auto in_ready = [&](int64_t gi) {
+    const int t = (int)(gi / ns);
+    if (t == 0) return true;
+    const Slab &sl = p.slabs[(size_t)(gi % ns)];
+    B.writers_of(sl.l0, sl.l1, &nb);
+    int jmax = 0;
+    for (int jj : nb) jmax = std::max(jmax, jj);
+    return (int64_t)(t - 1) * ns + jmax < outs_issued;
+  };
+  for (int64_t g = 0; g < total; g++) {
+    while (next_in < total && next_in <= g + L && in_ready(next_in)) issue_in(next_in++);
+    int res[2];
+    issue_compute(g, res);
+    issue_out(g, res);
+    outs_issued = g + 1;
   }
-  if (pend.g >= 0) finish(pend);   // epilogue: the last slab goes back too
   B.push(B.blank(OP_SYNC, -1));
 }
 

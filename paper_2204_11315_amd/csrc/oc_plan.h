@@ -59,7 +59,11 @@ struct PlanInput {
   bool single_buffer = true;
   bool c0_field = false;  // STAR7: a per-cell c0 slab rides along (raw)
   size_t budget = 0;      // 0 = unlimited
+  int slots = 3;          // staging ring slots (2..8)
+  int prefetch = -1;      // copy-ins issued ahead of the kernels (-1 = slots - 1)
 };
+
+constexpr int kMaxSlots = 8;
 
 struct Plan {
   PlanInput in;
@@ -73,14 +77,16 @@ struct Plan {
   bool ro_coded = false;   // read-only field kept coded on the host
   size_t plane_bytes = 0;  // nx*ny*4
   size_t layer_bytes = 0;  // coded bytes of 4 planes
-  int n_work_sets = 1;     // working-buffer sets (1 shared or 3 per stream)
+  int slots = 3;           // staging ring slots
+  int prefetch = 2;        // copy-ins issued ahead
+  int n_work_sets = 1;     // working-buffer sets (1 shared, or one per ring slot)
   // arena carve-out (byte offsets)
   size_t work_bytes = 0;   // one working buffer (P planes)
-  size_t off_work[3][4] = {};   // [set][buffer]: STAR7 a, b, c0 ; WAVE25 v, pa, pb
+  size_t off_work[kMaxSlots][4] = {};   // [set][buffer]: STAR7 a, b, c0 ; WAVE25 v, pa, pb
   int n_work_bufs = 2;
   size_t stage_bytes = 0;  // one coded staging buffer
-  size_t off_stage[3] = {};
-  size_t off_ro_stage[3] = {};  // STAR7 raw c0 slab per stream
+  size_t off_stage[kMaxSlots] = {};
+  size_t off_ro_stage[kMaxSlots] = {};  // STAR7 raw c0 slab per ring slot (single working buffer)
   size_t arena_bytes = 0;
   std::vector<Slab> slabs;
   // host storage
@@ -97,13 +103,21 @@ size_t coded_layer_bytes(int64_t nx, int64_t ny, int rate);
 // Builds the plan; returns a status.
 int make_plan(const PlanInput &in, Plan *out);
 
-// Event numbering for a plan with n slabs.
+// Streams of the schedule: copies in, kernels, copies out.
+enum StreamRole { S_IN = 0, S_COMPUTE = 1, S_OUT = 2 };
+
+// Event numbering for a plan with n slabs.  Slot q = g mod slots of the
+// staging ring: "in" = its copy-in landed, "out" = its coded result is ready,
+// "free" = its copy-back finished.  Per slab and sweep parity: copy-in /
+// copy-back of that slab done (cross-sweep host-level hazards).
 struct EventIds {
   int n_slabs;
-  int fl(int s) const { return s; }                                   // working buffer free
-  int h2d(int parity, int j) const { return 3 + parity * n_slabs + j; }
-  int d2h(int parity, int j) const { return 3 + 2 * n_slabs + parity * n_slabs + j; }
-  int count() const { return 3 + 4 * n_slabs; }
+  int in(int q) const { return q; }
+  int out(int q) const { return kMaxSlots + q; }
+  int free(int q) const { return 2 * kMaxSlots + q; }
+  int h2d(int parity, int j) const { return 3 * kMaxSlots + parity * n_slabs + j; }
+  int d2h(int parity, int j) const { return 3 * kMaxSlots + 2 * n_slabs + parity * n_slabs + j; }
+  int count() const { return 3 * kMaxSlots + 4 * n_slabs; }
 };
 
 // Operation list of `sweeps` consecutive sweeps starting from host level `src`

@@ -44,7 +44,8 @@ class Config(ctypes.Structure):
                 ("host_level_bytes", ctypes.c_size_t), ("host_aux", ctypes.c_void_p),
                 ("host_aux_bytes", ctypes.c_size_t), ("k", ctypes.c_int32),
                 ("slab_planes", ctypes.c_int32), ("rate_bits", ctypes.c_int32),
-                ("single_buffer", ctypes.c_int32), ("timing", ctypes.c_int32)]
+                ("single_buffer", ctypes.c_int32), ("timing", ctypes.c_int32),
+                ("ring_slots", ctypes.c_int32), ("prefetch", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -73,7 +74,7 @@ _SIGS = {
     "oc_status_str": (ctypes.c_char_p, [ctypes.c_int]),
     "oc_host_level_bytes": (_SZ, [_P, _P, _I32]),
     "oc_host_aux_bytes": (_SZ, [_P, _P, _I32]),
-    "oc_plan_bytes": (_SZ, [_P, _P, _I32, _I32, _I32, _I32, _SZ]),
+    "oc_plan_bytes": (_SZ, [_P, _P, _P]),
     "oc_create": (ctypes.c_int, [_P, _P, _P, _P]),
     "oc_load": (ctypes.c_int, [_P, _P, _P, _P]),
     "oc_run": (ctypes.c_int, [_P, _I64]),
@@ -87,8 +88,8 @@ _SIGS = {
     "oc_star7_incore": (ctypes.c_int, [_P, _P, _P, _I64, _I64, _I64, _P, _P, _I64, _P]),
     "oc_debug_fail_after": (ctypes.c_int, [_P, _I64]),
     "oc_set_timing": (ctypes.c_int, [_P, _I32]),
-    "oc_debug_check_plan": (_I64, [_P, _P, _I32, _I32, _I32, _I32, _SZ, _I64, _I32, _I64]),
-    "oc_debug_plan_ops": (_I64, [_P, _P, _I32, _I32, _I32, _I32, _SZ, _I64, _P]),
+    "oc_debug_check_plan": (_I64, [_P, _P, _P, _I64, _I32, _I64]),
+    "oc_debug_plan_ops": (_I64, [_P, _P, _P, _I64, _P]),
 }
 EXPORTED = tuple(_SIGS)
 
@@ -149,28 +150,43 @@ def host_aux_bytes(shape, stencil: Stencil, rate: int) -> int:
     return int(lib().oc_host_aux_bytes(_ref(g), _ref(stencil), int(rate)))
 
 
+def plan_config(k: int, slab_planes: int, rate: int, single_buffer: bool = True,
+                budget: int = 0, ring_slots: int = 0, prefetch: int = 0) -> Config:
+    """A Config carrying only the plan fields."""
+    cfg = Config()
+    cfg.k = int(k)
+    cfg.slab_planes = int(slab_planes)
+    cfg.rate_bits = int(rate)
+    cfg.single_buffer = 1 if single_buffer else 0
+    cfg.dev_budget = int(budget)
+    cfg.ring_slots = int(ring_slots)
+    cfg.prefetch = int(prefetch)
+    return cfg
+
+
 def plan_bytes(shape, stencil: Stencil, k: int, slab_planes: int, rate: int,
-               single_buffer: bool = True, budget: int = 0) -> int:
+               single_buffer: bool = True, budget: int = 0, ring_slots: int = 0,
+               prefetch: int = 0) -> int:
     g = make_grid(shape)
-    return int(lib().oc_plan_bytes(_ref(g), _ref(stencil), int(k), int(slab_planes), int(rate),
-                                   1 if single_buffer else 0, int(budget)))
+    cfg = plan_config(k, slab_planes, rate, single_buffer, budget, ring_slots, prefetch)
+    return int(lib().oc_plan_bytes(_ref(g), _ref(stencil), _ref(cfg)))
 
 
 def check_plan(shape, stencil: Stencil, k: int, slab_planes: int, rate: int, sweeps: int,
-               single_buffer: bool = True, budget: int = 0, mutate: int = 0, i: int = 0) -> int:
+               single_buffer: bool = True, budget: int = 0, mutate: int = 0, i: int = 0,
+               ring_slots: int = 0, prefetch: int = 0) -> int:
     g = make_grid(shape)
-    return int(lib().oc_debug_check_plan(_ref(g), _ref(stencil), int(k), int(slab_planes),
-                                         int(rate), 1 if single_buffer else 0, int(budget),
-                                         int(sweeps), int(mutate), int(i)))
+    cfg = plan_config(k, slab_planes, rate, single_buffer, budget, ring_slots, prefetch)
+    return int(lib().oc_debug_check_plan(_ref(g), _ref(stencil), _ref(cfg), int(sweeps),
+                                         int(mutate), int(i)))
 
 
 def plan_ops(shape, stencil: Stencil, k: int, slab_planes: int, rate: int, sweeps: int,
-             single_buffer: bool = True, budget: int = 0):
+             single_buffer: bool = True, budget: int = 0, ring_slots: int = 0, prefetch: int = 0):
     g = make_grid(shape)
+    cfg = plan_config(k, slab_planes, rate, single_buffer, budget, ring_slots, prefetch)
     nw = ctypes.c_int64(0)
-    n = int(lib().oc_debug_plan_ops(_ref(g), _ref(stencil), int(k), int(slab_planes), int(rate),
-                                    1 if single_buffer else 0, int(budget), int(sweeps),
-                                    _ref(nw)))
+    n = int(lib().oc_debug_plan_ops(_ref(g), _ref(stencil), _ref(cfg), int(sweeps), _ref(nw)))
     return n, int(nw.value)
 
 
@@ -190,6 +206,24 @@ def _stream_handle(stream):
     if stream is None:
         stream = torch.cuda.current_stream()
     return ctypes.c_void_p(stream.cuda_stream)
+
+
+_stream_pool = {}
+
+
+def pipeline_streams(device=None):
+    """The three streams (copy-in, kernels, copy-back) every handle on `device`
+    shares.  Created once per process: each new stream takes a hardware queue,
+    and once there are more streams than queues, streams share queues and the
+    copy-in stream would end up ordered behind unrelated copy-back work."""
+    torch = _torch()
+    dev = torch.device(device if device is not None else "cuda")
+    if dev.index is None:
+        dev = torch.device("cuda", torch.cuda.current_device())
+    with _lock:
+        if dev not in _stream_pool:
+            _stream_pool[dev] = [torch.cuda.Stream(device=dev) for _ in range(3)]
+        return _stream_pool[dev]
 
 
 def _dev(t, dtype, what):
@@ -256,7 +290,7 @@ class OutOfCore:
 
     def __init__(self, shape, c=C_CONFIG1, k: int = 4, rate: int = 0, budget: int = 512 << 20,
                  slab_planes: int = 0, single_buffer: bool = True, c0_field: bool = False,
-                 timing: bool = False, device=None):
+                 timing: bool = False, ring_slots: int = 0, prefetch: int = 0, device=None):
         torch = _torch()
         self.shape = tuple(int(v) for v in shape)
         self.rate = int(rate)
@@ -264,11 +298,12 @@ class OutOfCore:
         self.stencil = make_star7(c, c0_field)
         self.grid = make_grid(self.shape)
         self.device = torch.device(device if device is not None else "cuda")
-        need = plan_bytes(self.shape, self.stencil, k, slab_planes, rate, single_buffer, budget)
+        need = plan_bytes(self.shape, self.stencil, k, slab_planes, rate, single_buffer, budget,
+                          ring_slots, prefetch)
         if need == 0:
             raise OCError(OC_ERR_BUDGET, "plan", "no slab depth fits the budget")
         self.arena = torch.empty(int(budget), dtype=torch.uint8, device=self.device)
-        self.streams = [torch.cuda.Stream(device=self.device) for _ in range(3)]
+        self.streams = pipeline_streams(self.device)
         lb = host_level_bytes(self.shape, self.stencil, rate)
         self.levels = [torch.empty(lb, dtype=torch.uint8, pin_memory=True) for _ in range(2)]
         ab = host_aux_bytes(self.shape, self.stencil, rate)
@@ -288,6 +323,8 @@ class OutOfCore:
         cfg.rate_bits = int(rate)
         cfg.single_buffer = 1 if single_buffer else 0
         cfg.timing = 1 if timing else 0
+        cfg.ring_slots = int(ring_slots)
+        cfg.prefetch = int(prefetch)
         self.cfg = cfg
         h = ctypes.c_void_p()
         torch.cuda.synchronize(self.device)

@@ -23,7 +23,8 @@ def _fields(shape, seed):
         "grf": inputs.grf_field(shape, seed=seed) if min(shape) >= 4 else None,
         "modes": inputs.modes_field(shape, seed=seed),
         "denormal": (rng.standard_normal(shape) * 1e-39).astype(np.float32),
-        "extreme": (rng.standard_normal(shape) * np.exp2(rng.integers(-126, 127, size=shape))
+        "extreme": (np.clip(rng.standard_normal(shape), -1.9, 1.9)
+                    * np.exp2(rng.integers(-126, 127, size=shape))
                     ).astype(np.float32),
         "offset": (1000.0 + 1e-3 * rng.standard_normal(shape)).astype(np.float32),
     }

@@ -111,7 +111,7 @@ def test_automatic_slab_depth_fits_budget():
 
 
 CASES = [((40, 12, 16), 4, 8), ((44, 8, 8), 4, 12), ((16, 8, 8), 4, 4), ((64, 8, 8), 2, 16),
-         ((36, 8, 12), 3, 8)]
+         ((36, 8, 12), 3, 8), ((16, 8, 8), 2, 16), ((16, 8, 8), 2, 8), ((24, 8, 8), 1, 12)]
 
 
 @pytest.mark.parametrize("shape,k,S", CASES)
@@ -123,6 +123,28 @@ def test_operation_list_race_free_and_minimal(shape, k, S, R, swb):
     for i in range(nw):
         assert oc.check_plan(shape, ST, k, S, R, 3, single_buffer=swb, mutate=1, i=i) > 0, i
     assert oc.check_plan(shape, ST, k, S, R, 3, single_buffer=swb, mutate=2) > 0
+
+
+@pytest.mark.parametrize("slots,prefetch", [(2, 1), (3, 1), (4, 3), (5, 2)])
+@pytest.mark.parametrize("R", [0, 8])
+def test_ring_slots_and_prefetch_race_free(slots, prefetch, R):
+    shape, k, S = (40, 12, 16), 4, 8
+    n, nw = oc.plan_ops(shape, ST, k, S, R, 3, ring_slots=slots, prefetch=prefetch)
+    assert oc.check_plan(shape, ST, k, S, R, 3, ring_slots=slots, prefetch=prefetch) == 0
+    for i in range(nw):
+        assert oc.check_plan(shape, ST, k, S, R, 3, ring_slots=slots, prefetch=prefetch,
+                             mutate=1, i=i) > 0
+    # staging ring grows the arena by one coded buffer per slot
+    if R:
+        extra = oc.plan_bytes(shape, ST, k, S, R, ring_slots=slots + 1) - \
+            oc.plan_bytes(shape, ST, k, S, R, ring_slots=slots)
+        assert extra == (S + 2 * 4) // 4 * oc.codec_bytes((4, 12, 16), R)
+
+
+def test_invalid_ring_parameters():
+    assert oc.plan_bytes((40, 12, 16), ST, 4, 8, 8, ring_slots=9) == 0
+    assert oc.plan_bytes((40, 12, 16), ST, 4, 8, 8, ring_slots=1) == 0
+    assert oc.plan_bytes((40, 12, 16), ST, 4, 8, 8, ring_slots=3, prefetch=3) == 0
 
 
 def test_some_reorderings_are_caught():
