@@ -149,6 +149,33 @@ def cpu_baseline(u0, rate):
                       "(load-encode, decode, 4 FP64 steps, encode, decode), %.1f s" % (rate, dt)}
 
 
+def kernel_probe(rate, reps=20):
+    """Launches each hot kernel at its slab shape `reps` times through the C ABI
+    (no pipeline), plus a plain 256 MiB device copy as the counter reference.
+    Used under rocprofv3 (kernel trace, FETCH_SIZE / WRITE_SIZE counters)."""
+    import torch
+    from paper_2204_11315_amd import inputs, oc
+    P = S + 2 * 4
+    u = torch.from_numpy(inputs.grf_field((P, 512, 512), seed=3)).cuda()
+    codes = oc.compress(u, rate)
+    out = torch.empty_like(u)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        oc.decompress(codes, u.shape, rate, out=out)           # 18 layers = one slab copy-in
+    for _ in range(reps):
+        oc.compress(u[4:4 + S].contiguous(), rate)             # 16 layers = one slab interior
+    for _ in range(reps):
+        oc.star7_incore(u, C, 1)                               # one step over 72 planes
+    a = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)                                             # reference: 256 MiB read + write
+    torch.cuda.synchronize()
+    print(json.dumps({"kernel_probe": True, "rate": rate, "reps": reps,
+                      "decode_blocks": 128 * 128 * (P // 4), "encode_blocks": 128 * 128 * (S // 4),
+                      "stencil_cells": 512 * 512 * P, "ref_copy_bytes": 256 << 20}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -159,6 +186,8 @@ def main():
     ap.add_argument("--error", choices=["none", "sampled", "full"], default="sampled",
                     help="FP64 oracle reference over the full grid or at 16 sample cells")
     ap.add_argument("--extra-rates", default="8,12")
+    ap.add_argument("--kernels", action="store_true",
+                    help="launch each hot kernel at slab shape (for rocprofv3), then exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU; the multi-GPU z-sharding is a design "
@@ -171,6 +200,9 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
     oc.lib()
+    if args.kernels:
+        kernel_probe(args.rate)
+        return
     t0 = time.perf_counter()
     u0 = inputs.grf_field(SHAPE, seed=2)
     log("input ready in %.1f s" % (time.perf_counter() - t0))

@@ -182,6 +182,11 @@ int oc_debug_fail_after(oc_handle *h, int64_t n);
  * write-back); 3 swap op i with the next op of the same stream. */
 int64_t oc_debug_check_plan(const oc_grid *g, const oc_stencil *st, const oc_config *cfg,
                             int64_t sweeps, int32_t mutate, int64_t i);
+/* Writes a text listing of that operation list (one op per line) into buf
+ * (truncated to len-1 bytes, NUL-terminated); returns the bytes the full
+ * listing needs, or a negative OC_ERR_*. */
+int64_t oc_debug_plan_dump(const oc_grid *g, const oc_stencil *st, const oc_config *cfg,
+                           int64_t sweeps, char *buf, size_t len);
 /* Operations in that list; *n_waits receives the number of stream waits. */
 int64_t oc_debug_plan_ops(const oc_grid *g, const oc_stencil *st, const oc_config *cfg,
                           int64_t sweeps, int64_t *n_waits);

@@ -572,6 +572,23 @@ int64_t oc_debug_plan_ops(const oc_grid *g, const oc_stencil *st, const oc_confi
   return (int64_t)ops.size();
 }
 
+int64_t oc_debug_plan_dump(const oc_grid *g, const oc_stencil *st, const oc_config *cfg,
+                           int64_t sweeps, char *buf, size_t len) {
+  if (!grid_ok(g) || !st || !cfg || sweeps < 1) return OC_ERR_ARG;
+  oc::Plan p;
+  int r = oc::make_plan(plan_input(g, st, cfg), &p);
+  if (r != oc::ST_OK) return r;
+  std::vector<oc::Op> ops;
+  oc::build_ops(p, sweeps, p.in.k, 0, 0, &ops);
+  std::string s = oc::dump_ops(ops);
+  if (buf && len) {
+    size_t n = std::min(len - 1, s.size());
+    std::memcpy(buf, s.data(), n);
+    buf[n] = 0;
+  }
+  return (int64_t)s.size() + 1;
+}
+
 int64_t oc_debug_check_plan(const oc_grid *g, const oc_stencil *st, const oc_config *cfg,
                             int64_t sweeps, int32_t mutate, int64_t i) {
   if (!grid_ok(g) || !st || !cfg || sweeps < 1) return OC_ERR_ARG;

@@ -459,6 +459,23 @@ void build_ops(const Plan &p, int64_t sweeps, int steps_last, int src, int64_t s
   B.push(B.blank(OP_SYNC, -1));
 }
 
+std::string dump_ops(const std::vector<Op> &ops) {
+  static const char *names[] = {"H2D", "D2H", "DEC", "ENC", "STAR7", "WAVE", "REC", "WAIT", "SYNC"};
+  std::string out;
+  char line[256];
+  for (size_t i = 0; i < ops.size(); i++) {
+    const Op &o = ops[i];
+    if (o.type == OP_REC || o.type == OP_WAIT)
+      snprintf(line, sizeof line, "%zu s%d %s ev=%d\n", i, o.stream, names[o.type], o.ev);
+    else
+      snprintf(line, sizeof line, "%zu s%d %s sweep=%d slab=%d src=%lld dst=%lld host=%d off=%lld bytes=%lld z=[%lld,%lld)\n",
+               i, o.stream, names[o.type], o.sweep, o.slab, (long long)o.dev_src, (long long)o.dev_dst,
+               o.host_id, (long long)o.host_off, (long long)o.bytes, (long long)o.z_lo, (long long)o.z_hi);
+    out += line;
+  }
+  return out;
+}
+
 // ---------------------------------------------------------------------------
 // happens-before checker
 // ---------------------------------------------------------------------------

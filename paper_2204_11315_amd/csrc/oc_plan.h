@@ -126,6 +126,9 @@ struct EventIds {
 void build_ops(const Plan &p, int64_t sweeps, int steps_last, int src, int64_t step0,
                std::vector<Op> *ops);
 
+// Human-readable listing of an operation list (one op per line).
+std::string dump_ops(const std::vector<Op> &ops);
+
 // Happens-before checker: number of pairs of conflicting accesses that are not
 // ordered by stream order, event record/wait or host sync.  `why` (optional)
 // receives a description of the first one.

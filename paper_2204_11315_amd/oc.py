@@ -90,6 +90,7 @@ _SIGS = {
     "oc_set_timing": (ctypes.c_int, [_P, _I32]),
     "oc_debug_check_plan": (_I64, [_P, _P, _P, _I64, _I32, _I64]),
     "oc_debug_plan_ops": (_I64, [_P, _P, _P, _I64, _P]),
+    "oc_debug_plan_dump": (_I64, [_P, _P, _P, _I64, ctypes.c_char_p, _SZ]),
 }
 EXPORTED = tuple(_SIGS)
 
@@ -188,6 +189,20 @@ def plan_ops(shape, stencil: Stencil, k: int, slab_planes: int, rate: int, sweep
     nw = ctypes.c_int64(0)
     n = int(lib().oc_debug_plan_ops(_ref(g), _ref(stencil), _ref(cfg), int(sweeps), _ref(nw)))
     return n, int(nw.value)
+
+
+def plan_dump(shape, stencil: Stencil, k: int, slab_planes: int, rate: int, sweeps: int,
+              single_buffer: bool = True, budget: int = 0, ring_slots: int = 0,
+              prefetch: int = 0) -> str:
+    """Text listing of the operation list the executor would issue."""
+    g = make_grid(shape)
+    cfg = plan_config(k, slab_planes, rate, single_buffer, budget, ring_slots, prefetch)
+    n = int(lib().oc_debug_plan_dump(_ref(g), _ref(stencil), _ref(cfg), int(sweeps), None, 0))
+    if n < 0:
+        raise OCError(n, "oc_debug_plan_dump", status_str(n))
+    buf = ctypes.create_string_buffer(n)
+    lib().oc_debug_plan_dump(_ref(g), _ref(stencil), _ref(cfg), int(sweeps), buf, n)
+    return buf.value.decode()
 
 
 def codec_bytes(shape, rate: int) -> int:
