@@ -160,12 +160,41 @@ int oc_codec_decompress(const void *d_in, int64_t nx, int64_t ny, int64_t nz, in
  * the last call met a non-finite value (and clears the flag), else OC_OK. */
 int oc_codec_status(oc_stream stream);
 
+/* ---- adjoint (differentiation of the 7-point path, raw handles) ---------- */
+/* For u_T = A(c0)^T u_0 (A = the 7-point update with per-cell c0 when the
+ * stencil has a c0 field), the gradients of a loss L(u_T) given dL/du_T:
+ *   lambda_T = dL/du_T, lambda_n = A^T lambda_{n+1}  (A^T: -/+ coefficients
+ *   swapped, the diagonal c0(x) kept), dL/du_0 = lambda_0,
+ *   dL/dc0(x) = sum_n lambda_{n+1}(x) u_n(x).
+ * oc_forward_ckpt advances the loaded state like oc_run(steps) and keeps the
+ * states u_0, u_m, u_2m, ... (m = ckpt_every) in host_work, u_0 exact and the
+ * others as codes at ckpt_rate_bits (0 = raw).  oc_adjoint then runs reverse
+ * sweeps, one per checkpoint segment, newest first: each slab reloads its
+ * checkpoint, recomputes the segment's states in device memory and steps
+ * lambda back while accumulating dL/dc0.  It may be called again with another
+ * dL/du_T.  Both need a handle with rate_bits = 0.  host_work must hold
+ * oc_adjoint_host_bytes() bytes (pinned for overlap) and outlive the calls. */
+size_t oc_adjoint_host_bytes(const oc_handle *h, int64_t steps, int32_t ckpt_every,
+                             int32_t ckpt_rate_bits);
+int oc_forward_ckpt(oc_handle *h, int64_t steps, int32_t ckpt_every, int32_t ckpt_rate_bits,
+                    void *host_work, size_t host_work_bytes);
+/* gT, g_u0, g_c0: host FP32 [nz][ny][nx]; g_c0 may be NULL. */
+int oc_adjoint(oc_handle *h, const float *gT, float *g_u0, float *g_c0);
+
 /* ---- single-field device kernels (in-core building blocks) -------------- */
 /* out = A^steps in on the device, ping-ponging through `tmp` (same size);
  * result lands in `out`.  c0f (nullable) is a device c0 field. */
 int oc_star7_incore(const float *d_in, float *d_out, float *d_tmp, int64_t nx, int64_t ny,
                     int64_t nz, const float *c, const float *d_c0f, int64_t steps,
                     oc_stream stream);
+
+/* Advances (p^{n0-1}, p^{n0}) = (d_prev, d_cur) by `steps` 25-point leapfrog
+ * steps on the device (the Sec. 6 acoustic-wave update; WAVE25 stencil, Ricker
+ * source of st).  On return d_cur holds p^{n0+steps}, d_prev p^{n0+steps-1};
+ * d_tmp (same size) is needed when steps is odd, else may be NULL. */
+int oc_wave25_incore(float *d_prev, float *d_cur, const float *d_vel, float *d_tmp, int64_t nx,
+                     int64_t ny, int64_t nz, const oc_stencil *st, int64_t n0, int64_t steps,
+                     oc_stream stream);
 
 const char *oc_status_str(int status);
 
@@ -187,6 +216,12 @@ int64_t oc_debug_check_plan(const oc_grid *g, const oc_stencil *st, const oc_con
  * listing needs, or a negative OC_ERR_*. */
 int64_t oc_debug_plan_dump(const oc_grid *g, const oc_stencil *st, const oc_config *cfg,
                            int64_t sweeps, char *buf, size_t len);
+/* The same checker over the reverse-sweep operation list of the adjoint for
+ * `steps` steps with checkpoints every ckpt_every (mutate 0 or 1 as above).
+ * With mutate = 0 and i = -1 it returns the number of waits instead. */
+int64_t oc_debug_check_adjoint(const oc_grid *g, const oc_stencil *st, const oc_config *cfg,
+                               int64_t steps, int32_t ckpt_every, int32_t ckpt_rate_bits,
+                               int32_t mutate, int64_t i);
 /* Operations in that list; *n_waits receives the number of stream waits. */
 int64_t oc_debug_plan_ops(const oc_grid *g, const oc_stencil *st, const oc_config *cfg,
                           int64_t sweeps, int64_t *n_waits);

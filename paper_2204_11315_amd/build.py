@@ -15,7 +15,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liboc.so")
-SOURCES = ["oc_plan.cpp", "oc_api.cpp", "kern_codec.hip", "kern_star7.hip", "kern_copy.hip"]
+SOURCES = ["oc_plan.cpp", "oc_api.cpp", "kern_codec.hip", "kern_star7.hip", "kern_copy.hip",
+           "kern_wave25.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -248,14 +248,32 @@ struct BitReader {
   }
 };
 
+// ---- slot staging through LDS ----------------------------------------------------
+// A workgroup's slots are one contiguous range of global memory; they move
+// between global memory and LDS with coalesced dword accesses, and each lane
+// reads / writes its own slot in LDS at a padded stride of NW + 1 dwords so
+// that the per-lane sequential accesses spread over the LDS banks.
+__device__ __forceinline__ uint32_t div_magic(int nw) {  // floor(2^32 / nw) + 1
+  return (uint32_t)(0xFFFFFFFFu / (uint32_t)nw) + 1u;
+}
+__device__ __forceinline__ uint32_t lds_index(uint32_t i, int nw, uint32_t magic) {
+  const uint32_t slot = __umulhi(i, magic);   // exact floor(i / nw) for i * nw < 2^32
+  return i + slot;                            // slot * (nw + 1) + (i - slot * nw)
+}
+
+extern __shared__ uint32_t lds_slots[];
+
 // ---- encoder ------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_encode(const float *__restrict__ in, int64_t nx, int64_t ny,
                                                 int64_t nbx, int64_t nby, int64_t nblocks, int R,
                                                 uint32_t *__restrict__ out) {
   const int NW = 2 * R;        // dwords per slot
   const int BITS = 64 * R;     // slot bits
-  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= nblocks) return;
+  const int64_t b0 = (int64_t)blockIdx.x * blockDim.x;
+  const int64_t b = b0 + threadIdx.x;
+  const int nslots = (int)min<int64_t>(blockDim.x, nblocks - b0);
+  uint32_t *my = lds_slots + threadIdx.x * (NW + 1);
+  if (b < nblocks) {
   const int64_t bx = b % nbx;
   const int64_t by = (b / nbx) % nby;
   const int64_t bz = b / (nbx * nby);
@@ -304,7 +322,7 @@ __global__ __launch_bounds__(256) void k_encode(const float *__restrict__ in, in
 
   BitWriter w;
   w.NW = NW;
-  w.slot = out + b * NW;
+  w.slot = my;
   w.acc = 0;
   w.nacc = 0;
   w.widx = 0;
@@ -329,6 +347,13 @@ __global__ __launch_bounds__(256) void k_encode(const float *__restrict__ in, in
     }
   }
   w.finish();
+  }
+  __syncthreads();
+  // coalesced copy of the workgroup's slots to global memory
+  const uint32_t magic = div_magic(NW);
+  uint32_t *dst = out + b0 * NW;
+  const uint32_t total = (uint32_t)(nslots * NW);
+  for (uint32_t i = threadIdx.x; i < total; i += blockDim.x) dst[i] = lds_slots[lds_index(i, NW, magic)];
 }
 
 // ---- decoder ------------------------------------------------------------------
@@ -337,14 +362,24 @@ __global__ __launch_bounds__(256) void k_decode(const uint32_t *__restrict__ in,
                                                 float *__restrict__ out) {
   const int NW = 2 * R;
   const int BITS = 64 * R;
-  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t b0 = (int64_t)blockIdx.x * blockDim.x;
+  const int64_t b = b0 + threadIdx.x;
+  {
+    // coalesced copy of the workgroup's slots into LDS
+    const int nslots = (int)min<int64_t>(blockDim.x, nblocks - b0);
+    const uint32_t magic = div_magic(NW);
+    const uint32_t *src = in + b0 * NW;
+    const uint32_t total = (uint32_t)(nslots * NW);
+    for (uint32_t i = threadIdx.x; i < total; i += blockDim.x) lds_slots[lds_index(i, NW, magic)] = src[i];
+  }
+  __syncthreads();
   if (b >= nblocks) return;
   const int64_t bx = b % nbx;
   const int64_t by = (b / nbx) % nby;
   const int64_t bz = b / (nbx * nby);
 
   BitReader r;
-  r.init(in + b * NW, NW);
+  r.init(lds_slots + threadIdx.x * (NW + 1), NW);
   const int Eb = (int)r.get(8);
   uint32_t lo[32], hi[32];
   int n = 0;
@@ -391,6 +426,11 @@ __global__ __launch_bounds__(256) void k_decode(const uint32_t *__restrict__ in,
     }
 }
 
+// 256 lanes per workgroup (128 above 16 bits/value, to keep the slot staging
+// within 34 KiB of LDS per workgroup)
+int codec_threads(int rate) { return rate > 16 ? 128 : 256; }
+size_t codec_lds_bytes(int rate, int threads) { return (size_t)threads * (size_t)(2 * rate + 1) * 4u; }
+
 }  // namespace
 
 namespace oc {
@@ -400,9 +440,10 @@ hipError_t launch_encode(const float *d_in, int64_t nx, int64_t ny, int64_t nlay
   if (rate < 1 || rate > 32) return hipErrorInvalidValue;
   const int64_t nbx = nx / 4, nby = ny / 4, nb = nbx * nby * nlayers;
   if (nb <= 0) return hipSuccess;
-  dim3 grid((unsigned)((nb + 255) / 256));
-  hipLaunchKernelGGL(k_encode, grid, dim3(256), 0, s, d_in, nx, ny, nbx, nby, nb, rate,
-                     (uint32_t *)d_out);
+  const int threads = codec_threads(rate);
+  dim3 grid((unsigned)((nb + threads - 1) / threads));
+  hipLaunchKernelGGL(k_encode, grid, dim3(threads), codec_lds_bytes(rate, threads), s, d_in, nx, ny,
+                     nbx, nby, nb, rate, (uint32_t *)d_out);
   return hipGetLastError();
 }
 
@@ -411,9 +452,10 @@ hipError_t launch_decode(const void *d_in, int64_t nx, int64_t ny, int64_t nlaye
   if (rate < 1 || rate > 32) return hipErrorInvalidValue;
   const int64_t nbx = nx / 4, nby = ny / 4, nb = nbx * nby * nlayers;
   if (nb <= 0) return hipSuccess;
-  dim3 grid((unsigned)((nb + 255) / 256));
-  hipLaunchKernelGGL(k_decode, grid, dim3(256), 0, s, (const uint32_t *)d_in, nx, ny, nbx, nby, nb,
-                     rate, d_out);
+  const int threads = codec_threads(rate);
+  dim3 grid((unsigned)((nb + threads - 1) / threads));
+  hipLaunchKernelGGL(k_decode, grid, dim3(threads), codec_lds_bytes(rate, threads), s,
+                     (const uint32_t *)d_in, nx, ny, nbx, nby, nb, rate, d_out);
   return hipGetLastError();
 }
 

@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -23,10 +24,16 @@ struct oc_handle {
   hipStream_t s[3];
   std::vector<hipEvent_t> ev;
   uint8_t *arena = nullptr;
-  uint8_t *host[3] = {nullptr, nullptr, nullptr};  // level 0, level 1, aux
+  // host stores: level 0, level 1, aux, checkpoint store, gradient store
+  uint8_t *host[oc::kHostStores] = {};
   // device view of each host store when it is pinned and mapped (copy-backs
   // then run as a small kernel), else nullptr (copy-backs use hipMemcpyAsync)
-  uint8_t *host_dev[3] = {nullptr, nullptr, nullptr};
+  uint8_t *host_dev[oc::kHostStores] = {};
+  // adjoint: checkpoints of the last oc_forward_ckpt
+  bool ckpt_valid = false;
+  oc::AdjPlan adj;
+  uint8_t *adj_work = nullptr;
+  size_t adj_off[4] = {};   // checkpoint store, lambda A, lambda B, gradient store
   int cur = 0;            // host level holding the current state
   bool loaded = false;
   bool broken = false;
@@ -70,6 +77,15 @@ struct Exec {
     return true;
   }
 };
+
+// Ricker wavelet (1 - 2 a) exp(-a), a = (pi f (t - t0))^2: the source term's
+// time function, one scalar per step.
+double ricker(double t, double f, double t0) {
+  const double pi = 3.14159265358979323846;
+  double a = pi * f * (t - t0);
+  a *= a;
+  return (1.0 - 2.0 * a) * std::exp(-a);
+}
 
 oc::Star7Coef coef_of(const oc_stencil &s) {
   return oc::Star7Coef{s.c[0], s.c[1], s.c[2], s.c[3], s.c[4], s.c[5], s.c[6]};
@@ -119,9 +135,8 @@ TimedKind timed_kind(const oc::Op &o) {
   }
 }
 
-int issue(oc_handle *h, const std::vector<oc::Op> &ops) {
+int issue(oc_handle *h, const std::vector<oc::Op> &ops, const oc::Plan &p) {
   Exec x{h};
-  const oc::Plan &p = h->plan;
   const oc::Star7Coef c = coef_of(h->st);
   uint64_t h2d = 0, d2h = 0, cells = 0, bdec = 0, benc = 0;
   const uint64_t blocks_per_layer = (uint64_t)(p.in.nx / 4) * (uint64_t)(p.in.ny / 4);
@@ -173,15 +188,28 @@ int issue(oc_handle *h, const std::vector<oc::Op> &ops) {
                                p.in.rate, h->arena + o.dev_dst, s));
         benc += blocks_per_layer * (uint64_t)o.z_hi;
         break;
-      case oc::OP_STAR7:
+      case oc::OP_STAR7: {
+        // A^T: the neighbour coefficients swap direction, the diagonal stays
+        const oc::Star7Coef ct{c.c0, c.cpx, c.cmx, c.cpy, c.cmy, c.cpz, c.cmz};
         x.ok(oc::launch_star7((const float *)(h->arena + o.dev_src), (float *)(h->arena + o.dev_dst),
                               o.dev_src2 >= 0 ? (const float *)(h->arena + o.dev_src2) : nullptr,
-                              p.in.nx, p.in.ny, o.z_lo, o.z_hi, o.gz0, p.in.nz, c, s));
+                              p.in.nx, p.in.ny, o.z_lo, o.z_hi, o.gz0, p.in.nz,
+                              o.transpose ? ct : c, s));
         cells += (uint64_t)(o.z_hi - o.z_lo) * (uint64_t)p.in.nx * (uint64_t)p.in.ny;
         break;
-      case oc::OP_WAVE:
-        x.st = OC_ERR_UNSUPPORTED;
+      }
+      case oc::OP_AXPY:
+        x.ok(oc::launch_axpy_prod((float *)(h->arena + o.dev_dst), (const float *)(h->arena + o.dev_src),
+                                  (const float *)(h->arena + o.dev_src2), (size_t)o.bytes / 4u, s));
         break;
+      case oc::OP_WAVE: {
+        const float amp = (float)ricker((double)o.step * h->st.dt, h->st.f_peak, h->st.t0);
+        x.ok(oc::launch_wave25((const float *)(h->arena + o.dev_src), (float *)(h->arena + o.dev_dst),
+                               (const float *)(h->arena + o.dev_src2), p.in.nx, p.in.ny, o.z_lo,
+                               o.z_hi, o.gz0, p.in.nz, h->st.dt / h->st.h, h->st.src, amp, s));
+        cells += (uint64_t)(o.z_hi - o.z_lo) * (uint64_t)p.in.nx * (uint64_t)p.in.ny;
+        break;
+      }
       case oc::OP_REC:
         x.ok(hipEventRecord(h->ev[o.ev], s));
         break;
@@ -260,33 +288,41 @@ bool grid_ok(const oc_grid *g) {
          g->nz <= (1 << 30);
 }
 
-// Encodes (or copies) `planes` planes of host field `src` into host store
-// `dst` at plane z0 via the device working buffers; synchronous on stream 0.
-int load_field(oc_handle *h, const float *src, uint8_t *dst, bool coded) {
+// Encodes a whole host FP32 field into host codes at `rate`, in chunks of
+// `chunk` planes through the device buffers `work` (raw) and `stage` (codes);
+// synchronous on stream 0.
+int encode_field(oc_handle *h, const float *src, uint8_t *dst, int rate, int64_t chunk,
+                 uint8_t *work, uint8_t *stage) {
   const oc::Plan &p = h->plan;
   Exec x{h};
   hipStream_t s = h->s[0];
   const size_t pb = p.plane_bytes;
-  if (!coded) {
-    // raw: a plain host copy of the whole field
-    std::memcpy(dst, src, pb * (size_t)p.in.nz);
-    return OC_OK;
-  }
-  const int64_t chunk = std::max<int64_t>(4, p.P / 4 * 4);
-  uint8_t *work = h->arena + p.off_work[0][0];
-  uint8_t *stage = h->arena + p.off_stage[0];
+  const size_t layer = oc::coded_layer_bytes(p.in.nx, p.in.ny, rate);
   for (int64_t z = 0; z < p.in.nz; z += chunk) {
     int64_t n = std::min<int64_t>(chunk, p.in.nz - z);
     x.ok(hipMemcpyAsync(work, (const uint8_t *)src + (size_t)z * pb, (size_t)n * pb,
                         hipMemcpyHostToDevice, s));
-    x.ok(oc::launch_encode((const float *)work, p.in.nx, p.in.ny, n / 4, p.in.rate, stage, s));
-    x.ok(hipMemcpyAsync(dst + (size_t)(z / 4) * p.layer_bytes, stage, (size_t)(n / 4) * p.layer_bytes,
+    x.ok(oc::launch_encode((const float *)work, p.in.nx, p.in.ny, n / 4, rate, stage, s));
+    x.ok(hipMemcpyAsync(dst + (size_t)(z / 4) * layer, stage, (size_t)(n / 4) * layer,
                         hipMemcpyDeviceToHost, s));
     x.ok(hipStreamSynchronize(s));
     if (x.st) break;
   }
   if (x.st) return x.st;
   return codec_check_and_clear();
+}
+
+// Loads a host FP32 field into host store `dst`: a copy, or codes at the
+// plan's rate made on the GPU through the plan's first working and staging
+// buffers.
+int load_field(oc_handle *h, const float *src, uint8_t *dst, bool coded) {
+  const oc::Plan &p = h->plan;
+  if (!coded) {
+    std::memcpy(dst, src, p.plane_bytes * (size_t)p.in.nz);
+    return OC_OK;
+  }
+  return encode_field(h, src, dst, p.in.rate, std::max<int64_t>(4, p.P / 4 * 4),
+                      h->arena + p.off_work[0][0], h->arena + p.off_stage[0]);
 }
 
 int store_field(oc_handle *h, const uint8_t *src, float *dst, bool coded) {
@@ -401,6 +437,36 @@ int oc_star7_incore(const float *d_in, float *d_out, float *d_tmp, int64_t nx, i
   return OC_OK;
 }
 
+int oc_wave25_incore(float *d_prev, float *d_cur, const float *d_vel, float *d_tmp, int64_t nx,
+                     int64_t ny, int64_t nz, const oc_stencil *st, int64_t n0, int64_t steps,
+                     oc_stream stream) {
+  if (!d_prev || !d_cur || !d_vel || !st || nx <= 0 || ny <= 0 || nz <= 0 || steps < 0 || n0 < 0)
+    return OC_ERR_ARG;
+  if (st->kind != OC_WAVE25 || !(st->h > 0.f && st->dt > 0.f)) return OC_ERR_ARG;
+  if (nx > (1 << 30) || ny > (1 << 30) || nz > (1 << 30)) return OC_ERR_ARG;
+  if ((steps & 1) && !d_tmp) return OC_ERR_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = hipSuccess;
+  float *a = d_prev, *b = d_cur;   // a holds p^{n-1}, b holds p^n
+  for (int64_t i = 0; i < steps && e == hipSuccess; i++) {
+    const float amp = (float)ricker((double)(n0 + i) * st->dt, st->f_peak, st->t0);
+    e = oc::launch_wave25(b, a, d_vel, nx, ny, 0, nz, 0, nz, st->dt / st->h, st->src, amp, s);
+    std::swap(a, b);
+  }
+  if (e == hipSuccess && (steps & 1)) {
+    // the newest level is in d_prev: swap the two buffers' contents
+    const size_t bytes = (size_t)(nx * ny * nz) * 4u;
+    e = hipMemcpyAsync(d_tmp, d_prev, bytes, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_prev, d_cur, bytes, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_cur, d_tmp, bytes, hipMemcpyDeviceToDevice, s);
+  }
+  if (e != hipSuccess) {
+    g_last_hip = e;
+    return OC_ERR_HIP;
+  }
+  return OC_OK;
+}
+
 size_t oc_host_level_bytes(const oc_grid *g, const oc_stencil *st, int32_t rate_bits) {
   if (!grid_ok(g) || !st) return 0;
   oc::Plan p;
@@ -428,7 +494,7 @@ int oc_create(const oc_grid *g, const oc_stencil *st, const oc_config *cfg, oc_h
   if (!grid_ok(g) || !st || !cfg || !out) return OC_ERR_ARG;
   *out = nullptr;
   if (st->kind != OC_STAR7 && st->kind != OC_WAVE25) return OC_ERR_ARG;
-  if (st->kind == OC_WAVE25) return OC_ERR_UNSUPPORTED;
+  if (st->kind == OC_WAVE25 && !(st->h > 0.f && st->dt > 0.f)) return OC_ERR_ARG;
   oc::Plan p;
   int r = oc::make_plan(plan_input(g, st, cfg), &p);
   if (r != oc::ST_OK) return r;
@@ -452,6 +518,7 @@ int oc_create(const oc_grid *g, const oc_stencil *st, const oc_config *cfg, oc_h
   h->host[1] = (uint8_t *)cfg->host_level[1];
   h->host[2] = (uint8_t *)cfg->host_aux;
   for (int i = 0; i < 3; i++) h->host_dev[i] = mapped_host(h->host[i]);
+  h->ckpt_valid = false;
   oc::EventIds ids{(int)p.slabs.size()};
   h->ev.assign((size_t)ids.count(), nullptr);
   for (auto &e : h->ev) {
@@ -473,13 +540,16 @@ int oc_create(const oc_grid *g, const oc_stencil *st, const oc_config *cfg, oc_h
 }
 
 int oc_load(oc_handle *h, const float *u, const float *aux, const float *vel) {
-  (void)vel;
   if (!h || !u) return OC_ERR_ARG;
   if (h->broken) return OC_ERR_STATE;
   const oc::Plan &p = h->plan;
+  const bool wave = p.in.kind == oc::KIND_WAVE25;
   if (p.in.c0_field && !aux) return OC_ERR_ARG;
+  if (wave && (!aux || !vel)) return OC_ERR_ARG;
   h->cur = 0;
   int r = load_field(h, u, h->host[0], p.coded);
+  if (!r && wave) r = load_field(h, aux, h->host[0] + p.host_field_bytes, p.coded);
+  if (!r && wave) r = load_field(h, vel, h->host[2], p.ro_coded);
   if (r) {
     h->broken = r == OC_ERR_HIP;
     return r;
@@ -498,13 +568,14 @@ int oc_run(oc_handle *h, int64_t steps) {
   const int64_t k = p.in.k;
   const int64_t sweeps = (steps + k - 1) / k;
   const int steps_last = (int)(steps - (sweeps - 1) * k);
-  int64_t key[4] = {sweeps, steps_last, h->cur, h->time_index};
+  const int64_t t_key = p.in.kind == oc::KIND_WAVE25 ? h->time_index : 0;
+  int64_t key[4] = {sweeps, steps_last, h->cur, t_key};
   if (std::memcmp(key, h->ops_key, sizeof key) != 0) {
     oc::build_ops(p, sweeps, steps_last, h->cur, h->time_index, &h->ops);
     std::memcpy(h->ops_key, key, sizeof key);
   }
   auto t0 = std::chrono::steady_clock::now();
-  int r = issue(h, h->ops);
+  int r = issue(h, h->ops, h->plan);
   auto t1 = std::chrono::steady_clock::now();
   if (r) return r;
   int cr = p.coded ? codec_check_and_clear() : OC_OK;
@@ -520,10 +591,162 @@ int oc_run(oc_handle *h, int64_t steps) {
 }
 
 int oc_store(oc_handle *h, float *u, float *aux) {
-  (void)aux;
-  if (!h || !u) return OC_ERR_ARG;
+  if (!h || (!u && !aux)) return OC_ERR_ARG;
   if (h->broken || !h->loaded) return OC_ERR_STATE;
-  return store_field(h, h->host[h->cur], u, h->plan.coded);
+  const oc::Plan &p = h->plan;
+  int r = OC_OK;
+  if (u) r = store_field(h, h->host[h->cur], u, p.coded);
+  if (!r && aux && p.in.kind == oc::KIND_WAVE25)
+    r = store_field(h, h->host[h->cur] + p.host_field_bytes, aux, p.coded);
+  return r;
+}
+
+// ---- adjoint ------------------------------------------------------------
+namespace {
+
+size_t align4k(size_t x) { return (x + 4095) & ~(size_t)4095; }
+
+int adj_plan_for(const oc_handle *h, int64_t steps, int32_t every, int32_t rate, oc::AdjPlan *a) {
+  if (h->plan.in.kind != oc::KIND_STAR7) return OC_ERR_UNSUPPORTED;
+  if (h->plan.coded) return OC_ERR_UNSUPPORTED;     // the forward of the adjoint runs raw
+  if (steps < 1 || every < 1 || rate < 0 || rate > 32) return OC_ERR_ARG;
+  oc::PlanInput in = h->plan.in;
+  in.rate = rate;
+  in.slab_planes = 0;
+  in.budget = h->cfg.dev_budget;
+  int r = oc::make_adj_plan(in, every, steps, a);
+  return r;
+}
+
+size_t adj_work_bytes(const oc::AdjPlan &a, size_t *off) {
+  size_t o = 0;
+  off[0] = o;
+  o = align4k(o + a.ckpt_bytes);
+  for (int i = 1; i < 4; i++) {
+    off[i] = o;
+    o = align4k(o + a.field_bytes);
+  }
+  return o;
+}
+
+}  // namespace
+
+size_t oc_adjoint_host_bytes(const oc_handle *h, int64_t steps, int32_t ckpt_every,
+                             int32_t ckpt_rate_bits) {
+  if (!h) return 0;
+  oc::AdjPlan a;
+  if (adj_plan_for(h, steps, ckpt_every, ckpt_rate_bits, &a) != OC_OK) return 0;
+  size_t off[4];
+  return adj_work_bytes(a, off);
+}
+
+int oc_forward_ckpt(oc_handle *h, int64_t steps, int32_t ckpt_every, int32_t ckpt_rate_bits,
+                    void *host_work, size_t host_work_bytes) {
+  if (!h || !host_work) return OC_ERR_ARG;
+  if (h->broken || !h->loaded) return OC_ERR_STATE;
+  oc::AdjPlan a;
+  int r = adj_plan_for(h, steps, ckpt_every, ckpt_rate_bits, &a);
+  if (r != OC_OK) return r;
+  size_t off[4];
+  if (adj_work_bytes(a, off) > host_work_bytes) return OC_ERR_BUDGET;
+  h->ckpt_valid = false;
+  uint8_t *work = (uint8_t *)host_work;
+  for (int sg = 0; sg < a.nseg; sg++) {
+    uint8_t *dst = work + off[0] + a.ckpt_off[(size_t)sg];
+    const float *cur = (const float *)h->host[h->cur];
+    if (a.ckpt_coded[(size_t)sg]) {
+      // codes made on the GPU through the adjoint plan's first slot buffers
+      r = encode_field(h, cur, dst, a.ckpt_rate, std::max<int64_t>(4, a.g.P / 4 * 4),
+                       h->arena + a.off_buf[0][oc::A_U0], h->arena + a.off_cstage[0]);
+    } else {
+      std::memcpy(dst, cur, a.field_bytes);
+    }
+    if (r) {
+      h->broken = r == OC_ERR_HIP;
+      return r;
+    }
+    const int64_t len = std::min<int64_t>(ckpt_every, steps - (int64_t)sg * ckpt_every);
+    r = oc_run(h, len);
+    if (r) return r;
+  }
+  h->adj = a;
+  h->adj_work = work;
+  std::memcpy(h->adj_off, off, sizeof off);
+  h->ckpt_valid = true;
+  return OC_OK;
+}
+
+int oc_adjoint(oc_handle *h, const float *gT, float *g_u0, float *g_c0) {
+  if (!h || !gT || !g_u0) return OC_ERR_ARG;
+  if (h->broken) return OC_ERR_STATE;
+  if (!h->ckpt_valid) return OC_ERR_STATE;
+  const oc::AdjPlan &a = h->adj;
+  uint8_t *w = h->adj_work;
+  uint8_t *lam0 = w + h->adj_off[1], *lam1 = w + h->adj_off[2], *grad = w + h->adj_off[3];
+  std::memcpy(lam0, gT, a.field_bytes);
+  std::memset(grad, 0, a.field_bytes);
+  // map the host stores of the reverse sweeps, run them, restore the handle's
+  uint8_t *saved[oc::kHostStores], *saved_dev[oc::kHostStores];
+  std::memcpy(saved, h->host, sizeof saved);
+  std::memcpy(saved_dev, h->host_dev, sizeof saved_dev);
+  h->host[0] = lam0;
+  h->host[1] = lam1;
+  h->host[oc::HOST_CKPT] = w + h->adj_off[0];
+  h->host[oc::HOST_GRAD] = grad;
+  for (int i : {0, 1, (int)oc::HOST_CKPT, (int)oc::HOST_GRAD}) h->host_dev[i] = mapped_host(h->host[i]);
+  std::vector<oc::Op> ops;
+  oc::build_adjoint_ops(a, 0, &ops);
+  auto t0 = std::chrono::steady_clock::now();
+  int r = issue(h, ops, a.g);
+  auto t1 = std::chrono::steady_clock::now();
+  std::memcpy(h->host, saved, sizeof saved);
+  std::memcpy(h->host_dev, saved_dev, sizeof saved_dev);
+  if (r) return r;
+  if (a.ckpt_rate > 0) {
+    int cr = codec_check_and_clear();
+    if (cr) return cr;
+  }
+  h->stats.wall_s = std::chrono::duration<double>(t1 - t0).count();
+  h->stats.n_ops = ops.size();
+  std::memcpy(g_u0, (a.nseg & 1) ? lam1 : lam0, a.field_bytes);
+  if (g_c0) std::memcpy(g_c0, grad, a.field_bytes);
+  return OC_OK;
+}
+
+int64_t oc_debug_check_adjoint(const oc_grid *g, const oc_stencil *st, const oc_config *cfg,
+                               int64_t steps, int32_t ckpt_every, int32_t ckpt_rate_bits,
+                               int32_t mutate, int64_t i) {
+  if (!grid_ok(g) || !st || !cfg) return OC_ERR_ARG;
+  oc::PlanInput in = plan_input(g, st, cfg);
+  in.rate = ckpt_rate_bits;
+  in.slab_planes = cfg->slab_planes;
+  oc::AdjPlan a;
+  int r = oc::make_adj_plan(in, ckpt_every, steps, &a);
+  if (r != oc::ST_OK) return r;
+  std::vector<oc::Op> ops;
+  oc::build_adjoint_ops(a, 0, &ops);
+  if (mutate == 1) {
+    int64_t seen = 0;
+    bool dropped = false;
+    for (size_t j = 0; j < ops.size(); j++)
+      if (ops[j].type == oc::OP_WAIT && seen++ == i) {
+        ops.erase(ops.begin() + (ptrdiff_t)j);
+        dropped = true;
+        break;
+      }
+    if (!dropped) return OC_ERR_ARG;
+  } else if (mutate != 0) {
+    return OC_ERR_ARG;
+  }
+  std::string why;
+  int64_t bad = oc::check_ops(a.g, ops, &why);
+  if (bad && getenv("OC_CHECK_VERBOSE")) fprintf(stderr, "oc adjoint check: %s\n", why.c_str());
+  if (mutate == 0 && i == -1) {
+    int64_t w = 0;
+    for (const auto &o : ops) w += o.type == oc::OP_WAIT;
+    return w;   // number of waits (for the mutation sweep)
+  }
+  return bad;
 }
 
 int oc_stats_get(const oc_handle *h, oc_stats *s) {

@@ -26,6 +26,16 @@ hipError_t launch_star7(const float *in, float *out, const float *c0f, int64_t n
                         int64_t z_lo, int64_t z_hi, int64_t gz0, int64_t nz, const Star7Coef &c,
                         hipStream_t s);
 
+// g[i] += a[i] * b[i] for i < n.
+hipError_t launch_axpy_prod(float *g, const float *a, const float *b, size_t n, hipStream_t s);
+
+// One 25-point leapfrog step on a slab buffer (local plane 0 = global gz0):
+// pnm1 <- 2 pn - pnm1 + (v dt/h)^2 L8(pn) on local planes [z_lo, z_hi), plus
+// (v dt/h)^2 * src_amp at global cell src when it lies in that range.
+hipError_t launch_wave25(const float *pn, float *pnm1, const float *vel, int64_t nx, int64_t ny,
+                         int64_t z_lo, int64_t z_hi, int64_t gz0, int64_t nz, float dt_h,
+                         const int64_t *src, float src_amp, hipStream_t s);
+
 // Copies `bytes` from device memory into host memory that the device can
 // address (pinned, mapped); a small grid so that it overlaps other kernels.
 hipError_t launch_copy_to_host(void *dst, const void *src, size_t bytes, hipStream_t s);

@@ -459,6 +459,246 @@ void build_ops(const Plan &p, int64_t sweeps, int steps_last, int src, int64_t s
   B.push(B.blank(OP_SYNC, -1));
 }
 
+// ---------------------------------------------------------------------------
+// adjoint plan and reverse-sweep operation list
+// ---------------------------------------------------------------------------
+int make_adj_plan(const PlanInput &in0, int m, int64_t steps, AdjPlan *out) {
+  if (m < 1 || steps < 1 || in0.kind != KIND_STAR7) return ST_ARG;
+  PlanInput in = in0;
+  in.slots = 2;        // two full working sets: the copy-in of the next slab
+  in.prefetch = 1;     // overlaps the kernels of the current one
+  AdjPlan a;
+  a.m = m;
+  a.steps = steps;
+  a.nseg = (int)((steps + m - 1) / m);
+  a.ckpt_rate = in.rate;
+  Plan &p = a.g;
+  p.in = in;
+  if (in.nx <= 0 || in.ny <= 0 || in.nz <= 0 || in.rate < 0 || in.rate > 32) return ST_ARG;
+  p.r = 1;
+  p.coded = in.rate > 0;
+  if (p.coded && (in.nx % 4 || in.ny % 4 || in.nz % 4 || in.slab_planes % 4)) return ST_SHAPE;
+  p.slots = 2;
+  p.prefetch = 1;
+  p.n_rw = 1;
+  p.plane_bytes = (size_t)in.nx * (size_t)in.ny * 4u;
+  p.layer_bytes = p.coded ? coded_layer_bytes(in.nx, in.ny, in.rate) : 0;
+  p.halo = p.coded ? ((int64_t)m + 3) / 4 * 4 : m;
+  p.n_work_sets = 2;
+  p.n_work_bufs = 7;
+  auto carve_adj = [&](int64_t S) {
+    p.S = S;
+    p.P = S + 2 * p.halo;
+    p.work_bytes = align256((size_t)p.P * p.plane_bytes);
+    p.stage_bytes = p.coded ? align256((size_t)(p.P / 4) * p.layer_bytes) : 0;
+    size_t off = 0;
+    for (int q = 0; q < 2; q++) {
+      for (int b = 0; b < 7; b++) {
+        a.off_buf[q][b] = off;
+        off += p.work_bytes;
+      }
+      a.off_cstage[q] = off;
+      off += p.stage_bytes;
+    }
+    return off;
+  };
+  const int64_t step = p.coded ? 4 : 1;
+  int64_t S = 0;
+  if (in.slab_planes > 0) {
+    S = std::min<int64_t>(in.slab_planes, (in.nz + step - 1) / step * step);
+    if (in.budget && carve_adj(S) > in.budget) return ST_BUDGET;
+  } else {
+    for (int64_t s = (in.nz + step - 1) / step * step; s >= step; s -= step)
+      if (!in.budget || carve_adj(s) <= in.budget) {
+        S = s;
+        break;
+      }
+    if (!S) return ST_BUDGET;
+  }
+  p.arena_bytes = carve_adj(S);
+  for (int64_t z0 = 0; z0 < in.nz; z0 += p.S) {
+    Slab sl;
+    sl.z0 = z0;
+    sl.z1 = std::min<int64_t>(z0 + p.S, in.nz);
+    sl.gz0 = z0 - p.halo;
+    sl.l0 = std::max<int64_t>(0, z0 - p.halo);
+    sl.l1 = std::min<int64_t>(in.nz, sl.z1 + p.halo);
+    sl.planes = (sl.z1 - sl.z0) + 2 * p.halo;
+    p.slabs.push_back(sl);
+  }
+  a.field_bytes = (size_t)in.nx * (size_t)in.ny * (size_t)in.nz * 4u;
+  p.host_field_bytes = a.field_bytes;
+  p.host_level_bytes = a.field_bytes;   // lambda levels and the gradient store: raw fields
+  p.host_aux_bytes = in.c0_field ? a.field_bytes : 0;
+  size_t off = 0;
+  for (int sg = 0; sg < a.nseg; sg++) {
+    a.ckpt_off.push_back(off);
+    const int coded = (p.coded && sg > 0) ? 1 : 0;   // the start state stays exact
+    a.ckpt_coded.push_back(coded);
+    off += coded ? (size_t)(in.nz / 4) * p.layer_bytes : a.field_bytes;
+  }
+  a.ckpt_bytes = off;
+  *out = a;
+  return ST_OK;
+}
+
+void build_adjoint_ops(const AdjPlan &a, int lsrc, std::vector<Op> *ops) {
+  ops->clear();
+  const Plan &p = a.g;
+  Builder B(p, ops);
+  const int ns = (int)p.slabs.size();
+  const int64_t total = (int64_t)a.nseg * ns;
+  const int NQ = 2;
+  const bool c0f = p.in.c0_field;
+  std::vector<int> nb;
+  struct Geo {
+    int t, sg, j, q, lsrc, ldst;
+    int64_t n0, len, loc0, nload, nz_int;
+    const Slab *sl;
+  };
+  auto geo = [&](int64_t g) {
+    Geo x;
+    x.t = (int)(g / ns);
+    x.sg = a.nseg - 1 - x.t;                 // segments run newest first
+    x.j = (int)(g % ns);
+    x.q = (int)(g % NQ);
+    x.sl = &p.slabs[x.j];
+    x.lsrc = (lsrc + x.t) & 1;
+    x.ldst = (lsrc + x.t + 1) & 1;
+    x.n0 = (int64_t)x.sg * a.m;
+    x.len = std::min<int64_t>(a.m, a.steps - x.n0);
+    x.loc0 = x.sl->l0 - x.sl->gz0;
+    x.nload = x.sl->l1 - x.sl->l0;
+    x.nz_int = x.sl->z1 - x.sl->z0;
+    return x;
+  };
+  const size_t pb = p.plane_bytes;
+  auto buf = [&](int q, int b) { return (int64_t)a.off_buf[q][b]; };
+  auto h2d = [&](const Geo &x, int host, size_t host_off, int64_t dev, int64_t bytes) {
+    Op o = B.blank(OP_H2D, S_IN);
+    o.host_id = (int8_t)host;
+    o.host_off = (int64_t)host_off;
+    o.dev_dst = dev;
+    o.bytes = bytes;
+    o.slab = x.j;
+    o.sweep = x.t;
+    B.push(o);
+  };
+  auto issue_in = [&](int64_t g) {
+    const Geo x = geo(g);
+    std::vector<int> w;
+    if (g >= NQ) w.push_back(B.ev.free(x.q));
+    if (x.t > 0) {
+      B.writers_of(x.sl->l0, x.sl->l1, &nb);
+      for (int jj : nb) w.push_back(B.ev.d2h((x.t - 1) & 1, jj));
+    }
+    B.wait_all(S_IN, w);
+    if (a.ckpt_coded[(size_t)x.sg])
+      h2d(x, HOST_CKPT, a.ckpt_off[(size_t)x.sg] + (size_t)(x.sl->l0 / 4) * p.layer_bytes,
+          (int64_t)a.off_cstage[x.q], (int64_t)((size_t)(x.nload / 4) * p.layer_bytes));
+    else
+      h2d(x, HOST_CKPT, a.ckpt_off[(size_t)x.sg] + (size_t)x.sl->l0 * pb,
+          buf(x.q, A_U0) + x.loc0 * (int64_t)pb, x.nload * (int64_t)pb);
+    h2d(x, x.lsrc, (size_t)x.sl->l0 * pb, buf(x.q, A_LA) + x.loc0 * (int64_t)pb, x.nload * (int64_t)pb);
+    if (c0f)
+      h2d(x, HOST_AUX, (size_t)x.sl->l0 * pb, buf(x.q, A_C) + x.loc0 * (int64_t)pb, x.nload * (int64_t)pb);
+    h2d(x, HOST_GRAD, (size_t)x.sl->z0 * pb, buf(x.q, A_G) + p.halo * (int64_t)pb, x.nz_int * (int64_t)pb);
+    B.rec(S_IN, B.ev.in(x.q));
+    B.rec(S_IN, B.ev.h2d(x.t & 1, x.j));
+  };
+  auto issue_compute = [&](int64_t g) {
+    const Geo x = geo(g);
+    B.wait(S_COMPUTE, B.ev.in(x.q));
+    if (a.ckpt_coded[(size_t)x.sg]) {
+      Op o = B.blank(OP_DEC, S_COMPUTE);
+      o.dev_src = (int64_t)a.off_cstage[x.q];
+      o.dev_dst = buf(x.q, A_U0) + x.loc0 * (int64_t)pb;
+      o.z_hi = x.nload / 4;
+      o.planes = x.nload;
+      o.slab = x.j;
+      o.sweep = x.t;
+      B.push(o);
+    }
+    const int64_t dom_lo = std::max<int64_t>(0, -x.sl->gz0);
+    const int64_t dom_hi = std::min<int64_t>(x.sl->planes, p.in.nz - x.sl->gz0);
+    auto step = [&](int64_t src, int64_t dst, int64_t grow, bool tr) {
+      Op o = B.blank(OP_STAR7, S_COMPUTE);
+      o.dev_src = src;
+      o.dev_dst = dst;
+      o.dev_src2 = c0f ? buf(x.q, A_C) : -1;
+      o.transpose = tr;
+      o.z_lo = std::max<int64_t>(p.halo - grow, dom_lo);
+      o.z_hi = std::min<int64_t>(p.halo + x.nz_int + grow, dom_hi);
+      o.gz0 = x.sl->gz0;
+      o.planes = x.sl->planes;
+      o.slab = x.j;
+      o.sweep = x.t;
+      B.push(o);
+    };
+    int lcur = A_LA, loth = A_LB;
+    for (int64_t i = x.len - 1; i >= 0; i--) {
+      // u_{n0+i}: i forward steps from the checkpoint, the range shrinking to
+      // the interior at the last one
+      int64_t u = buf(x.q, A_U0);
+      for (int64_t tt = 1; tt <= i; tt++) {
+        const int64_t dst = buf(x.q, (tt & 1) ? A_WA : A_WB);
+        step(u, dst, i - tt, false);
+        u = dst;
+      }
+      Op o = B.blank(OP_AXPY, S_COMPUTE);   // g_c0 += lambda_{n0+i+1} * u_{n0+i}
+      o.dev_dst = buf(x.q, A_G) + p.halo * (int64_t)pb;
+      o.dev_src = buf(x.q, lcur) + p.halo * (int64_t)pb;
+      o.dev_src2 = u + p.halo * (int64_t)pb;
+      o.bytes = x.nz_int * (int64_t)pb;
+      o.slab = x.j;
+      o.sweep = x.t;
+      B.push(o);
+      step(buf(x.q, lcur), buf(x.q, loth), i, true);   // lambda_{n0+i} = A^T lambda_{n0+i+1}
+      std::swap(lcur, loth);
+    }
+    B.rec(S_COMPUTE, B.ev.out(x.q));
+    return lcur;
+  };
+  auto issue_out = [&](int64_t g, int lres) {
+    const Geo x = geo(g);
+    std::vector<int> w{B.ev.out(x.q)};
+    if (x.t > 0) {
+      B.readers_of(x.sl->z0, x.sl->z1, &nb);
+      for (int jj : nb) w.push_back(B.ev.h2d((x.t - 1) & 1, jj));
+    }
+    B.wait_all(S_OUT, w);
+    for (int f = 0; f < 2; f++) {
+      Op o = B.blank(OP_D2H, S_OUT);
+      o.host_id = (int8_t)(f == 0 ? x.ldst : HOST_GRAD);
+      o.dev_src = buf(x.q, f == 0 ? lres : A_G) + p.halo * (int64_t)pb;
+      o.host_off = (int64_t)((size_t)x.sl->z0 * pb);
+      o.bytes = x.nz_int * (int64_t)pb;
+      o.slab = x.j;
+      o.sweep = x.t;
+      B.push(o);
+    }
+    B.rec(S_OUT, B.ev.free(x.q));
+    B.rec(S_OUT, B.ev.d2h(x.t & 1, x.j));
+  };
+  int64_t next_in = 0, outs_issued = 0;
+  auto in_ready = [&](int64_t gi) {
+    const int t = (int)(gi / ns);
+    if (t == 0) return true;
+    const Slab &sl = p.slabs[(size_t)(gi % ns)];
+    B.writers_of(sl.l0, sl.l1, &nb);
+    int jmax = 0;
+    for (int jj : nb) jmax = std::max(jmax, jj);
+    return (int64_t)(t - 1) * ns + jmax < outs_issued;
+  };
+  for (int64_t g = 0; g < total; g++) {
+    while (next_in < total && next_in <= g + 1 && in_ready(next_in)) issue_in(next_in++);
+    const int lres = issue_compute(g);
+    issue_out(g, lres);
+    outs_issued = g + 1;
+  }
+  B.push(B.blank(OP_SYNC, -1));
+}
+
 std::string dump_ops(const std::vector<Op> &ops) {
   static const char *names[] = {"H2D", "D2H", "DEC", "ENC", "STAR7", "WAVE", "REC", "WAIT", "SYNC"};
   std::string out;
@@ -514,6 +754,12 @@ void accesses(const Plan &p, const Op &o, std::vector<Access> *a) {
       dev(o.dev_src, (int64_t)((size_t)o.z_hi * 4 * p.plane_bytes), false);
       dev(o.dev_dst, (int64_t)((size_t)o.z_hi * p.layer_bytes), true);
       break;
+    case OP_AXPY:
+      dev(o.dev_src, o.bytes, false);
+      dev(o.dev_src2, o.bytes, false);
+      dev(o.dev_dst, o.bytes, false);
+      dev(o.dev_dst, o.bytes, true);
+      break;
     case OP_STAR7:
     case OP_WAVE: {
       // reads planes [z_lo - r, z_hi + r) of the source (and the aux buffer),
@@ -533,11 +779,12 @@ void accesses(const Plan &p, const Op &o, std::vector<Access> *a) {
 
 }  // namespace
 
-int64_t check_ops(const Plan &p, const std::vector<Op> &ops, std::string *why) {
+int64_t check_ops(const Plan &p, const std::vector<Op> &ops, std::string *why,
+                  bool check_writeback) {
   const int NS = 3;
   // vector clock per stream, and the clock captured by each event's last record
   std::vector<std::vector<int64_t>> vc(NS, std::vector<int64_t>(NS, 0));
-  std::vector<std::vector<int64_t>> evc(EventIds{(int)p.slabs.size()}.count(),
+  std::vector<std::vector<int64_t>> evc(EventIds{(int)p.slabs.size()}.count() + 64,
                                         std::vector<int64_t>(NS, -1));
   std::vector<int> ev_recorded(evc.size(), 0);
   struct Stamp { int stream; int64_t clock; std::vector<int64_t> vc; size_t op; };
@@ -593,24 +840,35 @@ int64_t check_ops(const Plan &p, const std::vector<Op> &ops, std::string *why) {
     }
     for (const Access &a : acc) hist.push_back({st, a});
   }
-  // every sweep must write back its whole destination level exactly once
-  {
+  // every sweep must write back each host store it writes, whole and once
+  if (check_writeback) {
     int max_sweep = -1;
     for (const Op &o : ops) max_sweep = std::max(max_sweep, (int)o.sweep);
     for (int t = 0; t <= max_sweep; t++) {
-      std::vector<std::pair<int64_t, int64_t>> rs;
-      for (const Op &o : ops)
-        if (o.type == OP_D2H && o.sweep == t) rs.push_back({o.host_off, o.host_off + o.bytes});
-      std::sort(rs.begin(), rs.end());
-      int64_t at = 0;
-      for (const auto &r : rs) {
-        if (r.first != at) break;
-        at = r.second;
+      bool any = false;
+      for (int id = 0; id < kHostStores; id++) {
+        std::vector<std::pair<int64_t, int64_t>> rs;
+        for (const Op &o : ops)
+          if (o.type == OP_D2H && o.sweep == t && o.host_id == id)
+            rs.push_back({o.host_off, o.host_off + o.bytes});
+        if (rs.empty()) continue;
+        any = true;
+        std::sort(rs.begin(), rs.end());
+        int64_t at = 0;
+        for (const auto &r : rs) {
+          if (r.first != at) break;
+          at = r.second;
+        }
+        if (at != (int64_t)p.host_level_bytes) {
+          bad++;
+          if (why && why->empty())
+            *why = "sweep " + std::to_string(t) + " does not write back store " +
+                   std::to_string(id) + " whole";
+        }
       }
-      if (at != (int64_t)p.host_level_bytes) {
+      if (!any) {
         bad++;
-        if (why && why->empty())
-          *why = "sweep " + std::to_string(t) + " does not write back its whole level";
+        if (why && why->empty()) *why = "sweep " + std::to_string(t) + " writes nothing back";
       }
     }
   }

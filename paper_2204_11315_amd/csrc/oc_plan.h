@@ -14,8 +14,11 @@ namespace oc {
 
 enum Kind { KIND_STAR7 = 1, KIND_WAVE25 = 2 };
 
-// Storage ids of host memory an operation may touch.
-enum HostStore { HOST_LEVEL0 = 0, HOST_LEVEL1 = 1, HOST_AUX = 2 };
+// Storage ids of host memory an operation may touch.  The adjoint run maps
+// the two levels to its two lambda levels and adds the checkpoint store and
+// the coefficient-gradient store.
+enum HostStore { HOST_LEVEL0 = 0, HOST_LEVEL1 = 1, HOST_AUX = 2, HOST_CKPT = 3, HOST_GRAD = 4 };
+constexpr int kHostStores = 5;
 
 enum OpType : uint8_t {
   OP_H2D,    // host store -> device arena           (host_id, host_off, dev_dst, bytes)
@@ -24,6 +27,7 @@ enum OpType : uint8_t {
   OP_ENC,    // codec encode: dev_src planes -> dev_dst codes (layers)
   OP_STAR7,  // one 7-point step: dev_src -> dev_dst, local planes [z_lo, z_hi)
   OP_WAVE,   // one 25-point leapfrog step (dev_src = p^n, dev_dst = p^{n-1} -> p^{n+1})
+  OP_AXPY,   // dev_dst[i] += dev_src[i] * dev_src2[i] over `bytes` bytes of FP32
   OP_REC,    // record event ev on stream
   OP_WAIT,   // stream waits for the latest record of ev
   OP_SYNC    // host waits for every stream (end of a run)
@@ -40,6 +44,7 @@ struct Op {
   int64_t gz0;          // global z of local plane 0 of the slab buffer
   int64_t planes;       // planes of the slab buffer (extent for the hazard model)
   int64_t step;         // WAVE: global time index n of p^n (source term)
+  bool transpose;       // STAR7: apply A^T (the -/+ coefficients swapped)
   int32_t slab, sweep;  // bookkeeping (tests, stats)
 };
 
@@ -126,12 +131,43 @@ struct EventIds {
 void build_ops(const Plan &p, int64_t sweeps, int steps_last, int src, int64_t step0,
                std::vector<Op> *ops);
 
+// ---- adjoint (reverse sweeps over checkpoint segments) ------------------
+// Forward states u_{s*m} (s = 0 .. nseg-1) are kept as checkpoints; segment s
+// covers steps [s*m, min((s+1)*m, T)).  Per slab, the reverse of a segment
+// loads the checkpoint, lambda_{n1}, c0 and the slab's coefficient-gradient
+// interior, then for i = len-1 .. 0: recomputes u_{n0+i} from the checkpoint
+// (i stencil steps on a range shrinking to the interior), adds
+// lambda_{n0+i+1} * u_{n0+i} to the gradient, and steps lambda back with A^T.
+struct AdjPlan {
+  Plan g;                  // geometry (S, halo, P, slabs) and carve-out
+  int m = 8;               // checkpoint interval
+  int64_t steps = 0;       // T
+  int nseg = 0;
+  int ckpt_rate = 0;       // 0 = raw checkpoints
+  // arena: per slot: U0, Wa, Wb, La, Lb, C, G (P planes each) + coded stage
+  size_t off_buf[kMaxSlots][7] = {};
+  size_t off_cstage[kMaxSlots] = {};
+  // host checkpoint store: byte offset and coding of each checkpoint
+  std::vector<size_t> ckpt_off;
+  std::vector<int> ckpt_coded;
+  size_t ckpt_bytes = 0;   // whole checkpoint store
+  size_t field_bytes = 0;  // one raw field
+};
+enum AdjBuf { A_U0 = 0, A_WA, A_WB, A_LA, A_LB, A_C, A_G };
+// in: geometry input (kind STAR7, rate = ckpt rate for alignment, budget,
+// slots, slab_planes); m, T.  Returns a status.
+int make_adj_plan(const PlanInput &in, int m, int64_t steps, AdjPlan *out);
+// Reverse op list; lambda_T is read from host level `lsrc` (0/1); the final
+// lambda_0 lands in level (lsrc + nseg) & 1.
+void build_adjoint_ops(const AdjPlan &a, int lsrc, std::vector<Op> *ops);
+
 // Human-readable listing of an operation list (one op per line).
 std::string dump_ops(const std::vector<Op> &ops);
 
 // Happens-before checker: number of pairs of conflicting accesses that are not
 // ordered by stream order, event record/wait or host sync.  `why` (optional)
 // receives a description of the first one.
-int64_t check_ops(const Plan &p, const std::vector<Op> &ops, std::string *why);
+int64_t check_ops(const Plan &p, const std::vector<Op> &ops, std::string *why,
+                  bool check_writeback = true);
 
 }  // namespace oc

@@ -86,8 +86,13 @@ _SIGS = {
     "oc_codec_decompress": (ctypes.c_int, [_P, _I64, _I64, _I64, _I32, _P, _P]),
     "oc_codec_status": (ctypes.c_int, [_P]),
     "oc_star7_incore": (ctypes.c_int, [_P, _P, _P, _I64, _I64, _I64, _P, _P, _I64, _P]),
+    "oc_wave25_incore": (ctypes.c_int, [_P, _P, _P, _P, _I64, _I64, _I64, _P, _I64, _I64, _P]),
     "oc_debug_fail_after": (ctypes.c_int, [_P, _I64]),
     "oc_set_timing": (ctypes.c_int, [_P, _I32]),
+    "oc_adjoint_host_bytes": (_SZ, [_P, _I64, _I32, _I32]),
+    "oc_forward_ckpt": (ctypes.c_int, [_P, _I64, _I32, _I32, _P, _SZ]),
+    "oc_adjoint": (ctypes.c_int, [_P, _P, _P, _P]),
+    "oc_debug_check_adjoint": (_I64, [_P, _P, _P, _I64, _I32, _I32, _I32, _I64]),
     "oc_debug_check_plan": (_I64, [_P, _P, _P, _I64, _I32, _I64]),
     "oc_debug_plan_ops": (_I64, [_P, _P, _P, _I64, _P]),
     "oc_debug_plan_dump": (_I64, [_P, _P, _P, _I64, ctypes.c_char_p, _SZ]),
@@ -129,6 +134,20 @@ def _ref(x):
 def make_grid(shape) -> Grid:
     nz, ny, nx = (int(v) for v in shape)
     return Grid(nx, ny, nz)
+
+
+def make_wave25(h: float, dt: float, src, f_peak: float, t0: float) -> Stencil:
+    """25-point acoustic wave: grid spacing h (m), time step dt (s), Ricker source
+    at cell src = (x, y, z) with peak frequency f_peak (Hz) and delay t0 (s)."""
+    st = Stencil()
+    st.kind = OC_WAVE25
+    st.h = float(h)
+    st.dt = float(dt)
+    for i, v in enumerate(src):
+        st.src[i] = int(v)
+    st.f_peak = float(f_peak)
+    st.t0 = float(t0)
+    return st
 
 
 def make_star7(c=C_CONFIG1, c0_field: bool = False) -> Stencil:
@@ -203,6 +222,16 @@ def plan_dump(shape, stencil: Stencil, k: int, slab_planes: int, rate: int, swee
     buf = ctypes.create_string_buffer(n)
     lib().oc_debug_plan_dump(_ref(g), _ref(stencil), _ref(cfg), int(sweeps), buf, n)
     return buf.value.decode()
+
+
+def check_adjoint_plan(shape, stencil: Stencil, steps: int, ckpt_every: int, ckpt_rate: int,
+                       budget: int = 0, slab_planes: int = 0, mutate: int = 0, i: int = 0) -> int:
+    """Race check of the adjoint's reverse-sweep operation list (see oc.h);
+    mutate=0, i=-1 returns the number of waits."""
+    g = make_grid(shape)
+    cfg = plan_config(1, slab_planes, 0, True, budget)
+    return int(lib().oc_debug_check_adjoint(_ref(g), _ref(stencil), _ref(cfg), int(steps),
+                                            int(ckpt_every), int(ckpt_rate), int(mutate), int(i)))
 
 
 def codec_bytes(shape, rate: int) -> int:
@@ -295,22 +324,39 @@ def star7_incore(d_in, c, steps: int, c0f=None, stream=None):
     return out
 
 
-class OutOfCore:
-    """Out-of-core time stepping of a host-resident field (7-point star).
+def wave25_incore(d_prev, d_cur, d_vel, stencil: Stencil, n0: int, steps: int, stream=None):
+    """Advances (p^{n0-1}, p^{n0}) in place on the device; returns (d_prev, d_cur)."""
+    torch = _torch()
+    nz, ny, nx = d_cur.shape
+    tmp = torch.empty_like(d_cur) if steps % 2 else None
+    _check(lib().oc_wave25_incore(_dev(d_prev, torch.float32, "d_prev"), _dev(d_cur, torch.float32, "d_cur"),
+                                  _dev(d_vel, torch.float32, "d_vel"),
+                                  None if tmp is None else ctypes.c_void_p(tmp.data_ptr()),
+                                  nx, ny, nz, _ref(stencil), int(n0), int(steps),
+                                  _stream_handle(stream)), "oc_wave25_incore")
+    return d_prev, d_cur
 
-    shape = (nz, ny, nx).  budget = bytes of device memory the library may use
-    (one torch allocation).  rate = 0 keeps raw FP32 on the host; 1..32 keeps
-    fixed-rate codes.  k = steps per residency; slab_planes = S (0 = auto).
+
+class OutOfCore:
+    """Out-of-core time stepping of a host-resident field.
+
+    shape = (nz, ny, nx).  stencil = a Stencil (make_star7 / make_wave25); when
+    None, the 7-point star with coefficients `c` (and a c0 field if c0_field).
+    budget = bytes of device memory the library may use (one torch allocation).
+    rate = 0 keeps raw FP32 on the host; 1..32 keeps fixed-rate codes.  k =
+    steps per residency; slab_planes = S (0 = largest that fits the budget).
     """
 
     def __init__(self, shape, c=C_CONFIG1, k: int = 4, rate: int = 0, budget: int = 512 << 20,
                  slab_planes: int = 0, single_buffer: bool = True, c0_field: bool = False,
-                 timing: bool = False, ring_slots: int = 0, prefetch: int = 0, device=None):
+                 timing: bool = False, ring_slots: int = 0, prefetch: int = 0, device=None,
+                 stencil: Stencil = None):
         torch = _torch()
         self.shape = tuple(int(v) for v in shape)
         self.rate = int(rate)
         self.k = int(k)
-        self.stencil = make_star7(c, c0_field)
+        self.stencil = stencil if stencil is not None else make_star7(c, c0_field)
+        self.wave = self.stencil.kind == OC_WAVE25
         self.grid = make_grid(self.shape)
         self.device = torch.device(device if device is not None else "cuda")
         need = plan_bytes(self.shape, self.stencil, k, slab_planes, rate, single_buffer, budget,
@@ -353,18 +399,27 @@ class OutOfCore:
             raise ValueError("expected shape %s, got %s" % (self.shape, a.shape))
         return a
 
-    def load(self, u, c0=None):
+    def load(self, u, aux=None, vel=None):
+        """STAR7: u = field, aux = c0 field (if any).  WAVE25: u = p^0,
+        aux = p^{-1}, vel = velocity."""
         u = self._host_f32(u)
-        c0a = None if c0 is None else self._host_f32(c0)
+        a = None if aux is None else self._host_f32(aux)
+        v = None if vel is None else self._host_f32(vel)
         _check(lib().oc_load(self.h, ctypes.c_void_p(u.ctypes.data),
-                             None if c0a is None else ctypes.c_void_p(c0a.ctypes.data), None),
-               "oc_load")
+                             None if a is None else ctypes.c_void_p(a.ctypes.data),
+                             None if v is None else ctypes.c_void_p(v.ctypes.data)), "oc_load")
 
     def run(self, steps: int):
         _check(lib().oc_run(self.h, int(steps)), "oc_run")
 
-    def store(self) -> np.ndarray:
+    def store(self):
+        """STAR7: the field.  WAVE25: (p^n, p^{n-1})."""
         out = np.empty(self.shape, dtype=np.float32)
+        if self.wave:
+            prev = np.empty(self.shape, dtype=np.float32)
+            _check(lib().oc_store(self.h, ctypes.c_void_p(out.ctypes.data),
+                                  ctypes.c_void_p(prev.ctypes.data)), "oc_store")
+            return out, prev
         _check(lib().oc_store(self.h, ctypes.c_void_p(out.ctypes.data), None), "oc_store")
         return out
 
@@ -389,3 +444,64 @@ class OutOfCore:
             self.close()
         except Exception:
             pass
+
+
+class Adjoint:
+    """Forward with checkpoints, then gradients of a loss of u_T (7-point star).
+
+    Wraps an uncompressed OutOfCore handle (the forward is exact); checkpoints
+    every `ckpt_every` steps are kept on the host as codes at `ckpt_rate`
+    bits/value (0 = raw), u_0 exactly."""
+
+    def __init__(self, shape, c=C_CONFIG1, steps: int = 64, k: int = 4, ckpt_every: int = 8,
+                 ckpt_rate: int = 16, budget: int = 512 << 20, slab_planes: int = 0,
+                 c0_field: bool = True, device=None):
+        torch = _torch()
+        self.steps, self.ckpt_every, self.ckpt_rate = int(steps), int(ckpt_every), int(ckpt_rate)
+        self.ooc = OutOfCore(shape, c, k=k, rate=0, budget=budget, slab_planes=slab_planes,
+                             c0_field=c0_field, device=device)
+        n = int(lib().oc_adjoint_host_bytes(self.ooc.h, self.steps, self.ckpt_every,
+                                            self.ckpt_rate))
+        if n == 0:
+            raise OCError(OC_ERR_BUDGET, "oc_adjoint_host_bytes", "no adjoint plan fits")
+        self.work = torch.empty(n, dtype=torch.uint8, pin_memory=True)
+        self.shape = self.ooc.shape
+
+    def forward(self, u0, c0=None) -> np.ndarray:
+        self.ooc.load(u0, c0)
+        _check(lib().oc_forward_ckpt(self.ooc.h, self.steps, self.ckpt_every, self.ckpt_rate,
+                                     ctypes.c_void_p(self.work.data_ptr()), self.work.numel()),
+               "oc_forward_ckpt")
+        return self.ooc.store()
+
+    def backward(self, gT):
+        gT = self.ooc._host_f32(gT)
+        g_u0 = np.empty(self.shape, np.float32)
+        g_c0 = np.empty(self.shape, np.float32)
+        _check(lib().oc_adjoint(self.ooc.h, ctypes.c_void_p(gT.ctypes.data),
+                                ctypes.c_void_p(g_u0.ctypes.data), ctypes.c_void_p(g_c0.ctypes.data)),
+               "oc_adjoint")
+        return g_u0, g_c0
+
+    def close(self):
+        self.ooc.close()
+
+
+def stencil_function():
+    """torch.autograd.Function: u_T = A(c0)^steps u0 with host-resident CPU
+    float32 tensors; backward returns dL/du0 and dL/dc0 from the adjoint."""
+    torch = _torch()
+
+    class OCStencilFn(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, u0, c0, runner):
+            uT = runner.forward(u0.detach().cpu().numpy(), c0.detach().cpu().numpy())
+            ctx.runner = runner
+            return torch.from_numpy(uT)
+
+        @staticmethod
+        def backward(ctx, gT):
+            g_u0, g_c0 = ctx.runner.backward(gT.detach().to(torch.float32).cpu().numpy())
+            return torch.from_numpy(g_u0), torch.from_numpy(g_c0), None
+
+    return OCStencilFn

@@ -1,0 +1,118 @@
+"""Adjoint of the out-of-core 7-point path on the GPU, through the C ABI.
+
+Loss L = 1/2 sum over the top plane of u_T^2.  Checked against the FP64
+oracle's gradients (raw checkpoints: 1e-5; 16-bit codes: 1e-3), against
+central finite differences of the GPU forward on random directions (the loss
+is exactly quadratic in u0), and through torch.autograd.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2204_11315_amd import inputs, oc
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+C = (0.4, 0.1, 0.1, 0.1, 0.1, 0.1, 0.1)
+SHAPE = (44, 12, 16)
+STEPS, EVERY = 12, 4
+BUDGET = 200 << 10      # forces several slabs in the forward and the reverse sweeps
+
+
+def fields():
+    u0 = inputs.grf_field(SHAPE, seed=41)
+    c0 = inputs.c0_field(SHAPE, seed=5)
+    return u0, c0
+
+
+def top_grad(uT):
+    g = np.zeros_like(uT)
+    g[-1] = uT[-1]
+    return g
+
+
+def rel(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("rate,tol", [(0, 1e-5), (16, 1e-3)])
+def test_gradients_vs_oracle(rate, tol):
+    u0, c0 = fields()
+    adj = oc.Adjoint(SHAPE, C, steps=STEPS, k=2, ckpt_every=EVERY, ckpt_rate=rate, budget=BUDGET)
+    try:
+        uT = adj.forward(u0, c0)
+        g_u0, g_c0 = adj.backward(top_grad(uT))
+    finally:
+        adj.close()
+    L, uT_ref, gu_ref, gc_ref = oracle.star7_grad(u0, C, STEPS, c0)
+    assert rel(uT, uT_ref) < 1e-5
+    assert rel(g_u0, gu_ref) < tol
+    assert rel(g_c0, gc_ref) < tol
+
+
+def test_directional_derivatives_vs_central_differences():
+    u0, c0 = fields()
+    adj = oc.Adjoint(SHAPE, C, steps=STEPS, k=2, ckpt_every=EVERY, ckpt_rate=16, budget=BUDGET)
+    try:
+        uT = adj.forward(u0, c0)
+        g_u0, g_c0 = adj.backward(top_grad(uT))
+    finally:
+        adj.close()
+    fwd = oc.OutOfCore(SHAPE, C, k=2, rate=0, budget=BUDGET, c0_field=True)
+
+    def loss(u, c):
+        fwd.load(u.astype(np.float32), c.astype(np.float32))
+        fwd.run(STEPS)
+        return 0.5 * float(np.sum(fwd.store()[-1].astype(np.float64) ** 2))
+
+    rng = np.random.default_rng(43)
+    want, got = [], []
+    try:
+        for _ in range(4):
+            d = rng.standard_normal(SHAPE)
+            e = inputs.smooth_direction(SHAPE, rng)
+            eu = 1e-2 * np.sqrt(np.mean(u0.astype(np.float64) ** 2)) / np.sqrt(np.mean(d ** 2))
+            ec = 1e-2 * np.sqrt(np.mean(c0.astype(np.float64) ** 2)) / np.sqrt(np.mean(e ** 2))
+            want.append((loss(u0 + eu * d, c0) - loss(u0 - eu * d, c0)) / (2 * eu))
+            got.append(np.vdot(g_u0.astype(np.float64), d))
+            want.append((loss(u0, c0 + ec * e) - loss(u0, c0 - ec * e)) / (2 * ec))
+            got.append(np.vdot(g_c0.astype(np.float64), e))
+    finally:
+        fwd.close()
+    assert rel(got, want) < 1e-3
+
+
+def test_torch_autograd_function_and_linearity():
+    u0, c0 = fields()
+    runner = oc.Adjoint(SHAPE, C, steps=STEPS, k=2, ckpt_every=EVERY, ckpt_rate=16, budget=BUDGET)
+    try:
+        Fn = oc.stencil_function()
+        tu = torch.from_numpy(u0.copy()).requires_grad_(True)
+        tc = torch.from_numpy(c0.copy()).requires_grad_(True)
+        uT = Fn.apply(tu, tc, runner)
+        loss = 0.5 * (uT[-1].double() ** 2).sum()
+        loss.backward()
+        g_u0, g_c0 = runner.backward(2.0 * top_grad(uT.detach().numpy()))
+    finally:
+        runner.close()
+    assert np.allclose(2.0 * tu.grad.numpy(), g_u0, rtol=1e-6, atol=1e-12)
+    assert np.allclose(2.0 * tc.grad.numpy(), g_c0, rtol=1e-6, atol=1e-12)
+
+
+def test_adjoint_needs_checkpoints_and_raw_handle():
+    u0, c0 = fields()
+    o = oc.OutOfCore(SHAPE, C, k=2, rate=8, budget=BUDGET, c0_field=True)
+    try:
+        assert oc.lib().oc_adjoint_host_bytes(o.h, STEPS, EVERY, 16) == 0   # coded handle
+    finally:
+        o.close()
+    adj = oc.Adjoint(SHAPE, C, steps=STEPS, k=2, ckpt_every=EVERY, ckpt_rate=16, budget=BUDGET)
+    try:
+        with pytest.raises(oc.OCError) as e:
+            adj.backward(np.zeros(SHAPE, np.float32))
+        assert e.value.status == oc.OC_ERR_STATE
+    finally:
+        adj.close()

@@ -161,3 +161,41 @@ def test_c0_field_plan_race_free():
         assert oc.check_plan((40, 12, 16), st, 4, 8, R, 3) == 0
         for i in range(nw):
             assert oc.check_plan((40, 12, 16), st, 4, 8, R, 3, mutate=1, i=i) > 0
+
+
+WAVE = oc.make_wave25(10.0, 1e-3, (4, 4, 4), 15.0, 0.0667)
+
+
+@pytest.mark.parametrize("R,swb", [(0, True), (12, True), (12, False)])
+@pytest.mark.parametrize("shape,k,S", [((48, 8, 8), 2, 8), ((40, 8, 8), 1, 12), ((16, 8, 8), 2, 16)])
+def test_wave_operation_list_race_free_and_minimal(R, swb, shape, k, S):
+    n, nw = oc.plan_ops(shape, WAVE, k, S, R, 3, single_buffer=swb)
+    assert oc.check_plan(shape, WAVE, k, S, R, 3, single_buffer=swb) == 0
+    for i in range(nw):
+        assert oc.check_plan(shape, WAVE, k, S, R, 3, single_buffer=swb, mutate=1, i=i) > 0
+    assert oc.check_plan(shape, WAVE, k, S, R, 3, single_buffer=swb, mutate=2) > 0
+
+
+def test_wave_memory_model():
+    shape = (4096, 1024, 1024)
+    plane = 1024 * 1024 * 4
+    S, k = 128, 2
+    unit = (S + 2 * 8) * plane              # halo k*r = 8 planes per side
+    # raw: three working buffers (v, p^n, p^{n-1}) per ring slot
+    assert oc.plan_bytes(shape, WAVE, k, S, 0) == 9 * unit
+    # coded, single working buffer: 3 shared buffers + 3 slots x 3 coded fields
+    assert oc.plan_bytes(shape, WAVE, k, S, 12) == 3 * unit + 3 * 3 * unit * 12 // 32
+    assert oc.host_level_bytes(shape, WAVE, 0) == 2 * (16 << 30)
+    assert oc.host_aux_bytes(shape, WAVE, 12) == oc.codec_bytes(shape, 12)
+
+
+@pytest.mark.parametrize("shape,S,R", [((40, 12, 16), 8, 16), ((40, 12, 16), 8, 0), ((24, 8, 8), 24, 8),
+                                       ((36, 8, 8), 12, 0), ((44, 8, 8), 12, 16)])
+@pytest.mark.parametrize("steps,every", [(12, 4), (10, 4), (8, 8)])
+def test_adjoint_operation_list_race_free_and_minimal(shape, S, R, steps, every):
+    st = oc.make_star7(c0_field=True)
+    nw = oc.check_adjoint_plan(shape, st, steps, every, R, slab_planes=S, i=-1)
+    assert nw > 0
+    assert oc.check_adjoint_plan(shape, st, steps, every, R, slab_planes=S) == 0
+    for i in range(nw):
+        assert oc.check_adjoint_plan(shape, st, steps, every, R, slab_planes=S, mutate=1, i=i) > 0
