@@ -114,8 +114,9 @@ def run_leg(oc, torch, u0, rate, steps, warmup, ref=None, timing=True):
 
 def kernel_roofline(stats, rate):
     """Per-kernel averages over the timed runs; algorithmic bytes per launch:
-    decode reads 8R B and writes 256 B per 4x4x4 block, encode the reverse,
-    the stencil reads and writes 4 B per cell update."""
+    decode reads 8R B and writes 256 B per 4x4x4 block, encode the reverse;
+    a (fused) stencil launch reads its input plane range once and writes its
+    output range once (as counted by the library)."""
     tot = {"decode": 0.0, "encode": 0.0, "stencil": 0.0}
     cnt = {"decode": 0, "encode": 0, "stencil": 0}
     byt = {"decode": 0.0, "encode": 0.0, "stencil": 0.0}
@@ -125,7 +126,7 @@ def kernel_roofline(stats, rate):
             cnt[k] += s["n_" + k]
         byt["decode"] += s["blocks_decode"] * (8 * rate + 256)
         byt["encode"] += s["blocks_encode"] * (256 + 8 * rate)
-        byt["stencil"] += s["cells_stencil"] * 8
+        byt["stencil"] += s["bytes_stencil"]
     per = {}
     for k in tot:
         if cnt[k]:
@@ -168,6 +169,8 @@ def kernel_probe(rate, reps=20):
         oc.compress(u[4:4 + S].contiguous(), rate)             # 16 layers = one slab interior
     for _ in range(reps):
         oc.star7_incore(u, C, 1)                               # one step over 72 planes
+    for _ in range(reps):
+        oc.star7_incore(u, C, 4)                               # four fused steps over 72 planes
     a = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
     b = torch.empty_like(a)
     for _ in range(reps):
@@ -176,6 +179,129 @@ def kernel_probe(rate, reps=20):
     print(json.dumps({"kernel_probe": True, "rate": rate, "reps": reps,
                       "decode_blocks": 128 * 128 * (P // 4), "encode_blocks": 128 * 128 * (S // 4),
                       "stencil_cells": 512 * 512 * P, "ref_copy_bytes": 256 << 20}), flush=True)
+
+
+def wave_workload(args):
+    """25-point acoustic wave (config 4): 1024x1024x4096 FP32 per field, layered
+    velocity 1500..4500 m/s, Ricker 15 Hz, CFL 0.4, k = 2, 32 steps, 8 GiB budget,
+    S = 128; compressed at R = 12 beside an uncompressed run at the same S.  The
+    error of the compressed run is measured against the uncompressed GPU run (an
+    FP64 oracle of this size needs ~100 GiB; the oracle parity runs at reduced
+    sizes in the tests)."""
+    import torch
+    from paper_2204_11315_amd import inputs, oc
+    nz = args.wave_nz
+    shape = (nz, 1024, 1024)
+    h, f, steps = 10.0, 15.0, 32
+    t0 = time.perf_counter()
+    vel = inputs.layered_velocity(shape, seed=4)
+    dt = 0.4 * h / float(vel.max())
+    st = oc.make_wave25(h, dt, (512, 512, 32), f, 1.0 / f)
+    p0 = np.zeros(shape, np.float32)
+    log("wave inputs ready in %.1f s" % (time.perf_counter() - t0))
+    cells = float(np.prod(shape)) * steps
+    res = {}
+    for rate in (0, args.wave_rate):
+        o = oc.OutOfCore(shape, k=2, rate=rate, budget=8 << 30, slab_planes=128, stencil=st,
+                         timing=True)
+        try:
+            o.load(p0, p0, vel)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            o.run(steps)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t1
+            cur, _ = o.store()
+            stt = o.stats()
+        finally:
+            o.close()
+        res[rate] = {"gcell_per_s": cells / wall / 1e9, "wall_s": wall, "field": cur,
+                     "peak_dev_bytes": stt["peak_dev_bytes"], "bytes_h2d": stt["bytes_h2d"],
+                     "bytes_d2h": stt["bytes_d2h"], "kernels": kernel_roofline([stt], rate)}
+        log("wave rate %d: %.2f GCell/s (%.1f s)" % (rate, res[rate]["gcell_per_s"], wall))
+    a, b = res[args.wave_rate]["field"], res[0]["field"]
+    err = rel_l2(a, b)
+    emax = float(max(np.abs(a[z:z + 64].astype(np.float64) - b[z:z + 64]).max()
+                     for z in range(0, nz, 64)))
+    out = {"metric": "out-of-core GCell-updates/s compressed vs uncompressed (25-point wave)",
+           "value": res[args.wave_rate]["gcell_per_s"], "unit": "GCell-updates/s", "n_gpus": 1,
+           "steps": 1, "warmup": 0, "ms_per_step": res[args.wave_rate]["wall_s"] * 1e3,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic (layered velocity, Ricker source)",
+           "config": {"workload": "25-point acoustic wave 1024x1024x%d FP32, 32 steps, k=2, S=128, "
+                                  "8 GiB budget, R=%d" % (nz, args.wave_rate)},
+           "uncompressed_gcell_per_s": res[0]["gcell_per_s"],
+           "speedup_vs_uncompressed": res[args.wave_rate]["gcell_per_s"] / res[0]["gcell_per_s"],
+           "rel_l2_vs_uncompressed_gpu": err, "max_abs_vs_uncompressed_gpu": emax,
+           "peak_dev_bytes": res[args.wave_rate]["peak_dev_bytes"],
+           "uncompressed_peak_dev_bytes": res[0]["peak_dev_bytes"],
+           "legs": {str(r): {k: v for k, v in d.items() if k != "field"} for r, d in res.items()}}
+    print(json.dumps(out), flush=True)
+
+
+def adjoint_workload(args):
+    """Adjoint of the 7-point path (config 5): 512x512x2048, c0(x) in [0.3, 0.5],
+    L = 1/2 sum over the top plane of u_T^2 after 64 steps, checkpoints every 8
+    steps at R = 16, 512 MiB budget; checked by central differences of the
+    (uncompressed) GPU forward on random directions."""
+    import torch
+    from paper_2204_11315_amd import inputs, oc
+    shape = SHAPE
+    u0 = inputs.grf_field(shape, seed=2)
+    c0 = inputs.c0_field(shape, seed=5)
+    adj = oc.Adjoint(shape, C, steps=STEPS, k=K, ckpt_every=8, ckpt_rate=16, budget=BUDGET)
+    try:
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        uT = adj.forward(u0, c0)
+        t_fwd = time.perf_counter() - t1
+        gT = np.zeros_like(uT)
+        gT[-1] = uT[-1]
+        t1 = time.perf_counter()
+        g_u0, g_c0 = adj.backward(gT)
+        t_adj = time.perf_counter() - t1
+        fwd = adj.ooc
+        L0 = 0.5 * float(np.sum(uT[-1].astype(np.float64) ** 2))
+
+        def loss(u, c):
+            fwd.load(u, c)
+            fwd.run(STEPS)
+            top = fwd.store()[-1].astype(np.float64)
+            return 0.5 * float(np.sum(top * top))
+
+        rng = np.random.default_rng(51)
+        got, want = [], []
+        rms_u = float(np.sqrt(np.mean(u0.astype(np.float64) ** 2)))
+        rms_c = float(np.sqrt(np.mean(c0.astype(np.float64) ** 2)))
+        for i in range(args.fd_dirs):
+            d = rng.standard_normal(shape).astype(np.float32)
+            e = inputs.smooth_direction((shape[0], 64, 64), rng)   # smooth, tiled to full size
+            e = np.tile(e, (1, shape[1] // 64, shape[2] // 64)).astype(np.float32)
+            eu, ec = 1e-2 * rms_u, 2e-3 * rms_c / float(np.sqrt(np.mean(e.astype(np.float64) ** 2)))
+            # exact (quadratic) along u0; Richardson-extrapolated along c0,
+            # where L is a polynomial of degree 2 * STEPS
+            want.append((loss(u0 + eu * d, c0) - loss(u0 - eu * d, c0)) / (2 * eu))
+            got.append(float(np.vdot(g_u0.astype(np.float64).ravel(), d.astype(np.float64).ravel())))
+            d1 = (loss(u0, c0 + ec * e) - loss(u0, c0 - ec * e)) / (2 * ec)
+            d2 = (loss(u0, c0 + 0.5 * ec * e) - loss(u0, c0 - 0.5 * ec * e)) / ec
+            want.append((4 * d2 - d1) / 3)
+            got.append(float(np.vdot(g_c0.astype(np.float64).ravel(), e.astype(np.float64).ravel())))
+            log("fd direction %d done" % i)
+    finally:
+        adj.close()
+    got, want = np.array(got), np.array(want)
+    rel = float(np.linalg.norm(got - want) / np.linalg.norm(want))
+    cells = float(np.prod(shape)) * STEPS
+    out = {"metric": "adjoint (dL/du0, dL/dc0) of the out-of-core 7-point path vs central differences",
+           "value": cells / t_adj / 1e9, "unit": "GCell-updates/s (reverse)", "n_gpus": 1,
+           "steps": 1, "warmup": 0, "ms_per_step": t_adj * 1e3, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic (Gaussian random field u0, smooth c0 field)",
+           "config": {"workload": "adjoint of 7-point 512x512x2048, 64 steps, checkpoints every 8 "
+                                  "at R=16, 512 MiB budget", "fd_directions": args.fd_dirs},
+           "loss": L0, "forward_with_checkpoints_s": t_fwd, "adjoint_s": t_adj,
+           "fd_rel_l2": rel, "fd_max_rel": float(np.max(np.abs(got - want) / np.abs(want)))}
+    print(json.dumps(out), flush=True)
 
 
 def main():
@@ -192,6 +318,10 @@ def main():
                     help="FP64 oracle reference over the full grid or at 16 sample cells")
     ap.add_argument("--kernels", action="store_true",
                     help="launch each hot kernel at slab shape (for rocprofv3), then exit")
+    ap.add_argument("--workload", choices=["star7", "wave", "adjoint"], default="star7")
+    ap.add_argument("--wave-nz", type=int, default=4096)
+    ap.add_argument("--wave-rate", type=int, default=12)
+    ap.add_argument("--fd-dirs", type=int, default=32)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU; the multi-GPU z-sharding is a design "
@@ -206,6 +336,12 @@ def main():
     oc.lib()
     if args.kernels:
         kernel_probe(args.rate or 16)
+        return
+    if args.workload == "wave":
+        wave_workload(args)
+        return
+    if args.workload == "adjoint":
+        adjoint_workload(args)
         return
     t0 = time.perf_counter()
     u0 = inputs.grf_field(SHAPE, seed=2)

@@ -94,10 +94,13 @@ typedef struct {
   int64_t slab_planes, halo_planes, n_slabs;  /* the plan                                  */
   uint64_t n_ops;          /* operations issued by the last oc_run                          */
   /* with timing on: summed durations (ms) and counts of the last oc_run's ops,
-   * each measured between events recorded on the op's own stream            */
+   * each measured between events recorded on the op's own stream; a fused
+   * multi-step stencil launch counts once                                     */
   double ms_decode, ms_stencil, ms_encode, ms_h2d, ms_d2h;
   uint64_t n_decode, n_stencil, n_encode, n_h2d, n_d2h;
-  uint64_t cells_stencil;  /* cell updates done by the stencil launches (halo included)   */
+  uint64_t cells_stencil;  /* cell updates credited to the stencil launches               */
+  uint64_t bytes_stencil;  /* algorithmic HBM bytes of those launches (input range read once,
+                              output range written once, coefficient / velocity fields)    */
   uint64_t blocks_decode, blocks_encode;  /* 4x4x4 blocks coded                           */
 } oc_stats;
 

@@ -159,38 +159,34 @@ __device__ __forceinline__ uint64_t lowmask64(int n) {
 }
 
 // ---- bit writer over one slot of NW dwords ----------------------------------
+// Branch-free: every put stores the current (possibly partial) dword, so a
+// later put simply overwrites it; once the budget is spent the index is
+// clamped onto the slot's padding dword (index NW), which is never copied out.
+// The slot must start zeroed, and flush() ends the stream.
 struct BitWriter {
   uint32_t *slot;
   int NW;    // dwords in the slot
   uint64_t acc;
   int nacc;  // valid bits in acc (< 32 between calls)
-  int widx;  // dwords already stored
+  int widx;  // dwords completed
   __device__ __forceinline__ int pos() const { return 32 * widx + nacc; }
   __device__ __forceinline__ void put(uint32_t v, int len) {  // len <= 32, v < 2^len
     acc |= (uint64_t)v << nacc;
     nacc += len;
-    if (nacc >= 32) {
-      if (widx < NW) slot[widx] = (uint32_t)acc;
-      widx++;
-      acc >>= 32;
-      nacc -= 32;
-    }
+    slot[min(widx, NW)] = (uint32_t)acc;
+    const bool full = nacc >= 32;
+    widx += full ? 1 : 0;
+    acc = full ? (acc >> 32) : acc;
+    nacc -= full ? 32 : 0;
   }
   __device__ __forceinline__ void put64(uint64_t v, int len) {  // len <= 64
-    if (len > 32) {
-      put((uint32_t)v, 32);
-      put((uint32_t)(v >> 32), len - 32);
-    } else {
-      put((uint32_t)v, len);
-    }
+    const int lo = min(len, 32);
+    put((uint32_t)v & (lo >= 32 ? 0xFFFFFFFFu : ((1u << lo) - 1u)), lo);
+    put((uint32_t)(v >> 32), len - lo);
   }
-  __device__ __forceinline__ void finish() {
-    if (widx < NW) {
-      slot[widx] = (uint32_t)acc;
-      widx++;
-    }
-    for (; widx < NW; widx++) slot[widx] = 0u;
-  }
+  // Stores the bits still held in acc (a put that completes a dword leaves the
+  // carry in acc until the next put).
+  __device__ __forceinline__ void flush() { slot[min(widx, NW)] = (uint32_t)acc; }
 };
 
 // ---- bit reader over one slot of NW dwords ----------------------------------
@@ -199,7 +195,10 @@ struct BitReader {
   int NW;
   uint64_t win;  // dwords wi, wi+1
   int wi, off;   // bit position = 32*wi + off, 0 <= off < 32
-  __device__ __forceinline__ uint32_t fetch(int i) const { return i < NW ? slot[i] : 0u; }
+  __device__ __forceinline__ uint32_t fetch(int i) const {   // 0 past the slot, branch-free
+    const uint32_t v = slot[min(i, NW - 1)];
+    return i < NW ? v : 0u;
+  }
   __device__ __forceinline__ void init(const uint32_t *s, int nw) {
     slot = s;
     NW = nw;
@@ -210,11 +209,11 @@ struct BitReader {
   __device__ __forceinline__ int pos() const { return 32 * wi + off; }
   __device__ __forceinline__ void advance(int len) {  // off + len < 64
     off += len;
-    if (off >= 32) {
-      off -= 32;
-      wi++;
-      win = (win >> 32) | ((uint64_t)fetch(wi + 1) << 32);
-    }
+    const bool f = off >= 32;
+    const uint32_t nxt = fetch(wi + 2);
+    off -= f ? 32 : 0;
+    wi += f ? 1 : 0;
+    win = f ? ((win >> 32) | ((uint64_t)nxt << 32)) : win;
   }
   __device__ __forceinline__ uint32_t get(int len) {  // 1 <= len <= 32
     uint32_t v = (uint32_t)(win >> off) & (uint32_t)(len >= 32 ? 0xFFFFFFFFu : ((1u << len) - 1u));
@@ -273,6 +272,7 @@ __global__ __launch_bounds__(256) void k_encode(const float *__restrict__ in, in
   const int64_t b = b0 + threadIdx.x;
   const int nslots = (int)min<int64_t>(blockDim.x, nblocks - b0);
   uint32_t *my = lds_slots + threadIdx.x * (NW + 1);
+  for (int i = 0; i <= NW; i++) my[i] = 0u;   // own slot (+ pad); the writer only ORs in order
   if (b < nblocks) {
   const int64_t bx = b % nbx;
   const int64_t by = (b / nbx) % nby;
@@ -337,8 +337,13 @@ __global__ __launch_bounds__(256) void k_encode(const float *__restrict__ in, in
         uint64_t rest = x >> n;
         while (rest && w.pos() < BITS) {
           int tz = __builtin_ctzll(rest);
-          w.put(1u, 1);                      // group test: something left
-          w.put64(1ull << tz, tz + 1);       // tz zeros, then the set bit
+          // group test 1, then tz zeros and the set bit
+          if (tz < 62) {
+            w.put64(1ull | (2ull << tz), tz + 2);
+          } else {
+            w.put(1u, 1);
+            w.put64(1ull << tz, tz + 1);
+          }
           n += tz + 1;
           rest = (tz + 1 < 64) ? (rest >> (tz + 1)) : 0ull;
         }
@@ -346,7 +351,7 @@ __global__ __launch_bounds__(256) void k_encode(const float *__restrict__ in, in
       }
     }
   }
-  w.finish();
+  w.flush();
   }
   __syncthreads();
   // coalesced copy of the workgroup's slots to global memory

@@ -138,7 +138,7 @@ TimedKind timed_kind(const oc::Op &o) {
 int issue(oc_handle *h, const std::vector<oc::Op> &ops, const oc::Plan &p) {
   Exec x{h};
   const oc::Star7Coef c = coef_of(h->st);
-  uint64_t h2d = 0, d2h = 0, cells = 0, bdec = 0, benc = 0;
+  uint64_t h2d = 0, d2h = 0, cells = 0, bdec = 0, benc = 0, sbytes = 0;
   const uint64_t blocks_per_layer = (uint64_t)(p.in.nx / 4) * (uint64_t)(p.in.ny / 4);
   // timing: a pair of events around every timed op, recorded on its stream
   std::vector<std::pair<int, size_t>> timed;  // (kind, first event index)
@@ -191,11 +191,24 @@ int issue(oc_handle *h, const std::vector<oc::Op> &ops, const oc::Plan &p) {
       case oc::OP_STAR7: {
         // A^T: the neighbour coefficients swap direction, the diagonal stays
         const oc::Star7Coef ct{c.c0, c.cpx, c.cmx, c.cpy, c.cmy, c.cpz, c.cmz};
-        x.ok(oc::launch_star7((const float *)(h->arena + o.dev_src), (float *)(h->arena + o.dev_dst),
-                              o.dev_src2 >= 0 ? (const float *)(h->arena + o.dev_src2) : nullptr,
-                              p.in.nx, p.in.ny, o.z_lo, o.z_hi, o.gz0, p.in.nz,
-                              o.transpose ? ct : c, s));
-        cells += (uint64_t)(o.z_hi - o.z_lo) * (uint64_t)p.in.nx * (uint64_t)p.in.ny;
+        const float *c0p = o.dev_src2 >= 0 ? (const float *)(h->arena + o.dev_src2) : nullptr;
+        if (o.levels > 1)
+          x.ok(oc::launch_star7_multi((const float *)(h->arena + o.dev_src), (float *)(h->arena + o.dev_dst),
+                                      c0p, p.in.nx, p.in.ny, o.z_lo, o.z_hi, o.gz0, p.in.nz, o.levels,
+                                      o.transpose ? ct : c, s));
+        else
+          x.ok(oc::launch_star7((const float *)(h->arena + o.dev_src), (float *)(h->arena + o.dev_dst),
+                                c0p, p.in.nx, p.in.ny, o.z_lo, o.z_hi, o.gz0, p.in.nz,
+                                o.transpose ? ct : c, s));
+        {
+          // credited cell updates: levels x output planes; algorithmic bytes:
+          // the input range read once, the output range written once (+ c0)
+          const uint64_t pc = (uint64_t)p.in.nx * (uint64_t)p.in.ny;
+          const uint64_t out_planes = (uint64_t)(o.z_hi - o.z_lo);
+          const uint64_t in_planes = out_planes + 2u * (uint64_t)(o.levels * p.r);
+          cells += (uint64_t)o.levels * out_planes * pc;
+          sbytes += 4u * pc * (in_planes + out_planes + (c0p ? in_planes : 0u));
+        }
         break;
       }
       case oc::OP_AXPY:
@@ -208,13 +221,19 @@ int issue(oc_handle *h, const std::vector<oc::Op> &ops, const oc::Plan &p) {
                                (const float *)(h->arena + o.dev_src2), p.in.nx, p.in.ny, o.z_lo,
                                o.z_hi, o.gz0, p.in.nz, h->st.dt / h->st.h, h->st.src, amp, s));
         cells += (uint64_t)(o.z_hi - o.z_lo) * (uint64_t)p.in.nx * (uint64_t)p.in.ny;
+        sbytes += 16u * (uint64_t)(o.z_hi - o.z_lo) * (uint64_t)p.in.nx * (uint64_t)p.in.ny;
         break;
       }
       case oc::OP_REC:
-        x.ok(hipEventRecord(h->ev[o.ev], s));
-        break;
       case oc::OP_WAIT:
-        x.ok(hipStreamWaitEvent(s, h->ev[o.ev], 0));
+        if (o.ev < 0 || (size_t)o.ev >= h->ev.size()) {
+          x.st = OC_ERR_STATE;   // an event the handle does not own: never issue it
+          break;
+        }
+        if (o.type == oc::OP_REC)
+          x.ok(hipEventRecord(h->ev[o.ev], s));
+        else
+          x.ok(hipStreamWaitEvent(s, h->ev[o.ev], 0));
         break;
       case oc::OP_SYNC:
         for (int i = 0; i < 3; i++) x.ok(hipStreamSynchronize(h->s[i]));
@@ -229,6 +248,7 @@ int issue(oc_handle *h, const std::vector<oc::Op> &ops, const oc::Plan &p) {
   h->stats.bytes_h2d = h2d;
   h->stats.bytes_d2h = d2h;
   h->stats.cells_stencil = cells;
+  h->stats.bytes_stencil = sbytes;
   h->stats.blocks_decode = bdec;
   h->stats.blocks_encode = benc;
   double ms[5] = {0, 0, 0, 0, 0};
@@ -413,7 +433,7 @@ int oc_star7_incore(const float *d_in, float *d_out, float *d_tmp, int64_t nx, i
                     int64_t nz, const float *c, const float *d_c0f, int64_t steps,
                     oc_stream stream) {
   if (!d_in || !d_out || !c || nx <= 0 || ny <= 0 || nz <= 0 || steps < 0) return OC_ERR_ARG;
-  if (steps > 1 && !d_tmp) return OC_ERR_ARG;
+  if (steps > oc::kMaxFusedSteps && !d_tmp) return OC_ERR_ARG;
   if (nx > (1 << 30) || ny > (1 << 30) || nz > (1 << 30)) return OC_ERR_ARG;
   hipStream_t s = (hipStream_t)stream;
   oc::Star7Coef cf{c[0], c[1], c[2], c[3], c[4], c[5], c[6]};
@@ -421,13 +441,20 @@ int oc_star7_incore(const float *d_in, float *d_out, float *d_tmp, int64_t nx, i
   if (steps == 0) {
     e = hipMemcpyAsync(d_out, d_in, (size_t)(nx * ny * nz) * 4u, hipMemcpyDeviceToDevice, s);
   } else {
-    float *X = (steps % 2 == 1) ? d_out : d_tmp;
-    float *Y = (steps % 2 == 1) ? d_tmp : d_out;
+    // groups of up to kMaxFusedSteps fused steps, ping-ponging so that the
+    // last group writes d_out
+    const int64_t groups = (steps + oc::kMaxFusedSteps - 1) / oc::kMaxFusedSteps;
+    float *X = (groups % 2 == 1) ? d_out : d_tmp;
+    float *Y = (groups % 2 == 1) ? d_tmp : d_out;
     const float *src = d_in;
-    for (int64_t i = 1; i <= steps && e == hipSuccess; i++) {
-      float *dst = (i % 2 == 1) ? X : Y;
-      e = oc::launch_star7(src, dst, d_c0f, nx, ny, 0, nz, 0, nz, cf, s);
+    int64_t done = 0;
+    for (int64_t gi = 1; gi <= groups && e == hipSuccess; gi++) {
+      const int lv = (int)std::min<int64_t>(oc::kMaxFusedSteps, steps - done);
+      float *dst = (gi % 2 == 1) ? X : Y;
+      e = lv > 1 ? oc::launch_star7_multi(src, dst, d_c0f, nx, ny, 0, nz, 0, nz, lv, cf, s)
+                 : oc::launch_star7(src, dst, d_c0f, nx, ny, 0, nz, 0, nz, cf, s);
       src = dst;
+      done += lv;
     }
   }
   if (e != hipSuccess) {
@@ -606,6 +633,20 @@ namespace {
 
 size_t align4k(size_t x) { return (x + 4095) & ~(size_t)4095; }
 
+// Grows the handle's event pool to n events.
+int ensure_events(oc_handle *h, size_t n) {
+  while (h->ev.size() < n) {
+    hipEvent_t e = nullptr;
+    hipError_t err = hipEventCreateWithFlags(&e, hipEventDisableTiming);
+    if (err != hipSuccess) {
+      g_last_hip = err;
+      return OC_ERR_HIP;
+    }
+    h->ev.push_back(e);
+  }
+  return OC_OK;
+}
+
 int adj_plan_for(const oc_handle *h, int64_t steps, int32_t every, int32_t rate, oc::AdjPlan *a) {
   if (h->plan.in.kind != oc::KIND_STAR7) return OC_ERR_UNSUPPORTED;
   if (h->plan.coded) return OC_ERR_UNSUPPORTED;     // the forward of the adjoint runs raw
@@ -694,6 +735,12 @@ int oc_adjoint(oc_handle *h, const float *gT, float *g_u0, float *g_c0) {
   h->host[oc::HOST_CKPT] = w + h->adj_off[0];
   h->host[oc::HOST_GRAD] = grad;
   for (int i : {0, 1, (int)oc::HOST_CKPT, (int)oc::HOST_GRAD}) h->host_dev[i] = mapped_host(h->host[i]);
+  const int er = ensure_events(h, (size_t)oc::EventIds{(int)a.g.slabs.size()}.count());
+  if (er) {
+    std::memcpy(h->host, saved, sizeof saved);
+    std::memcpy(h->host_dev, saved_dev, sizeof saved_dev);
+    return er;
+  }
   std::vector<oc::Op> ops;
   oc::build_adjoint_ops(a, 0, &ops);
   auto t0 = std::chrono::steady_clock::now();

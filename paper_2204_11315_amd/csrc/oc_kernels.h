@@ -26,6 +26,14 @@ hipError_t launch_star7(const float *in, float *out, const float *c0f, int64_t n
                         int64_t z_lo, int64_t z_hi, int64_t gz0, int64_t nz, const Star7Coef &c,
                         hipStream_t s);
 
+// `levels` (1..4) fused 7-point steps: writes level `levels` on local planes
+// [zo_lo, zo_hi) of out, reading in on [zo_lo - levels, zo_hi + levels).
+// Bit-identical to `levels` single steps over shrinking ranges.
+constexpr int kMaxFusedSteps = 4;
+hipError_t launch_star7_multi(const float *in, float *out, const float *c0f, int64_t nx, int64_t ny,
+                              int64_t zo_lo, int64_t zo_hi, int64_t gz0, int64_t nz, int levels,
+                              const Star7Coef &c, hipStream_t s);
+
 // g[i] += a[i] * b[i] for i < n.
 hipError_t launch_axpy_prod(float *g, const float *a, const float *b, size_t n, hipStream_t s);
 

@@ -179,6 +179,7 @@ struct Builder {
     o.host_id = -1;
     o.ev = -1;
     o.dev_src = o.dev_src2 = o.dev_dst = -1;
+    o.levels = 1;
     return o;
   }
   void push(const Op &o) {
@@ -363,19 +364,25 @@ void build_ops(const Plan &p, int64_t sweeps, int steps_last, int src, int64_t s
     const int64_t dom_hi = std::min<int64_t>(x.sl->planes, p.in.nz - x.sl->gz0);
     int cur_a = 0, cur_b = 1;   // STAR7 ping-pong
     int wa = bpa, wb = bpb;     // WAVE25: wa holds p^{n-1}, wb holds p^n
-    for (int st = 1; st <= x.ks; st++) {
-      const int64_t grow = (int64_t)(x.ks - st) * p.r;
+    // STAR7: the k steps go in groups of up to kMaxFused fused steps; a group
+    // ending after step s1 writes its last level on the planes the remaining
+    // k - s1 steps still need
+    const int group = wave ? 1 : kMaxFused;
+    for (int s0 = 0; s0 < x.ks; s0 += group) {
+      const int s1 = std::min(x.ks, s0 + group);
+      const int64_t grow = (int64_t)(x.ks - s1) * p.r;
       Op o = B.blank(wave ? OP_WAVE : OP_STAR7, S_COMPUTE);
       if (wave) {
         o.dev_src = (int64_t)B.work(x.q, wb);     // p^n
         o.dev_dst = (int64_t)B.work(x.q, wa);     // p^{n-1} -> p^{n+1}
         o.dev_src2 = (int64_t)B.work(x.q, bv);    // velocity
-        o.step = step0 + (int64_t)x.t * p.in.k + (st - 1);
+        o.step = step0 + (int64_t)x.t * p.in.k + s0;
         std::swap(wa, wb);
       } else {
         o.dev_src = (int64_t)B.work(x.q, cur_a);
         o.dev_dst = (int64_t)B.work(x.q, cur_b);
         o.dev_src2 = p.in.c0_field ? (int64_t)B.work(x.q, 2) : -1;
+        o.levels = s1 - s0;
         std::swap(cur_a, cur_b);
       }
       o.z_lo = std::max<int64_t>(p.halo - grow, dom_lo);
@@ -700,7 +707,7 @@ void build_adjoint_ops(const AdjPlan &a, int lsrc, std::vector<Op> *ops) {
 }
 
 std::string dump_ops(const std::vector<Op> &ops) {
-  static const char *names[] = {"H2D", "D2H", "DEC", "ENC", "STAR7", "WAVE", "REC", "WAIT", "SYNC"};
+  static const char *names[] = {"H2D", "D2H", "DEC", "ENC", "STAR7", "WAVE", "AXPY", "REC", "WAIT", "SYNC"};
   std::string out;
   char line[256];
   for (size_t i = 0; i < ops.size(); i++) {
@@ -708,9 +715,10 @@ std::string dump_ops(const std::vector<Op> &ops) {
     if (o.type == OP_REC || o.type == OP_WAIT)
       snprintf(line, sizeof line, "%zu s%d %s ev=%d\n", i, o.stream, names[o.type], o.ev);
     else
-      snprintf(line, sizeof line, "%zu s%d %s sweep=%d slab=%d src=%lld dst=%lld host=%d off=%lld bytes=%lld z=[%lld,%lld)\n",
+      snprintf(line, sizeof line, "%zu s%d %s sweep=%d slab=%d src=%lld dst=%lld host=%d off=%lld bytes=%lld z=[%lld,%lld) lv=%d\n",
                i, o.stream, names[o.type], o.sweep, o.slab, (long long)o.dev_src, (long long)o.dev_dst,
-               o.host_id, (long long)o.host_off, (long long)o.bytes, (long long)o.z_lo, (long long)o.z_hi);
+               o.host_id, (long long)o.host_off, (long long)o.bytes, (long long)o.z_lo, (long long)o.z_hi,
+               (int)o.levels);
     out += line;
   }
   return out;
@@ -765,9 +773,14 @@ void accesses(const Plan &p, const Op &o, std::vector<Access> *a) {
       // reads planes [z_lo - r, z_hi + r) of the source (and the aux buffer),
       // writes [z_lo, z_hi) of the destination; WAVE also reads the destination
       int64_t pb = (int64_t)p.plane_bytes;
-      int64_t rlo = std::max<int64_t>(0, o.z_lo - p.r), rhi = std::min<int64_t>(o.planes, o.z_hi + p.r);
+      const int64_t reach = (int64_t)p.r * o.levels;
+      int64_t rlo = std::max<int64_t>(0, o.z_lo - reach), rhi = std::min<int64_t>(o.planes, o.z_hi + reach);
       dev(o.dev_src + rlo * pb, (rhi - rlo) * pb, false);
-      if (o.dev_src2 >= 0) dev(o.dev_src2 + o.z_lo * pb, (o.z_hi - o.z_lo) * pb, false);
+      if (o.dev_src2 >= 0) {
+        const int64_t clo = std::max<int64_t>(0, o.z_lo - reach + p.r);
+        const int64_t chi = std::min<int64_t>(o.planes, o.z_hi + reach - p.r);
+        dev(o.dev_src2 + clo * pb, (chi - clo) * pb, false);
+      }
       if (o.type == OP_WAVE) dev(o.dev_dst + o.z_lo * pb, (o.z_hi - o.z_lo) * pb, false);
       dev(o.dev_dst + o.z_lo * pb, (o.z_hi - o.z_lo) * pb, true);
       break;

@@ -45,6 +45,7 @@ struct Op {
   int64_t planes;       // planes of the slab buffer (extent for the hazard model)
   int64_t step;         // WAVE: global time index n of p^n (source term)
   bool transpose;       // STAR7: apply A^T (the -/+ coefficients swapped)
+  int32_t levels;       // STAR7: fused time steps in this launch (z_lo..z_hi = output planes)
   int32_t slab, sweep;  // bookkeeping (tests, stats)
 };
 
@@ -69,6 +70,7 @@ struct PlanInput {
 };
 
 constexpr int kMaxSlots = 8;
+constexpr int kMaxFused = 4;   // time steps one 7-point launch may fuse
 
 struct Plan {
   PlanInput in;

@@ -59,7 +59,8 @@ class Stats(ctypes.Structure):
                 ("ms_d2h", ctypes.c_double), ("n_decode", ctypes.c_uint64),
                 ("n_stencil", ctypes.c_uint64), ("n_encode", ctypes.c_uint64),
                 ("n_h2d", ctypes.c_uint64), ("n_d2h", ctypes.c_uint64),
-                ("cells_stencil", ctypes.c_uint64), ("blocks_decode", ctypes.c_uint64),
+                ("cells_stencil", ctypes.c_uint64), ("bytes_stencil", ctypes.c_uint64),
+                ("blocks_decode", ctypes.c_uint64),
                 ("blocks_encode", ctypes.c_uint64)]
 
 

@@ -3,7 +3,9 @@
 Loss L = 1/2 sum over the top plane of u_T^2.  Checked against the FP64
 oracle's gradients (raw checkpoints: 1e-5; 16-bit codes: 1e-3), against
 central finite differences of the GPU forward on random directions (the loss
-is exactly quadratic in u0), and through torch.autograd.
+is exactly quadratic in u0; along c0 the differences are Richardson
+extrapolated, since the loss is a polynomial of degree 2*steps in c0), and
+through torch.autograd.
 """
 import numpy as np
 import pytest
@@ -68,6 +70,9 @@ def test_directional_derivatives_vs_central_differences():
         fwd.run(STEPS)
         return 0.5 * float(np.sum(fwd.store()[-1].astype(np.float64) ** 2))
 
+    def central(f, eps):
+        return (f(eps) - f(-eps)) / (2 * eps)
+
     rng = np.random.default_rng(43)
     want, got = [], []
     try:
@@ -75,10 +80,14 @@ def test_directional_derivatives_vs_central_differences():
             d = rng.standard_normal(SHAPE)
             e = inputs.smooth_direction(SHAPE, rng)
             eu = 1e-2 * np.sqrt(np.mean(u0.astype(np.float64) ** 2)) / np.sqrt(np.mean(d ** 2))
-            ec = 1e-2 * np.sqrt(np.mean(c0.astype(np.float64) ** 2)) / np.sqrt(np.mean(e ** 2))
-            want.append((loss(u0 + eu * d, c0) - loss(u0 - eu * d, c0)) / (2 * eu))
+            ec = 2e-3 * np.sqrt(np.mean(c0.astype(np.float64) ** 2)) / np.sqrt(np.mean(e ** 2))
+            # L is quadratic in u0: the central difference is exact up to rounding
+            want.append(central(lambda t: loss(u0 + t * d, c0), eu))
             got.append(np.vdot(g_u0.astype(np.float64), d))
-            want.append((loss(u0, c0 + ec * e) - loss(u0, c0 - ec * e)) / (2 * ec))
+            # L has degree 2*STEPS in c0: Richardson-extrapolated central
+            # differences (truncation O(eps^4))
+            fc = lambda t: loss(u0, c0 + t * e)
+            want.append((4 * central(fc, ec / 2) - central(fc, ec)) / 3)
             got.append(np.vdot(g_c0.astype(np.float64), e))
     finally:
         fwd.close()

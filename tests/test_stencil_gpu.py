@@ -58,3 +58,19 @@ def test_zero_and_one_step():
     assert np.array_equal(oc.star7_incore(_dev(u0), C, 0).cpu().numpy(), u0)
     got = oc.star7_incore(_dev(u0), C, 1).cpu().numpy()
     assert rel_l2(got, oracle.star7_run(u0, C, 1)) <= 1e-6
+
+
+@pytest.mark.parametrize("steps", [2, 3, 4, 7])
+def test_fused_steps_equal_single_steps_bitwise(steps):
+    shape = (21, 37, 131)          # ragged against the 56x8 (and 58x10 ...) output tiles
+    rng = np.random.default_rng(5)
+    u0 = rng.standard_normal(shape).astype(np.float32)
+    c = (0.3, 0.05, 0.15, 0.07, 0.13, 0.11, 0.09)
+    c0f = _dev(inputs.c0_field(shape))
+    for field in (None, c0f):
+        fused = oc.star7_incore(_dev(u0), c, steps, c0f=field).cpu().numpy()
+        u = _dev(u0)
+        for _ in range(steps):
+            u = oc.star7_incore(u, c, 1, c0f=field)
+        single = u.cpu().numpy()
+        assert np.array_equal(fused.view(np.uint32), single.view(np.uint32))
