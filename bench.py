@@ -30,7 +30,6 @@ sys.path.insert(0, ROOT)
 C = (0.4, 0.1, 0.1, 0.1, 0.1, 0.1, 0.1)
 SHAPE = (2048, 512, 512)
 K, S, STEPS, BUDGET = 4, 64, 64, 512 << 20
-HBM_PEAK_GBS = 8000.0
 
 
 def log(msg):
@@ -48,24 +47,31 @@ def rel_l2(a, b):
     return (d / n) ** 0.5
 
 
-def sample_points(n=16, seed=21):
+def sample_points(n=192, seed=21):
+    """Cells drawn uniformly over the grid (boundary cells included as drawn)."""
     rng = np.random.default_rng(seed)
-    pts = [(0, 0, 0), (SHAPE[0] - 1, SHAPE[1] - 1, SHAPE[2] - 1), (S, 256, 256), (S - 1, 10, 500)]
-    while len(pts) < n:
-        pts.append(tuple(int(rng.integers(0, m)) for m in SHAPE))
-    return pts
+    return [tuple(int(rng.integers(0, m)) for m in SHAPE) for _ in range(n)]
 
 
 def sampled_reference(u0, pts):
-    """FP64 oracle values at sample cells: each advances only the box of its
-    dependency cone (half-width = number of steps), clipped to the grid."""
+    """FP64 oracle values at sample cells, each exact: the box of the cell's
+    dependency cone (half-width = number of steps, clipped to the grid) is
+    advanced one step at a time and trimmed by one cell on every face that is
+    not a grid face, so only cells whose inputs are all inside the box remain."""
     import oracle
     vals = []
     for (z, y, x) in pts:
         lo = [max(0, v - STEPS) for v in (z, y, x)]
         hi = [min(m, v + STEPS + 1) for v, m in zip((z, y, x), SHAPE)]
-        r = oracle.star7_run(u0[lo[0]:hi[0], lo[1]:hi[1], lo[2]:hi[2]], C, STEPS)
-        vals.append(r[z - lo[0], y - lo[1], x - lo[2]])
+        box = u0[lo[0]:hi[0], lo[1]:hi[1], lo[2]:hi[2]]
+        for _ in range(STEPS):
+            box = oracle.star7_run(box, C, 1)
+            cut = [slice(1 if lo[d] > 0 else 0, box.shape[d] - (1 if hi[d] < SHAPE[d] else 0))
+                   for d in range(3)]
+            box = box[tuple(cut)]
+            lo = [lo[d] + (1 if lo[d] > 0 else 0) for d in range(3)]
+            hi = [hi[d] - (1 if hi[d] < SHAPE[d] else 0) for d in range(3)]
+        vals.append(box[z - lo[0], y - lo[1], x - lo[2]])
     return np.array(vals)
 
 
@@ -112,14 +118,37 @@ def run_leg(oc, torch, u0, rate, steps, warmup, ref=None, timing=True):
         o.close()
 
 
+# Peaks of one MI355X: HBM3E 8 TB/s; 32-bit vector ALU = 256 CUs x 4 SIMDs x
+# 16 lanes x 2.4 GHz = 39.3 T lane-ops/s (one wave64 VALU instruction per CU
+# per cycle; the FP32 rate of 157.3 TFLOP/s counts packed FMA as 4 flops).
+HBM_PEAK_GBS = 8000.0
+ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+
+# Per-kernel work figures measured with rocprofv3 on the slab-shaped kernel
+# probe (`bench.py --kernels --rate R`), one figure per code rate:
+# VALU wave-instructions per wave of 64 blocks (SQ_INSTS_VALU / SQ_WAVES).
+VALU_PER_WAVE = {("decode", 9): 4384.6, ("encode", 9): 5624.2,
+                 ("decode", 16): 4794.2, ("encode", 16): 6068.8}
+# HBM bytes per launch relative to the algorithmic bytes: FETCH_SIZE and
+# WRITE_SIZE of the slab-shaped probe launches (72 planes of 512 x 512), each
+# scaled by what the counter reads for a plain 256 MiB device copy (FETCH x 2,
+# WRITE x 1 KiB per unit).  Single-step stencil: 84.8 MB fetched for 75.5 MB
+# read, 75.5 MB written for 75.5 MB -> 1.06.  Decode at R = 16: 1.02 / 1.00;
+# encode at R = 16: 1.01 / 1.01.  None = not measured for the kernel as it
+# stands at this rate.
+TRAFFIC_RATIO = {"stencil": 1.06, "decode": None, "encode": None}
+
+
 def kernel_roofline(stats, rate):
-    """Per-kernel averages over the timed runs; algorithmic bytes per launch:
-    decode reads 8R B and writes 256 B per 4x4x4 block, encode the reverse;
-    a (fused) stencil launch reads its input plane range once and writes its
-    output range once (as counted by the library)."""
+    """Per-kernel averages over the timed runs.  Algorithmic bytes per launch:
+    decode reads 8R B and writes 256 B per 4x4x4 block, encode the reverse; a
+    stencil launch reads its input plane range once and writes its output range
+    once (as counted by the library).  Codec launches also carry their VALU
+    issue rate where the instruction count per block is known for this rate."""
     tot = {"decode": 0.0, "encode": 0.0, "stencil": 0.0}
     cnt = {"decode": 0, "encode": 0, "stencil": 0}
     byt = {"decode": 0.0, "encode": 0.0, "stencil": 0.0}
+    blk = {"decode": 0, "encode": 0, "stencil": 0}
     for s in stats:
         for k in tot:
             tot[k] += s["ms_" + k]
@@ -127,14 +156,39 @@ def kernel_roofline(stats, rate):
         byt["decode"] += s["blocks_decode"] * (8 * rate + 256)
         byt["encode"] += s["blocks_encode"] * (256 + 8 * rate)
         byt["stencil"] += s["bytes_stencil"]
+        blk["decode"] += s["blocks_decode"]
+        blk["encode"] += s["blocks_encode"]
     per = {}
     for k in tot:
         if cnt[k]:
             avg_ms = tot[k] / cnt[k]
             per_launch = byt[k] / cnt[k]
-            per[k] = {"avg_ms": avg_ms, "launches": cnt[k], "bytes_per_launch": per_launch,
-                      "gbs": per_launch / (avg_ms * 1e-3) / 1e9, "total_ms": tot[k]}
+            d = {"avg_ms": avg_ms, "launches": cnt[k], "bytes_per_launch": per_launch,
+                 "gbs": per_launch / (avg_ms * 1e-3) / 1e9, "total_ms": tot[k]}
+            vw = VALU_PER_WAVE.get((k, rate))
+            if vw is not None:
+                lane_ops = vw * 64 * (blk[k] / 64.0) / cnt[k]      # per launch
+                d["valu_lane_ops_per_launch"] = lane_ops
+                d["valu_tops"] = lane_ops / (avg_ms * 1e-3) / 1e12
+            per[k] = d
     return per
+
+
+def roofline_of(kern):
+    """The roofline object of the kernel with the largest total time."""
+    dom = max(kern, key=lambda k: kern[k]["total_ms"])
+    d = kern[dom]
+    ratio = TRAFFIC_RATIO.get(dom)
+    traffic = ratio * d["bytes_per_launch"] if ratio is not None else None
+    if dom == "stencil" or "valu_tops" not in d:
+        return {"bound": "hbm", "kernel": dom, "achieved": d["gbs"], "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": d["gbs"] / HBM_PEAK_GBS, "traffic": traffic,
+                "avg_launch_ms": d["avg_ms"], "bytes_per_launch": d["bytes_per_launch"]}
+    return {"bound": "alu", "kernel": dom, "achieved": d["valu_tops"], "peak": ALU_PEAK_TOPS,
+            "unit": "T lane-ops/s (32-bit VALU)", "frac": d["valu_tops"] / ALU_PEAK_TOPS,
+            "traffic": traffic, "avg_launch_ms": d["avg_ms"],
+            "bytes_per_launch": d["bytes_per_launch"], "hbm_gbs": d["gbs"],
+            "valu_lane_ops_per_launch": d["valu_lane_ops_per_launch"]}
 
 
 def cpu_baseline(u0, rate):
@@ -315,7 +369,7 @@ def main():
     ap.add_argument("--budget", type=float, default=1e-3, help="rel-L2 error budget vs FP64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--error", choices=["none", "sampled", "full"], default="sampled",
-                    help="FP64 oracle reference over the full grid or at 16 sample cells")
+                    help="FP64 oracle reference over the full grid or at 192 sample cells")
     ap.add_argument("--kernels", action="store_true",
                     help="launch each hot kernel at slab shape (for rocprofv3), then exit")
     ap.add_argument("--workload", choices=["star7", "wave", "adjoint"], default="star7")
@@ -378,12 +432,7 @@ def main():
         head = ok[0] if ok else max(cands)
     main_leg = legs[head]
     base_leg = legs[0]
-    kern = main_leg["kernels"]
-    dom = max(kern, key=lambda k: kern[k]["total_ms"])
-    roof = {"bound": "hbm", "kernel": dom, "achieved": kern[dom]["gbs"], "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": kern[dom]["gbs"] / HBM_PEAK_GBS, "traffic": None,
-            "avg_launch_ms": kern[dom]["avg_ms"],
-            "bytes_per_launch": kern[dom]["bytes_per_launch"]}
+    roof = roofline_of(main_leg["kernels"])
     cpu = None
     if not args.no_cpu_baseline:
         t0 = time.perf_counter()

@@ -83,6 +83,11 @@ typedef struct {
   int32_t ring_slots;      /* staging buffers in the copy ring, 2..8; 0 = 3 (Sec. 5)       */
   int32_t prefetch;        /* slabs copied in ahead of the kernels, 1..ring_slots-1;
                               0 = ring_slots - 1                                           */
+  int32_t fuse_steps;      /* 7-point: time steps per stencil launch, 1..4 (one kernel
+                              marches all of them through LDS); 0 = 1                      */
+  int32_t copy_back;       /* device-to-host copies: n > 0 = a copy kernel of n workgroups
+                              (1..1024) storing into the mapped pinned host pages; 0 = such a
+                              kernel with 4 workgroups; -1 = the runtime's hipMemcpyAsync   */
 } oc_config;
 
 typedef struct {
@@ -102,6 +107,10 @@ typedef struct {
   uint64_t bytes_stencil;  /* algorithmic HBM bytes of those launches (input range read once,
                               output range written once, coefficient / velocity fields)    */
   uint64_t blocks_decode, blocks_encode;  /* 4x4x4 blocks coded                           */
+  /* host wall time the last oc_run spent inside HIP calls: kernel launches
+   * (including the copy-back kernel), host<->device copy calls, event record /
+   * wait calls, and the final stream synchronisation (always measured)     */
+  double host_ms_kernels, host_ms_copies, host_ms_events, host_ms_sync;
 } oc_stats;
 
 /* Bytes one host level needs for this grid / stencil / rate (raw FP32 planes,
@@ -228,6 +237,15 @@ int64_t oc_debug_check_adjoint(const oc_grid *g, const oc_stencil *st, const oc_
 /* Operations in that list; *n_waits receives the number of stream waits. */
 int64_t oc_debug_plan_ops(const oc_grid *g, const oc_stencil *st, const oc_config *cfg,
                           int64_t sweeps, int64_t *n_waits);
+
+/* GPU timeline of the last oc_run (timing on): for each timed op, its class
+ * (0 decode, 1 stencil, 2 encode, 3 host-to-device, 4 device-to-host), its
+ * sweep * 100000 + slab, and its start / end in ms after the first timed op
+ * started, from the op's own event pair.  With null arrays or cap <= 0,
+ * returns the number of timed ops; else fills min(n, cap) entries and returns
+ * that count.  Test and tuning aid. */
+int64_t oc_debug_timeline(const oc_handle *h, int32_t *kind, int64_t *slab, double *start_ms,
+                          double *end_ms, int64_t cap);
 
 #ifdef __cplusplus
 }

@@ -441,25 +441,27 @@ size_t codec_lds_bytes(int rate, int threads) { return (size_t)threads * (size_t
 namespace oc {
 
 hipError_t launch_encode(const float *d_in, int64_t nx, int64_t ny, int64_t nlayers, int rate,
-                         void *d_out, hipStream_t s) {
+                         void *d_out, hipStream_t s, KernelTimer *kt) {
   if (rate < 1 || rate > 32) return hipErrorInvalidValue;
   const int64_t nbx = nx / 4, nby = ny / 4, nb = nbx * nby * nlayers;
   if (nb <= 0) return hipSuccess;
   const int threads = codec_threads(rate);
   dim3 grid((unsigned)((nb + threads - 1) / threads));
-  hipLaunchKernelGGL(k_encode, grid, dim3(threads), codec_lds_bytes(rate, threads), s, d_in, nx, ny,
+  hipExtLaunchKernelGGL(k_encode, grid, dim3(threads), codec_lds_bytes(rate, threads), s, kt_start(kt),
+                        kt_stop(kt), 0, d_in, nx, ny,
                      nbx, nby, nb, rate, (uint32_t *)d_out);
   return hipGetLastError();
 }
 
 hipError_t launch_decode(const void *d_in, int64_t nx, int64_t ny, int64_t nlayers, int rate,
-                         float *d_out, hipStream_t s) {
+                         float *d_out, hipStream_t s, KernelTimer *kt) {
   if (rate < 1 || rate > 32) return hipErrorInvalidValue;
   const int64_t nbx = nx / 4, nby = ny / 4, nb = nbx * nby * nlayers;
   if (nb <= 0) return hipSuccess;
   const int threads = codec_threads(rate);
   dim3 grid((unsigned)((nb + threads - 1) / threads));
-  hipLaunchKernelGGL(k_decode, grid, dim3(threads), codec_lds_bytes(rate, threads), s,
+  hipExtLaunchKernelGGL(k_decode, grid, dim3(threads), codec_lds_bytes(rate, threads), s, kt_start(kt),
+                        kt_stop(kt), 0,
                      (const uint32_t *)d_in, nx, ny, nbx, nby, nb, rate, d_out);
   return hipGetLastError();
 }

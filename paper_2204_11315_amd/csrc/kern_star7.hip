@@ -163,7 +163,7 @@ __global__ __launch_bounds__(FX *FY) void k_star7_multi(const float *__restrict_
 template <int K>
 hipError_t launch_multi(const float *in, float *out, const float *c0f, int64_t nx, int64_t ny,
                         int64_t zo_lo, int64_t zo_hi, int64_t gz0, int64_t nz, const oc::Star7Coef &c,
-                        hipStream_t s) {
+                        hipStream_t s, oc::KernelTimer *kt) {
   constexpr int OX = FX - 2 * K, OY = FY - 2 * K;
   const int nbx = (int)((nx + OX - 1) / OX);
   const int nby = (int)((ny + OY - 1) / OY);
@@ -171,10 +171,12 @@ hipError_t launch_multi(const float *in, float *out, const float *c0f, int64_t n
   const int64_t nb = (int64_t)nbx * nby * nbz;
   if (nb > 0x7fffffff) return hipErrorInvalidValue;
   if (c0f)
-    hipLaunchKernelGGL((k_star7_multi<K, true>), dim3((unsigned)nb), dim3(FX, FY), 0, s, in, out, c0f,
+    hipExtLaunchKernelGGL((k_star7_multi<K, true>), dim3((unsigned)nb), dim3(FX, FY), 0, s, oc::kt_start(kt),
+                          oc::kt_stop(kt), 0, in, out, c0f,
                        (int)nx, (int)ny, (int)zo_lo, (int)zo_hi, (int)gz0, (int)nz, nbx, nby, nbz, c);
   else
-    hipLaunchKernelGGL((k_star7_multi<K, false>), dim3((unsigned)nb), dim3(FX, FY), 0, s, in, out, c0f,
+    hipExtLaunchKernelGGL((k_star7_multi<K, false>), dim3((unsigned)nb), dim3(FX, FY), 0, s, oc::kt_start(kt),
+                          oc::kt_stop(kt), 0, in, out, c0f,
                        (int)nx, (int)ny, (int)zo_lo, (int)zo_hi, (int)gz0, (int)nz, nbx, nby, nbz, c);
   return hipGetLastError();
 }
@@ -193,27 +195,29 @@ namespace oc {
 
 hipError_t launch_star7_multi(const float *in, float *out, const float *c0f, int64_t nx, int64_t ny,
                               int64_t zo_lo, int64_t zo_hi, int64_t gz0, int64_t nz, int levels,
-                              const Star7Coef &c, hipStream_t s) {
+                              const Star7Coef &c, hipStream_t s, KernelTimer *kt) {
   if (zo_hi <= zo_lo) return hipSuccess;
   switch (levels) {
-    case 1: return launch_multi<1>(in, out, c0f, nx, ny, zo_lo, zo_hi, gz0, nz, c, s);
-    case 2: return launch_multi<2>(in, out, c0f, nx, ny, zo_lo, zo_hi, gz0, nz, c, s);
-    case 3: return launch_multi<3>(in, out, c0f, nx, ny, zo_lo, zo_hi, gz0, nz, c, s);
-    case 4: return launch_multi<4>(in, out, c0f, nx, ny, zo_lo, zo_hi, gz0, nz, c, s);
+    case 1: return launch_multi<1>(in, out, c0f, nx, ny, zo_lo, zo_hi, gz0, nz, c, s, kt);
+    case 2: return launch_multi<2>(in, out, c0f, nx, ny, zo_lo, zo_hi, gz0, nz, c, s, kt);
+    case 3: return launch_multi<3>(in, out, c0f, nx, ny, zo_lo, zo_hi, gz0, nz, c, s, kt);
+    case 4: return launch_multi<4>(in, out, c0f, nx, ny, zo_lo, zo_hi, gz0, nz, c, s, kt);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_axpy_prod(float *g, const float *a, const float *b, size_t n, hipStream_t s) {
+hipError_t launch_axpy_prod(float *g, const float *a, const float *b, size_t n, hipStream_t s,
+                            KernelTimer *kt) {
   if (!n) return hipSuccess;
   const size_t blocks = std::min<size_t>((n + 255) / 256, 4096);
-  hipLaunchKernelGGL(k_axpy_prod, dim3((unsigned)blocks), dim3(256), 0, s, g, a, b, n);
+  hipExtLaunchKernelGGL(k_axpy_prod, dim3((unsigned)blocks), dim3(256), 0, s, kt_start(kt), kt_stop(kt), 0,
+                        g, a, b, n);
   return hipGetLastError();
 }
 
 hipError_t launch_star7(const float *in, float *out, const float *c0f, int64_t nx, int64_t ny,
                         int64_t z_lo, int64_t z_hi, int64_t gz0, int64_t nz, const Star7Coef &c,
-                        hipStream_t s) {
+                        hipStream_t s, KernelTimer *kt) {
   if (z_hi <= z_lo) return hipSuccess;
   const int nbx = (int)((nx + TX - 1) / TX);
   const int nby = (int)((ny + TY - 1) / TY);
@@ -222,10 +226,12 @@ hipError_t launch_star7(const float *in, float *out, const float *c0f, int64_t n
   if (nb > 0x7fffffff) return hipErrorInvalidValue;
   dim3 grid((unsigned)nb);
   if (c0f)
-    hipLaunchKernelGGL(k_star7<true>, grid, dim3(TX, TY), 0, s, in, out, c0f, (int)nx, (int)ny,
+    hipExtLaunchKernelGGL(k_star7<true>, grid, dim3(TX, TY), 0, s, kt_start(kt), kt_stop(kt), 0, in, out,
+                          c0f, (int)nx, (int)ny,
                        (int)z_lo, (int)z_hi, (int)gz0, (int)nz, nbx, nby, nbz, c);
   else
-    hipLaunchKernelGGL(k_star7<false>, grid, dim3(TX, TY), 0, s, in, out, c0f, (int)nx, (int)ny,
+    hipExtLaunchKernelGGL(k_star7<false>, grid, dim3(TX, TY), 0, s, kt_start(kt), kt_stop(kt), 0, in, out,
+                          c0f, (int)nx, (int)ny,
                        (int)z_lo, (int)z_hi, (int)gz0, (int)nz, nbx, nby, nbz, c);
   return hipGetLastError();
 }

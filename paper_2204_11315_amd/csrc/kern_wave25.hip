@@ -86,13 +86,14 @@ namespace oc {
 
 hipError_t launch_wave25(const float *pn, float *pnm1, const float *vel, int64_t nx, int64_t ny,
                          int64_t z_lo, int64_t z_hi, int64_t gz0, int64_t nz, float dt_h,
-                         const int64_t *src, float src_amp, hipStream_t s) {
+                         const int64_t *src, float src_amp, hipStream_t s, KernelTimer *kt) {
   if (z_hi <= z_lo) return hipSuccess;
   dim3 grid((unsigned)((nx + TX - 1) / TX), (unsigned)((ny + TY - 1) / TY),
             (unsigned)((z_hi - z_lo + ZC - 1) / ZC));
   const bool has_src = src && src[0] >= 0 && src[0] < nx && src[1] >= 0 && src[1] < ny &&
                        src[2] >= 0 && src[2] < nz;
-  hipLaunchKernelGGL(k_wave25, grid, dim3(TX, TY), 0, s, pn, pnm1, vel, (int)nx, (int)ny, (int)z_lo,
+  hipExtLaunchKernelGGL(k_wave25, grid, dim3(TX, TY), 0, s, kt_start(kt), kt_stop(kt), 0, pn, pnm1, vel,
+                        (int)nx, (int)ny, (int)z_lo,
                      (int)z_hi, (int)gz0, (int)nz, dt_h, has_src ? (int)src[0] : -1,
                      has_src ? (int)src[1] : -1, has_src ? (int)src[2] : -1, src_amp);
   return hipGetLastError();

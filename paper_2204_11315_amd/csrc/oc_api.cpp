@@ -45,6 +45,13 @@ struct oc_handle {
   // per-op timing (oc_config.timing)
   bool timing = false;
   std::vector<hipEvent_t> tev;
+  // the last oc_run's timed ops: (kind, slab, index of its first event)
+  struct TimedOp {
+    int kind;
+    int64_t slab;
+    size_t ev;
+  };
+  std::vector<TimedOp> last_timed;
   // cached operation list
   std::vector<oc::Op> ops;
   int64_t ops_key[4] = {-1, -1, -1, -1};
@@ -105,6 +112,7 @@ oc::PlanInput plan_input(const oc_grid *g, const oc_stencil *st, const oc_config
   in.budget = c->dev_budget;
   in.slots = c->ring_slots ? c->ring_slots : 3;
   in.prefetch = c->prefetch ? c->prefetch : -1;
+  in.fuse = c->fuse_steps ? c->fuse_steps : 1;
   return in;
 }
 
@@ -142,6 +150,7 @@ int issue(oc_handle *h, const std::vector<oc::Op> &ops, const oc::Plan &p) {
   const uint64_t blocks_per_layer = (uint64_t)(p.in.nx / 4) * (uint64_t)(p.in.ny / 4);
   // timing: a pair of events around every timed op, recorded on its stream
   std::vector<std::pair<int, size_t>> timed;  // (kind, first event index)
+  h->last_timed.clear();
   if (h->timing) {
     size_t need = 0;
     for (const oc::Op &o : ops) need += timed_kind(o) != T_NONE ? 2 : 0;
@@ -151,12 +160,30 @@ int issue(oc_handle *h, const std::vector<oc::Op> &ops, const oc::Plan &p) {
     }
   }
   size_t tnext = 0;
+  // host time spent inside the HIP calls of each op class
+  enum { H_KERNEL, H_COPY, H_EVENT, H_SYNC, H_N };
+  double host_s[H_N] = {0, 0, 0, 0};
   for (const oc::Op &o : ops) {
     hipStream_t s = o.stream >= 0 ? h->s[o.stream] : nullptr;
+    const auto th0 = std::chrono::steady_clock::now();
     const TimedKind tk = h->timing ? timed_kind(o) : T_NONE;
     if (tk != T_NONE) {
       timed.push_back({(int)tk, tnext});
+      h->last_timed.push_back({(int)tk, o.sweep * 100000 + o.slab, tnext});
+    }
+    // kernels carry their timing events themselves (stamped with the kernels'
+    // own start / end); runtime copies are bracketed by marker events
+    const bool kernel_d2h = o.type == oc::OP_D2H && h->host_dev[o.host_id] && h->cfg.copy_back >= 0;
+    const bool marker_timed = tk != T_NONE && (o.type == oc::OP_H2D || (o.type == oc::OP_D2H && !kernel_d2h) ||
+                                               (o.type == oc::OP_DEC && o.z_hi < 0));
+    oc::KernelTimer ktimer;
+    oc::KernelTimer *kt = nullptr;
+    if (marker_timed) {
       x.ok(hipEventRecord(h->tev[tnext], s));
+    } else if (tk != T_NONE) {
+      ktimer.start = h->tev[tnext];
+      ktimer.stop = h->tev[tnext + 1];
+      kt = &ktimer;
     }
     switch (o.type) {
       case oc::OP_H2D:
@@ -165,9 +192,9 @@ int issue(oc_handle *h, const std::vector<oc::Op> &ops, const oc::Plan &p) {
         h2d += (uint64_t)o.bytes;
         break;
       case oc::OP_D2H:
-        if (h->host_dev[o.host_id])
+        if (kernel_d2h)
           x.ok(oc::launch_copy_to_host(h->host_dev[o.host_id] + o.host_off, h->arena + o.dev_src,
-                                       (size_t)o.bytes, s));
+                                       (size_t)o.bytes, h->cfg.copy_back, s, kt));
         else
           x.ok(hipMemcpyAsync(h->host[o.host_id] + o.host_off, h->arena + o.dev_src,
                               (size_t)o.bytes, hipMemcpyDeviceToHost, s));
@@ -179,13 +206,13 @@ int issue(oc_handle *h, const std::vector<oc::Op> &ops, const oc::Plan &p) {
                               hipMemcpyDeviceToDevice, s));
         } else {
           x.ok(oc::launch_decode(h->arena + o.dev_src, p.in.nx, p.in.ny, o.z_hi, p.in.rate,
-                                 (float *)(h->arena + o.dev_dst), s));
+                                 (float *)(h->arena + o.dev_dst), s, kt));
           bdec += blocks_per_layer * (uint64_t)o.z_hi;
         }
         break;
       case oc::OP_ENC:
         x.ok(oc::launch_encode((const float *)(h->arena + o.dev_src), p.in.nx, p.in.ny, o.z_hi,
-                               p.in.rate, h->arena + o.dev_dst, s));
+                               p.in.rate, h->arena + o.dev_dst, s, kt));
         benc += blocks_per_layer * (uint64_t)o.z_hi;
         break;
       case oc::OP_STAR7: {
@@ -195,11 +222,11 @@ int issue(oc_handle *h, const std::vector<oc::Op> &ops, const oc::Plan &p) {
         if (o.levels > 1)
           x.ok(oc::launch_star7_multi((const float *)(h->arena + o.dev_src), (float *)(h->arena + o.dev_dst),
                                       c0p, p.in.nx, p.in.ny, o.z_lo, o.z_hi, o.gz0, p.in.nz, o.levels,
-                                      o.transpose ? ct : c, s));
+                                      o.transpose ? ct : c, s, kt));
         else
           x.ok(oc::launch_star7((const float *)(h->arena + o.dev_src), (float *)(h->arena + o.dev_dst),
                                 c0p, p.in.nx, p.in.ny, o.z_lo, o.z_hi, o.gz0, p.in.nz,
-                                o.transpose ? ct : c, s));
+                                o.transpose ? ct : c, s, kt));
         {
           // credited cell updates: levels x output planes; algorithmic bytes:
           // the input range read once, the output range written once (+ c0)
@@ -213,13 +240,13 @@ int issue(oc_handle *h, const std::vector<oc::Op> &ops, const oc::Plan &p) {
       }
       case oc::OP_AXPY:
         x.ok(oc::launch_axpy_prod((float *)(h->arena + o.dev_dst), (const float *)(h->arena + o.dev_src),
-                                  (const float *)(h->arena + o.dev_src2), (size_t)o.bytes / 4u, s));
+                                  (const float *)(h->arena + o.dev_src2), (size_t)o.bytes / 4u, s, kt));
         break;
       case oc::OP_WAVE: {
         const float amp = (float)ricker((double)o.step * h->st.dt, h->st.f_peak, h->st.t0);
         x.ok(oc::launch_wave25((const float *)(h->arena + o.dev_src), (float *)(h->arena + o.dev_dst),
                                (const float *)(h->arena + o.dev_src2), p.in.nx, p.in.ny, o.z_lo,
-                               o.z_hi, o.gz0, p.in.nz, h->st.dt / h->st.h, h->st.src, amp, s));
+                               o.z_hi, o.gz0, p.in.nz, h->st.dt / h->st.h, h->st.src, amp, s, kt));
         cells += (uint64_t)(o.z_hi - o.z_lo) * (uint64_t)p.in.nx * (uint64_t)p.in.ny;
         sbytes += 16u * (uint64_t)(o.z_hi - o.z_lo) * (uint64_t)p.in.nx * (uint64_t)p.in.ny;
         break;
@@ -240,11 +267,32 @@ int issue(oc_handle *h, const std::vector<oc::Op> &ops, const oc::Plan &p) {
         break;
     }
     if (tk != T_NONE) {
-      x.ok(hipEventRecord(h->tev[tnext + 1], s));
+      if (marker_timed) {
+        x.ok(hipEventRecord(h->tev[tnext + 1], s));
+      } else if (!ktimer.used) {   // nothing was launched: an empty interval
+        x.ok(hipEventRecord(h->tev[tnext], s));
+        x.ok(hipEventRecord(h->tev[tnext + 1], s));
+      }
       tnext += 2;
+    }
+    {
+      int hc = H_KERNEL;
+      switch (o.type) {
+        case oc::OP_H2D: hc = H_COPY; break;
+        case oc::OP_D2H: hc = h->host_dev[o.host_id] && h->cfg.copy_back >= 0 ? H_KERNEL : H_COPY; break;
+        case oc::OP_REC:
+        case oc::OP_WAIT: hc = H_EVENT; break;
+        case oc::OP_SYNC: hc = H_SYNC; break;
+        default: break;
+      }
+      host_s[hc] += std::chrono::duration<double>(std::chrono::steady_clock::now() - th0).count();
     }
     if (x.st != OC_OK) break;
   }
+  h->stats.host_ms_kernels = host_s[H_KERNEL] * 1e3;
+  h->stats.host_ms_copies = host_s[H_COPY] * 1e3;
+  h->stats.host_ms_events = host_s[H_EVENT] * 1e3;
+  h->stats.host_ms_sync = host_s[H_SYNC] * 1e3;
   h->stats.bytes_h2d = h2d;
   h->stats.bytes_d2h = d2h;
   h->stats.cells_stencil = cells;
@@ -522,6 +570,7 @@ int oc_create(const oc_grid *g, const oc_stencil *st, const oc_config *cfg, oc_h
   *out = nullptr;
   if (st->kind != OC_STAR7 && st->kind != OC_WAVE25) return OC_ERR_ARG;
   if (st->kind == OC_WAVE25 && !(st->h > 0.f && st->dt > 0.f)) return OC_ERR_ARG;
+  if (cfg->copy_back < -1 || cfg->copy_back > 1024) return OC_ERR_ARG;
   oc::Plan p;
   int r = oc::make_plan(plan_input(g, st, cfg), &p);
   if (r != oc::ST_OK) return r;
@@ -794,6 +843,28 @@ int64_t oc_debug_check_adjoint(const oc_grid *g, const oc_stencil *st, const oc_
     return w;   // number of waits (for the mutation sweep)
   }
   return bad;
+}
+
+int64_t oc_debug_timeline(const oc_handle *h, int32_t *kind, int64_t *slab, double *start_ms,
+                          double *end_ms, int64_t cap) {
+  if (!h) return OC_ERR_ARG;
+  const int64_t n = (int64_t)h->last_timed.size();
+  if (!kind || !slab || !start_ms || !end_ms || cap <= 0) return n;
+  if (h->broken || n == 0) return n == 0 ? 0 : OC_ERR_STATE;
+  const hipEvent_t base = h->tev[h->last_timed[0].ev];
+  const int64_t m = std::min(n, cap);
+  for (int64_t i = 0; i < m; i++) {
+    const auto &t = h->last_timed[(size_t)i];
+    float a = 0.f, b = 0.f;
+    if (hipEventElapsedTime(&a, base, h->tev[t.ev]) != hipSuccess ||
+        hipEventElapsedTime(&b, base, h->tev[t.ev + 1]) != hipSuccess)
+      return OC_ERR_HIP;
+    kind[i] = t.kind;
+    slab[i] = t.slab;
+    start_ms[i] = a;
+    end_ms[i] = b;
+  }
+  return m;
 }
 
 int oc_stats_get(const oc_handle *h, oc_stats *s) {

@@ -1,16 +1,35 @@
 // oc_kernels.h -- launchers of the gfx950 kernels (internal to the library).
 #pragma once
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 #include <stdint.h>
 
 namespace oc {
 
+// Optional per-launch timing: a launcher given a KernelTimer attaches its
+// events to the first and last kernel it launches (hipExtLaunchKernel stamps
+// them with those kernels' own start and end times, so no marker packets sit
+// between the kernels) and sets `used`; a launcher that launches nothing
+// leaves the events alone.
+struct KernelTimer {
+  hipEvent_t start = nullptr, stop = nullptr;
+  bool used = false;
+};
+inline hipEvent_t kt_start(KernelTimer *kt) {
+  if (!kt) return nullptr;
+  kt->used = true;
+  return kt->start;
+}
+inline hipEvent_t kt_stop(KernelTimer *kt) { return kt ? kt->stop : nullptr; }
+
 // Fixed-rate codec over `nlayers` block layers (4 planes each) of an
 // [4*nlayers][ny][nx] FP32 array; coded layers are contiguous.
 hipError_t launch_encode(const float *d_in, int64_t nx, int64_t ny, int64_t nlayers, int rate,
-                         void *d_out, hipStream_t s);
+                         void *d_out, hipStream_t s,
+                         KernelTimer *kt = nullptr);
 hipError_t launch_decode(const void *d_in, int64_t nx, int64_t ny, int64_t nlayers, int rate,
-                         float *d_out, hipStream_t s);
+                         float *d_out, hipStream_t s,
+                         KernelTimer *kt = nullptr);
 // Device address of the codec's sticky error word.
 hipError_t codec_error_word(int **dev_ptr);
 
@@ -24,7 +43,8 @@ struct Star7Coef {
 // (nullable) is the per-cell c0 slab with the same local indexing.
 hipError_t launch_star7(const float *in, float *out, const float *c0f, int64_t nx, int64_t ny,
                         int64_t z_lo, int64_t z_hi, int64_t gz0, int64_t nz, const Star7Coef &c,
-                        hipStream_t s);
+                        hipStream_t s,
+                         KernelTimer *kt = nullptr);
 
 // `levels` (1..4) fused 7-point steps: writes level `levels` on local planes
 // [zo_lo, zo_hi) of out, reading in on [zo_lo - levels, zo_hi + levels).
@@ -32,20 +52,24 @@ hipError_t launch_star7(const float *in, float *out, const float *c0f, int64_t n
 constexpr int kMaxFusedSteps = 4;
 hipError_t launch_star7_multi(const float *in, float *out, const float *c0f, int64_t nx, int64_t ny,
                               int64_t zo_lo, int64_t zo_hi, int64_t gz0, int64_t nz, int levels,
-                              const Star7Coef &c, hipStream_t s);
+                              const Star7Coef &c, hipStream_t s,
+                         KernelTimer *kt = nullptr);
 
 // g[i] += a[i] * b[i] for i < n.
-hipError_t launch_axpy_prod(float *g, const float *a, const float *b, size_t n, hipStream_t s);
+hipError_t launch_axpy_prod(float *g, const float *a, const float *b, size_t n, hipStream_t s,
+                         KernelTimer *kt = nullptr);
 
 // One 25-point leapfrog step on a slab buffer (local plane 0 = global gz0):
 // pnm1 <- 2 pn - pnm1 + (v dt/h)^2 L8(pn) on local planes [z_lo, z_hi), plus
 // (v dt/h)^2 * src_amp at global cell src when it lies in that range.
 hipError_t launch_wave25(const float *pn, float *pnm1, const float *vel, int64_t nx, int64_t ny,
                          int64_t z_lo, int64_t z_hi, int64_t gz0, int64_t nz, float dt_h,
-                         const int64_t *src, float src_amp, hipStream_t s);
+                         const int64_t *src, float src_amp, hipStream_t s,
+                         KernelTimer *kt = nullptr);
 
 // Copies `bytes` from device memory into host memory that the device can
 // address (pinned, mapped); a small grid so that it overlaps other kernels.
-hipError_t launch_copy_to_host(void *dst, const void *src, size_t bytes, hipStream_t s);
+hipError_t launch_copy_to_host(void *dst, const void *src, size_t bytes, int workgroups, hipStream_t s,
+                         KernelTimer *kt = nullptr);
 
 }  // namespace oc

@@ -86,6 +86,7 @@ int make_plan(const PlanInput &in, Plan *out) {
     return ST_ARG;
   if (in.kind == KIND_WAVE25 && in.c0_field) return ST_ARG;
   if (in.slots < 2 || in.slots > kMaxSlots || in.prefetch >= in.slots) return ST_ARG;
+  if (in.fuse < 1 || in.fuse > kMaxFused) return ST_ARG;
   p.slots = in.slots;
   p.prefetch = in.prefetch < 0 ? in.slots - 1 : in.prefetch;
   p.r = stencil_radius(in.kind);
@@ -367,7 +368,7 @@ void build_ops(const Plan &p, int64_t sweeps, int steps_last, int src, int64_t s
     // STAR7: the k steps go in groups of up to kMaxFused fused steps; a group
     // ending after step s1 writes its last level on the planes the remaining
     // k - s1 steps still need
-    const int group = wave ? 1 : kMaxFused;
+    const int group = wave ? 1 : p.in.fuse;
     for (int s0 = 0; s0 < x.ks; s0 += group) {
       const int s1 = std::min(x.ks, s0 + group);
       const int64_t grow = (int64_t)(x.ks - s1) * p.r;

@@ -45,7 +45,8 @@ class Config(ctypes.Structure):
                 ("host_aux_bytes", ctypes.c_size_t), ("k", ctypes.c_int32),
                 ("slab_planes", ctypes.c_int32), ("rate_bits", ctypes.c_int32),
                 ("single_buffer", ctypes.c_int32), ("timing", ctypes.c_int32),
-                ("ring_slots", ctypes.c_int32), ("prefetch", ctypes.c_int32)]
+                ("ring_slots", ctypes.c_int32), ("prefetch", ctypes.c_int32),
+                ("fuse_steps", ctypes.c_int32), ("copy_back", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -61,7 +62,9 @@ class Stats(ctypes.Structure):
                 ("n_h2d", ctypes.c_uint64), ("n_d2h", ctypes.c_uint64),
                 ("cells_stencil", ctypes.c_uint64), ("bytes_stencil", ctypes.c_uint64),
                 ("blocks_decode", ctypes.c_uint64),
-                ("blocks_encode", ctypes.c_uint64)]
+                ("blocks_encode", ctypes.c_uint64),
+                ("host_ms_kernels", ctypes.c_double), ("host_ms_copies", ctypes.c_double),
+                ("host_ms_events", ctypes.c_double), ("host_ms_sync", ctypes.c_double)]
 
 
 _lock = threading.Lock()
@@ -97,6 +100,7 @@ _SIGS = {
     "oc_debug_check_plan": (_I64, [_P, _P, _P, _I64, _I32, _I64]),
     "oc_debug_plan_ops": (_I64, [_P, _P, _P, _I64, _P]),
     "oc_debug_plan_dump": (_I64, [_P, _P, _P, _I64, ctypes.c_char_p, _SZ]),
+    "oc_debug_timeline": (_I64, [_P, _P, _P, _P, _P, _I64]),
 }
 EXPORTED = tuple(_SIGS)
 
@@ -172,7 +176,7 @@ def host_aux_bytes(shape, stencil: Stencil, rate: int) -> int:
 
 
 def plan_config(k: int, slab_planes: int, rate: int, single_buffer: bool = True,
-                budget: int = 0, ring_slots: int = 0, prefetch: int = 0) -> Config:
+                budget: int = 0, ring_slots: int = 0, prefetch: int = 0, fuse: int = 0) -> Config:
     """A Config carrying only the plan fields."""
     cfg = Config()
     cfg.k = int(k)
@@ -182,30 +186,32 @@ def plan_config(k: int, slab_planes: int, rate: int, single_buffer: bool = True,
     cfg.dev_budget = int(budget)
     cfg.ring_slots = int(ring_slots)
     cfg.prefetch = int(prefetch)
+    cfg.fuse_steps = int(fuse)
     return cfg
 
 
 def plan_bytes(shape, stencil: Stencil, k: int, slab_planes: int, rate: int,
                single_buffer: bool = True, budget: int = 0, ring_slots: int = 0,
-               prefetch: int = 0) -> int:
+               prefetch: int = 0, fuse: int = 0) -> int:
     g = make_grid(shape)
-    cfg = plan_config(k, slab_planes, rate, single_buffer, budget, ring_slots, prefetch)
+    cfg = plan_config(k, slab_planes, rate, single_buffer, budget, ring_slots, prefetch, fuse)
     return int(lib().oc_plan_bytes(_ref(g), _ref(stencil), _ref(cfg)))
 
 
 def check_plan(shape, stencil: Stencil, k: int, slab_planes: int, rate: int, sweeps: int,
                single_buffer: bool = True, budget: int = 0, mutate: int = 0, i: int = 0,
-               ring_slots: int = 0, prefetch: int = 0) -> int:
+               ring_slots: int = 0, prefetch: int = 0, fuse: int = 0) -> int:
     g = make_grid(shape)
-    cfg = plan_config(k, slab_planes, rate, single_buffer, budget, ring_slots, prefetch)
+    cfg = plan_config(k, slab_planes, rate, single_buffer, budget, ring_slots, prefetch, fuse)
     return int(lib().oc_debug_check_plan(_ref(g), _ref(stencil), _ref(cfg), int(sweeps),
                                          int(mutate), int(i)))
 
 
 def plan_ops(shape, stencil: Stencil, k: int, slab_planes: int, rate: int, sweeps: int,
-             single_buffer: bool = True, budget: int = 0, ring_slots: int = 0, prefetch: int = 0):
+             single_buffer: bool = True, budget: int = 0, ring_slots: int = 0, prefetch: int = 0,
+             fuse: int = 0):
     g = make_grid(shape)
-    cfg = plan_config(k, slab_planes, rate, single_buffer, budget, ring_slots, prefetch)
+    cfg = plan_config(k, slab_planes, rate, single_buffer, budget, ring_slots, prefetch, fuse)
     nw = ctypes.c_int64(0)
     n = int(lib().oc_debug_plan_ops(_ref(g), _ref(stencil), _ref(cfg), int(sweeps), _ref(nw)))
     return n, int(nw.value)
@@ -213,10 +219,10 @@ def plan_ops(shape, stencil: Stencil, k: int, slab_planes: int, rate: int, sweep
 
 def plan_dump(shape, stencil: Stencil, k: int, slab_planes: int, rate: int, sweeps: int,
               single_buffer: bool = True, budget: int = 0, ring_slots: int = 0,
-              prefetch: int = 0) -> str:
+              prefetch: int = 0, fuse: int = 0) -> str:
     """Text listing of the operation list the executor would issue."""
     g = make_grid(shape)
-    cfg = plan_config(k, slab_planes, rate, single_buffer, budget, ring_slots, prefetch)
+    cfg = plan_config(k, slab_planes, rate, single_buffer, budget, ring_slots, prefetch, fuse)
     n = int(lib().oc_debug_plan_dump(_ref(g), _ref(stencil), _ref(cfg), int(sweeps), None, 0))
     if n < 0:
         raise OCError(n, "oc_debug_plan_dump", status_str(n))
@@ -351,7 +357,7 @@ class OutOfCore:
     def __init__(self, shape, c=C_CONFIG1, k: int = 4, rate: int = 0, budget: int = 512 << 20,
                  slab_planes: int = 0, single_buffer: bool = True, c0_field: bool = False,
                  timing: bool = False, ring_slots: int = 0, prefetch: int = 0, device=None,
-                 stencil: Stencil = None):
+                 stencil: Stencil = None, fuse: int = 0, copy_back: int = 0):
         torch = _torch()
         self.shape = tuple(int(v) for v in shape)
         self.rate = int(rate)
@@ -361,7 +367,7 @@ class OutOfCore:
         self.grid = make_grid(self.shape)
         self.device = torch.device(device if device is not None else "cuda")
         need = plan_bytes(self.shape, self.stencil, k, slab_planes, rate, single_buffer, budget,
-                          ring_slots, prefetch)
+                          ring_slots, prefetch, fuse)
         if need == 0:
             raise OCError(OC_ERR_BUDGET, "plan", "no slab depth fits the budget")
         self.arena = torch.empty(int(budget), dtype=torch.uint8, device=self.device)
@@ -387,6 +393,8 @@ class OutOfCore:
         cfg.timing = 1 if timing else 0
         cfg.ring_slots = int(ring_slots)
         cfg.prefetch = int(prefetch)
+        cfg.fuse_steps = int(fuse)
+        cfg.copy_back = int(copy_back)
         self.cfg = cfg
         h = ctypes.c_void_p()
         torch.cuda.synchronize(self.device)
@@ -428,6 +436,23 @@ class OutOfCore:
         s = Stats()
         _check(lib().oc_stats_get(self.h, _ref(s)), "oc_stats_get")
         return {name: getattr(s, name) for name, _ in Stats._fields_}
+
+    def timeline(self):
+        """Per timed op of the last run (timing on): (class, sweep*100000+slab,
+        start ms, end ms) arrays; classes 0 decode, 1 stencil, 2 encode, 3 H2D, 4 D2H."""
+        n = int(lib().oc_debug_timeline(self.h, None, None, None, None, 0))
+        if n < 0:
+            raise OCError(n, "oc_debug_timeline", status_str(n))
+        kind = np.zeros(n, np.int32)
+        slab = np.zeros(n, np.int64)
+        t0 = np.zeros(n, np.float64)
+        t1 = np.zeros(n, np.float64)
+        if n:
+            m = int(lib().oc_debug_timeline(self.h, kind.ctypes.data, slab.ctypes.data,
+                                            t0.ctypes.data, t1.ctypes.data, n))
+            if m < 0:
+                raise OCError(m, "oc_debug_timeline", status_str(m))
+        return kind, slab, t0, t1
 
     def set_timing(self, on: bool):
         _check(lib().oc_set_timing(self.h, 1 if on else 0), "oc_set_timing")

@@ -129,6 +129,18 @@ def test_c0_field_ooc():
     assert st.c0_is_field == 1
 
 
+@pytest.mark.parametrize("fuse", [2, 3, 4])
+@pytest.mark.parametrize("R", [0, 8])
+def test_fused_stencil_launches_equal_single_steps_bitwise(fuse, R):
+    u0 = inputs.grf_field(SHAPE, seed=12)
+    c0 = inputs.c0_field(SHAPE, seed=13)
+    kw = dict(k=4, rate=R, slab_planes=8, c0_field=True, runs=[8, 3])
+    want, _ = run_ooc(u0, 0, c0, fuse=1, **kw)
+    got, st = run_ooc(u0, 0, c0, fuse=fuse, timing=True, **kw)   # counts need timing
+    assert np.array_equal(got.view(np.uint32), want.view(np.uint32))
+    assert st["n_stencil"] == 6 * -(-3 // fuse)      # the short sweep of 3 steps
+
+
 def test_stats_bytes_and_visits():
     u0 = inputs.modes_field(SHAPE, seed=10)
     _, st = run_ooc(u0, 8, k=4, rate=8, slab_planes=8, timing=True)
@@ -138,8 +150,8 @@ def test_stats_bytes_and_visits():
     assert st["bytes_d2h"] == 2 * lb
     # each slab also loads one 4-plane layer of halo per interior face
     assert st["bytes_h2d"] == 2 * (lb + 2 * 5 * layer)
-    # one fused 4-step stencil launch per slab visit
-    assert st["n_decode"] == 12 and st["n_encode"] == 12 and st["n_stencil"] == 12
+    # one single-step stencil launch per step and slab visit (the default)
+    assert st["n_decode"] == 12 and st["n_encode"] == 12 and st["n_stencil"] == 12 * 4
     # every cell is updated 8 times; halo recomputation is credited on top
     assert st["cells_stencil"] >= 8 * int(np.prod(SHAPE))
     assert st["ms_decode"] > 0 and st["ms_stencil"] > 0 and st["ms_encode"] > 0

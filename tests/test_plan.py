@@ -141,10 +141,26 @@ def test_ring_slots_and_prefetch_race_free(slots, prefetch, R):
         assert extra == (S + 2 * 4) // 4 * oc.codec_bytes((4, 12, 16), R)
 
 
+@pytest.mark.parametrize("fuse", [1, 2, 3, 4])
+@pytest.mark.parametrize("k", [3, 4])
+def test_fused_stencil_launches_race_free(fuse, k):
+    shape, S = (40, 12, 16), 8
+    for R in (0, 8):
+        n, nw = oc.plan_ops(shape, ST, k, S, R, 3, fuse=fuse)
+        assert oc.check_plan(shape, ST, k, S, R, 3, fuse=fuse) == 0
+        for i in range(nw):
+            assert oc.check_plan(shape, ST, k, S, R, 3, fuse=fuse, mutate=1, i=i) > 0
+        # one launch per group of up to `fuse` steps, per slab visit
+        dump = oc.plan_dump(shape, ST, k, S, R, 1, fuse=fuse)
+        launches = sum(" STAR7 " in line for line in dump.splitlines())
+        assert launches == 5 * -(-k // fuse)
+
+
 def test_invalid_ring_parameters():
     assert oc.plan_bytes((40, 12, 16), ST, 4, 8, 8, ring_slots=9) == 0
     assert oc.plan_bytes((40, 12, 16), ST, 4, 8, 8, ring_slots=1) == 0
     assert oc.plan_bytes((40, 12, 16), ST, 4, 8, 8, ring_slots=3, prefetch=3) == 0
+    assert oc.plan_bytes((40, 12, 16), ST, 4, 8, 8, fuse=5) == 0
 
 
 def test_some_reorderings_are_caught():
