@@ -84,7 +84,7 @@ typedef struct {
   int32_t prefetch;        /* slabs copied in ahead of the kernels, 1..ring_slots-1;
                               0 = ring_slots - 1                                           */
   int32_t fuse_steps;      /* 7-point: time steps per stencil launch, 1..4 (one kernel
-                              marches all of them through LDS); 0 = 1                      */
+                              carries all of them through registers); 0 = 4                */
   int32_t copy_back;       /* device-to-host copies: n > 0 = a copy kernel of n workgroups
                               (1..1024) storing into the mapped pinned host pages; 0 = such a
                               kernel with 4 workgroups; -1 = the runtime's hipMemcpyAsync   */

@@ -90,94 +90,164 @@ __global__ __launch_bounds__(TX *TY) void k_star7(const float *__restrict__ in, 
 }
 
 // ---- K fused time steps (temporal blocking inside one launch) --------------
-// A 64x16 workgroup loads a 64x16 column region and marches z; level s
-// (s = 1..K) of the region is computed one plane behind level s-1, from
-// level s-1's three newest planes (registers) and its previous plane's xy
-// neighbours (LDS, double-buffered by plane parity, one barrier per plane).
-// The valid area shrinks by one column per level, so the (64-2K) x (16-2K)
-// centre of the region is written at level K.  Only level 0 is read from and
-// level K written to memory: 2 passes instead of 2K.
-constexpr int FX = 64, FY = 16, FZC = 32;
+// A workgroup of FW waves owns a 64 x (FW*RY) column tile of the xy plane and
+// marches z.  Lane l of every wave holds column x = x0 + l; wave w holds the
+// RY consecutive rows y0 + w*RY + r in registers.  Level s (s = 1..K) is
+// computed one plane behind level s-1: at input plane z, level s produces
+// plane z - s from level s-1's planes z-s-1, z-s, z-s+1, which every thread
+// keeps in a three-plane register window per level.  Neighbours of the centre
+// plane come from:
+//   x +- 1: the neighbouring lanes' registers (DPP wave shifts, no memory);
+//   y +- 1: the thread's own rows, or, at the strip's first / last row, the
+//           adjacent wave's edge row, published in LDS one plane earlier
+//           (double-buffered by plane parity: one barrier per plane).
+// Every level is valid one column / row further inside the tile than the
+// level below it, so the (64 - 2K) x (FW*RY - 2K) centre is written at level
+// K.  Cells outside the grid are held at zero at every level (the boundary
+// condition).  The per-cell arithmetic is star7_point's, so the result is bit
+// identical to K single steps.
+constexpr int FW = 8, RY = 4, FTY = FW * RY;
+
+__device__ __forceinline__ float lane_from_left(float v) {    // value of lane - 1
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float lane_from_right(float v) {   // value of lane + 1
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, false));
+}
 
 template <int K, bool FIELD>
-__global__ __launch_bounds__(FX *FY) void k_star7_multi(const float *__restrict__ in, float *__restrict__ out,
-                                                       const float *__restrict__ c0f, int nx, int ny,
-                                                       int zo_lo, int zo_hi, int gz0, int nz, int nbx,
-                                                       int nby, int nbz, oc::Star7Coef c) {
-  constexpr int OX = FX - 2 * K, OY = FY - 2 * K;
-  __shared__ float lds[2][K][FY][FX];
+__global__ __launch_bounds__(64 * FW) void k_star7_fused(const float *__restrict__ in, float *__restrict__ out,
+                                                         const float *__restrict__ c0f, int nx, int ny,
+                                                         int zo_lo, int zo_hi, int gz0, int nz, int nbx,
+                                                         int nby, int nbz, int fz, oc::Star7Coef c) {
+  constexpr int OX = 64 - 2 * K, OY = FTY - 2 * K;
+  // edge rows of levels 0..K-1: [plane parity][level][wave][first/last row][lane]
+  __shared__ float edge[2][K][FW][2][64];
   const int nb = nbx * nby * nbz;
   const int t = xcd_tile(blockIdx.x, nb);
   if (t >= nb) return;   // uniform across the workgroup
   const int tbx = t % nbx, tby = (t / nbx) % nby, tbz = t / (nbx * nby);
-  const int tx = threadIdx.x, ty = threadIdx.y;
-  const int x = tbx * OX - K + tx;
-  const int y = tby * OY - K + ty;
-  const bool col_in = x >= 0 && x < nx && y >= 0 && y < ny;
-  const bool col_out = tx >= K && tx < K + OX && ty >= K && ty < K + OY && col_in;
-  const int zlo = zo_lo + tbz * FZC;
-  const int zhi = min(zlo + FZC, zo_hi);
-  const size_t plane = (size_t)nx * (size_t)ny;
-  const ptrdiff_t col = (ptrdiff_t)y * nx + x;
-  const int txm = max(tx - 1, 0), txp = min(tx + 1, FX - 1);
-  const int tym = max(ty - 1, 0), typ = min(ty + 1, FY - 1);
-  // w[s][0..2]: level s at planes (p-2, p-1, p), p = newest plane of level s
-  float w[K + 1][3];
+  const int lane = (int)threadIdx.x & 63, w = (int)threadIdx.x >> 6;
+  const int x = tbx * OX - K + lane;
+  const int y0 = tby * OY - K + w * RY;
+  const bool x_in = x >= 0 && x < nx;
+  const bool x_out = lane >= K && lane < K + OX && x_in;
+  bool row_in[RY], row_out[RY];
 #pragma unroll
-  for (int s = 0; s <= K; s++) w[s][0] = w[s][1] = w[s][2] = 0.0f;
+  for (int r = 0; r < RY; r++) {
+    const int y = y0 + r, ty = w * RY + r;
+    row_in[r] = x_in && y >= 0 && y < ny;
+    row_out[r] = x_out && y >= 0 && y < ny && ty >= K && ty < K + OY;
+  }
+  const int zlo = zo_lo + tbz * fz;
+  const int zhi = min(zlo + fz, zo_hi);
+  const ptrdiff_t plane = (ptrdiff_t)nx * (ptrdiff_t)ny;
+  const ptrdiff_t col0 = (ptrdiff_t)y0 * nx + x;   // row 0 of this thread's strip
+
+  float win[K][3][RY];   // win[s][j][r]: level s at plane (newest - 2 + j)
+  float cw[K][RY];       // c0 at planes z-1 .. z-K (FIELD)
+#pragma unroll
+  for (int s = 0; s < K; s++)
+#pragma unroll
+    for (int r = 0; r < RY; r++) {
+      win[s][0][r] = win[s][1][r] = win[s][2][r] = 0.0f;
+      cw[s][r] = 0.0f;
+    }
+
+  for (int i = (int)threadIdx.x; i < 2 * K * FW * 2 * 64; i += 64 * FW) (&edge[0][0][0][0][0])[i] = 0.0f;
+  __syncthreads();
+
   for (int z = zlo - K; z < zhi + K; z++) {
     const int par = z & 1;
-    // level 0: plane z
+    // level 0: input plane z
     {
-      const bool in_d = col_in && gz0 + z >= 0 && gz0 + z < nz;
-      const float v = in_d ? in[(ptrdiff_t)z * (ptrdiff_t)plane + col] : 0.0f;
-      w[0][0] = w[0][1];
-      w[0][1] = w[0][2];
-      w[0][2] = v;
+      const bool p_in = gz0 + z >= 0 && gz0 + z < nz;
+#pragma unroll
+      for (int r = 0; r < RY; r++) {
+        win[0][0][r] = win[0][1][r];
+        win[0][1][r] = win[0][2][r];
+        win[0][2][r] = (p_in && row_in[r]) ? in[(ptrdiff_t)z * plane + col0 + (ptrdiff_t)r * nx] : 0.0f;
+      }
     }
+    if (FIELD) {
+      const int p = z - 1;
+      const bool p_in = gz0 + p >= 0 && gz0 + p < nz;
+#pragma unroll
+      for (int s = K - 1; s > 0; s--)
+#pragma unroll
+        for (int r = 0; r < RY; r++) cw[s][r] = cw[s - 1][r];
+#pragma unroll
+      for (int r = 0; r < RY; r++)
+        cw[0][r] = (p_in && row_in[r]) ? c0f[(ptrdiff_t)p * plane + col0 + (ptrdiff_t)r * nx] : 0.0f;
+    }
+    // levels 1..K: plane z - s from level s-1's window
 #pragma unroll
     for (int s = 1; s <= K; s++) {
-      const int p = z - s;   // plane of level s computed now
-      const bool in_d = col_in && gz0 + p >= 0 && gz0 + p < nz;
-      float v = 0.0f;
-      if (in_d) {
-        const float (*L)[FX] = lds[par ^ 1][s - 1];   // level s-1 at plane p
-        const float c0 = FIELD ? c0f[(ptrdiff_t)p * (ptrdiff_t)plane + col] : c.c0;
-        v = star7_point(c0, w[s - 1][1], L[ty][txm], L[ty][txp], L[tym][tx], L[typ][tx],
-                        w[s - 1][0], w[s - 1][2], c);
-      }
-      w[s][0] = w[s][1];
-      w[s][1] = w[s][2];
-      w[s][2] = v;
-    }
-    // publish this plane of levels 0..K-1 for the next plane's neighbours
+      const int p = z - s;
+      const bool p_in = gz0 + p >= 0 && gz0 + p < nz;
+      const float(&lo)[3][RY] = win[s - 1];
+      // y neighbours across the strip ends: the adjacent waves' edge rows of
+      // level s-1 at plane p, published at the end of the previous plane
+      const float up = w > 0 ? edge[par ^ 1][s - 1][w - 1][1][lane] : 0.0f;
+      const float dn = w < FW - 1 ? edge[par ^ 1][s - 1][w + 1][0][lane] : 0.0f;
+      float nv[RY];
 #pragma unroll
-    for (int s = 0; s < K; s++) lds[par][s][ty][tx] = w[s][2];
-    const int po = z - K;
-    if (col_out && po >= zlo && po < zhi)
-      out[(ptrdiff_t)po * (ptrdiff_t)plane + col] = w[K][2];
+      for (int r = 0; r < RY; r++) {
+        const float cur = lo[1][r];
+        const float xm = lane_from_left(cur);
+        const float xp = lane_from_right(cur);
+        const float ym = r > 0 ? lo[1][r - 1] : up;
+        const float yp = r < RY - 1 ? lo[1][r + 1] : dn;
+        const float c0 = FIELD ? cw[s - 1][r] : c.c0;
+        const float v = star7_point(c0, cur, xm, xp, ym, yp, lo[0][r], lo[2][r], c);
+        nv[r] = (p_in && row_in[r]) ? v : 0.0f;
+      }
+      if (s < K) {
+#pragma unroll
+        for (int r = 0; r < RY; r++) {
+          win[s][0][r] = win[s][1][r];
+          win[s][1][r] = win[s][2][r];
+          win[s][2][r] = nv[r];
+        }
+      } else if (p >= zlo && p < zhi) {
+#pragma unroll
+        for (int r = 0; r < RY; r++)
+          if (row_out[r]) out[(ptrdiff_t)p * plane + col0 + (ptrdiff_t)r * nx] = nv[r];
+      }
+    }
+    // publish the edge rows of the planes just made (levels 0..K-1)
+#pragma unroll
+    for (int s = 0; s < K; s++) {
+      edge[par][s][w][0][lane] = win[s][2][0];
+      edge[par][s][w][1][lane] = win[s][2][RY - 1];
+    }
     __syncthreads();
   }
 }
 
 template <int K>
-hipError_t launch_multi(const float *in, float *out, const float *c0f, int64_t nx, int64_t ny,
+hipError_t launch_fused(const float *in, float *out, const float *c0f, int64_t nx, int64_t ny,
                         int64_t zo_lo, int64_t zo_hi, int64_t gz0, int64_t nz, const oc::Star7Coef &c,
                         hipStream_t s, oc::KernelTimer *kt) {
-  constexpr int OX = FX - 2 * K, OY = FY - 2 * K;
+  constexpr int OX = 64 - 2 * K, OY = FTY - 2 * K;
   const int nbx = (int)((nx + OX - 1) / OX);
   const int nby = (int)((ny + OY - 1) / OY);
-  const int nbz = (int)((zo_hi - zo_lo + FZC - 1) / FZC);
-  const int64_t nb = (int64_t)nbx * nby * nbz;
+  // z chunk: enough workgroups to cover the chip about twice
+  const int64_t nz_out = zo_hi - zo_lo;
+  const int64_t xy = (int64_t)nbx * nby;
+  int64_t nbz = std::max<int64_t>(1, std::min<int64_t>(nz_out / (2 * K), (512 + xy - 1) / xy));
+  const int fz = (int)((nz_out + nbz - 1) / nbz);
+  nbz = (nz_out + fz - 1) / fz;
+  const int64_t nb = xy * nbz;
   if (nb > 0x7fffffff) return hipErrorInvalidValue;
   if (c0f)
-    hipExtLaunchKernelGGL((k_star7_multi<K, true>), dim3((unsigned)nb), dim3(FX, FY), 0, s, oc::kt_start(kt),
-                          oc::kt_stop(kt), 0, in, out, c0f,
-                       (int)nx, (int)ny, (int)zo_lo, (int)zo_hi, (int)gz0, (int)nz, nbx, nby, nbz, c);
+    hipExtLaunchKernelGGL((k_star7_fused<K, true>), dim3((unsigned)nb), dim3(64 * FW), 0, s, oc::kt_start(kt),
+                          oc::kt_stop(kt), 0, in, out, c0f, (int)nx, (int)ny, (int)zo_lo, (int)zo_hi,
+                          (int)gz0, (int)nz, nbx, nby, (int)nbz, fz, c);
   else
-    hipExtLaunchKernelGGL((k_star7_multi<K, false>), dim3((unsigned)nb), dim3(FX, FY), 0, s, oc::kt_start(kt),
-                          oc::kt_stop(kt), 0, in, out, c0f,
-                       (int)nx, (int)ny, (int)zo_lo, (int)zo_hi, (int)gz0, (int)nz, nbx, nby, nbz, c);
+    hipExtLaunchKernelGGL((k_star7_fused<K, false>), dim3((unsigned)nb), dim3(64 * FW), 0, s, oc::kt_start(kt),
+                          oc::kt_stop(kt), 0, in, out, c0f, (int)nx, (int)ny, (int)zo_lo, (int)zo_hi,
+                          (int)gz0, (int)nz, nbx, nby, (int)nbz, fz, c);
   return hipGetLastError();
 }
 
@@ -198,10 +268,10 @@ hipError_t launch_star7_multi(const float *in, float *out, const float *c0f, int
                               const Star7Coef &c, hipStream_t s, KernelTimer *kt) {
   if (zo_hi <= zo_lo) return hipSuccess;
   switch (levels) {
-    case 1: return launch_multi<1>(in, out, c0f, nx, ny, zo_lo, zo_hi, gz0, nz, c, s, kt);
-    case 2: return launch_multi<2>(in, out, c0f, nx, ny, zo_lo, zo_hi, gz0, nz, c, s, kt);
-    case 3: return launch_multi<3>(in, out, c0f, nx, ny, zo_lo, zo_hi, gz0, nz, c, s, kt);
-    case 4: return launch_multi<4>(in, out, c0f, nx, ny, zo_lo, zo_hi, gz0, nz, c, s, kt);
+    case 1: return launch_fused<1>(in, out, c0f, nx, ny, zo_lo, zo_hi, gz0, nz, c, s, kt);
+    case 2: return launch_fused<2>(in, out, c0f, nx, ny, zo_lo, zo_hi, gz0, nz, c, s, kt);
+    case 3: return launch_fused<3>(in, out, c0f, nx, ny, zo_lo, zo_hi, gz0, nz, c, s, kt);
+    case 4: return launch_fused<4>(in, out, c0f, nx, ny, zo_lo, zo_hi, gz0, nz, c, s, kt);
     default: return hipErrorInvalidValue;
   }
 }

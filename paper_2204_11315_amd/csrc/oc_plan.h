@@ -67,7 +67,7 @@ struct PlanInput {
   size_t budget = 0;      // 0 = unlimited
   int slots = 3;          // staging ring slots (2..8)
   int prefetch = -1;      // copy-ins issued ahead of the kernels (-1 = slots - 1)
-  int fuse = 1;           // STAR7: time steps per stencil launch (1..kMaxFused)
+  int fuse = 4;           // STAR7: time steps per stencil launch (1..kMaxFused)
 };
 
 constexpr int kMaxSlots = 8;

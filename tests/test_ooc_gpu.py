@@ -150,8 +150,8 @@ def test_stats_bytes_and_visits():
     assert st["bytes_d2h"] == 2 * lb
     # each slab also loads one 4-plane layer of halo per interior face
     assert st["bytes_h2d"] == 2 * (lb + 2 * 5 * layer)
-    # one single-step stencil launch per step and slab visit (the default)
-    assert st["n_decode"] == 12 and st["n_encode"] == 12 and st["n_stencil"] == 12 * 4
+    # one fused 4-step stencil launch per slab visit (the default)
+    assert st["n_decode"] == 12 and st["n_encode"] == 12 and st["n_stencil"] == 12
     # every cell is updated 8 times; halo recomputation is credited on top
     assert st["cells_stencil"] >= 8 * int(np.prod(SHAPE))
     assert st["ms_decode"] > 0 and st["ms_stencil"] > 0 and st["ms_encode"] > 0
