@@ -105,14 +105,128 @@ __global__ __launch_bounds__(TX *TY) void k_star7(const float *__restrict__ in, 
 // level below it, so the (64 - 2K) x (FW*RY - 2K) centre is written at level
 // K.  Cells outside the grid are held at zero at every level (the boundary
 // condition).  The per-cell arithmetic is star7_point's, so the result is bit
-// identical to K single steps.
+// identical to K single steps.  The caller guarantees that input planes
+// [zo_lo - K, zo_hi + K) lie inside the buffers; no plane outside that range
+// is read.
 constexpr int FW = 8, RY = 4, FTY = FW * RY;
+constexpr int kFusedTargetWgs = 512;   // workgroups a fused launch aims for (z chunks)
 
+// DPP wave shifts by one lane; the lane with no source reads zero (bound_ctrl)
 __device__ __forceinline__ float lane_from_left(float v) {    // value of lane - 1
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, false));
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x138, 0xf, 0xf, true));
 }
 __device__ __forceinline__ float lane_from_right(float v) {   // value of lane + 1
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, false));
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x130, 0xf, 0xf, true));
+}
+
+// State of one thread of the fused kernel.  win[s][slot][r] holds level s of
+// row r at three consecutive planes in rotating slots: in phase PH (the input
+// plane index mod 3) the slot (PH + 2) % 3 holds the oldest plane, which the
+// new plane replaces, so the window never moves in registers.
+template <int K, bool FIELD>
+struct FusedState {
+  float win[K][3][RY];
+  float cw[K][RY];   // c0 at planes z-1 .. z-K (FIELD)
+  bool row_in[RY], row_out[RY];
+};
+
+// One input plane z of the fused kernel.  MASK = false is the interior form:
+// the workgroup's whole column range and plane range lie inside the grid, so
+// no cell needs the zero boundary value.
+template <int K, bool FIELD, bool MASK, int PH>
+__device__ __forceinline__ void fused_plane(FusedState<K, FIELD> &st, float (*edge)[K][FW][2][64], int z,
+                                            const float *__restrict__ in, float *__restrict__ out,
+                                            const float *__restrict__ c0f, ptrdiff_t plane, ptrdiff_t col0,
+                                            int nx, int gz0, int nz, int zlo, int zhi, int lane, int w,
+                                            const oc::Star7Coef &c) {
+  // slots in this phase: the new plane goes to N, its two predecessors are in
+  // C (one before) and O (two before)
+  constexpr int N = (PH + 2) % 3, C = (PH + 1) % 3, O = PH % 3;
+  const int par = z & 1;
+  {
+    // level 0: input plane z (the other resident waves hide its latency;
+    // fetching a plane ahead costs registers and so occupancy, and measured
+    // slower)
+    const bool p_in = !MASK || (gz0 + z >= 0 && gz0 + z < nz);
+#pragma unroll
+    for (int r = 0; r < RY; r++)
+      st.win[0][N][r] = (!MASK || (p_in && st.row_in[r])) ? in[(ptrdiff_t)z * plane + col0 + (ptrdiff_t)r * nx]
+                                                          : 0.0f;
+  }
+  if (FIELD) {
+    // c0 at plane z-1; planes below zlo-K+1 are needed by no level (and may
+    // lie before the buffer), so they are not read
+    const int p = z - 1;
+    const bool p_use = p >= zlo - K + 1 && (!MASK || (gz0 + p >= 0 && gz0 + p < nz));
+#pragma unroll
+    for (int s = K - 1; s > 0; s--)
+#pragma unroll
+      for (int r = 0; r < RY; r++) st.cw[s][r] = st.cw[s - 1][r];
+#pragma unroll
+    for (int r = 0; r < RY; r++)
+      st.cw[0][r] = (p_use && (!MASK || st.row_in[r])) ? c0f[(ptrdiff_t)p * plane + col0 + (ptrdiff_t)r * nx]
+                                                       : 0.0f;
+  }
+  // the outermost waves read a clamped neighbour: their outer row lies in the
+  // tile's invalid border, where any value may go
+  const int wu = w > 0 ? w - 1 : 0, wd = w < FW - 1 ? w + 1 : FW - 1;
+  // level s makes plane z - s from level s-1's planes z-s-1 (slot O),
+  // z-s (slot C) and z-s+1 (slot N, made just now)
+#pragma unroll
+  for (int s = 1; s <= K; s++) {
+    const int p = z - s;
+    const bool p_in = !MASK || (gz0 + p >= 0 && gz0 + p < nz);
+    const float up = edge[par ^ 1][s - 1][wu][1][lane];
+    const float dn = edge[par ^ 1][s - 1][wd][0][lane];
+    float nv[RY];
+#pragma unroll
+    for (int r = 0; r < RY; r++) {
+      const float cur = st.win[s - 1][C][r];
+      const float xm = lane_from_left(cur);
+      const float xp = lane_from_right(cur);
+      const float ym = r > 0 ? st.win[s - 1][C][r - 1] : up;
+      const float yp = r < RY - 1 ? st.win[s - 1][C][r + 1] : dn;
+      const float c0 = FIELD ? st.cw[s - 1][r] : c.c0;
+      const float v = star7_point(c0, cur, xm, xp, ym, yp, st.win[s - 1][O][r], st.win[s - 1][N][r], c);
+      nv[r] = (!MASK || (p_in && st.row_in[r])) ? v : 0.0f;
+    }
+    if (s < K) {
+#pragma unroll
+      for (int r = 0; r < RY; r++) st.win[s][N][r] = nv[r];
+    } else if (p >= zlo && p < zhi) {
+#pragma unroll
+      for (int r = 0; r < RY; r++)
+        if (st.row_out[r]) out[(ptrdiff_t)p * plane + col0 + (ptrdiff_t)r * nx] = nv[r];
+    }
+  }
+  // publish the edge rows of the planes just made (levels 0..K-1)
+#pragma unroll
+  for (int s = 0; s < K; s++) {
+    edge[par][s][w][0][lane] = st.win[s][N][0];
+    edge[par][s][w][1][lane] = st.win[s][N][RY - 1];
+  }
+  __syncthreads();
+}
+
+// input planes z = zlo-K .. zhi+K-1, three per trip so that the window slots
+// rotate at compile time
+template <int K, bool FIELD, bool MASK>
+__device__ __forceinline__ void fused_march(FusedState<K, FIELD> &st, float (*edge)[K][FW][2][64],
+                                            const float *__restrict__ in, float *__restrict__ out,
+                                            const float *__restrict__ c0f, ptrdiff_t plane, ptrdiff_t col0,
+                                            int nx, int gz0, int nz, int zlo, int zhi, int lane, int w,
+                                            const oc::Star7Coef &c) {
+  int z = zlo - K;
+  const int zend = zhi + K;
+  for (; z + 3 <= zend; z += 3) {
+    fused_plane<K, FIELD, MASK, 0>(st, edge, z, in, out, c0f, plane, col0, nx, gz0, nz, zlo, zhi, lane, w, c);
+    fused_plane<K, FIELD, MASK, 1>(st, edge, z + 1, in, out, c0f, plane, col0, nx, gz0, nz, zlo, zhi, lane, w, c);
+    fused_plane<K, FIELD, MASK, 2>(st, edge, z + 2, in, out, c0f, plane, col0, nx, gz0, nz, zlo, zhi, lane, w, c);
+  }
+  if (z < zend)
+    fused_plane<K, FIELD, MASK, 0>(st, edge, z, in, out, c0f, plane, col0, nx, gz0, nz, zlo, zhi, lane, w, c);
+  if (z + 1 < zend)
+    fused_plane<K, FIELD, MASK, 1>(st, edge, z + 1, in, out, c0f, plane, col0, nx, gz0, nz, zlo, zhi, lane, w, c);
 }
 
 template <int K, bool FIELD>
@@ -128,101 +242,38 @@ __global__ __launch_bounds__(64 * FW) void k_star7_fused(const float *__restrict
   if (t >= nb) return;   // uniform across the workgroup
   const int tbx = t % nbx, tby = (t / nbx) % nby, tbz = t / (nbx * nby);
   const int lane = (int)threadIdx.x & 63, w = (int)threadIdx.x >> 6;
-  const int x = tbx * OX - K + lane;
-  const int y0 = tby * OY - K + w * RY;
+  const int xt = tbx * OX - K, yt = tby * OY - K;   // tile origin
+  const int x = xt + lane;
+  const int y0 = yt + w * RY;
   const bool x_in = x >= 0 && x < nx;
   const bool x_out = lane >= K && lane < K + OX && x_in;
-  bool row_in[RY], row_out[RY];
+  FusedState<K, FIELD> st;
 #pragma unroll
   for (int r = 0; r < RY; r++) {
     const int y = y0 + r, ty = w * RY + r;
-    row_in[r] = x_in && y >= 0 && y < ny;
-    row_out[r] = x_out && y >= 0 && y < ny && ty >= K && ty < K + OY;
+    st.row_in[r] = x_in && y >= 0 && y < ny;
+    st.row_out[r] = x_out && y >= 0 && y < ny && ty >= K && ty < K + OY;
   }
   const int zlo = zo_lo + tbz * fz;
   const int zhi = min(zlo + fz, zo_hi);
   const ptrdiff_t plane = (ptrdiff_t)nx * (ptrdiff_t)ny;
   const ptrdiff_t col0 = (ptrdiff_t)y0 * nx + x;   // row 0 of this thread's strip
-
-  float win[K][3][RY];   // win[s][j][r]: level s at plane (newest - 2 + j)
-  float cw[K][RY];       // c0 at planes z-1 .. z-K (FIELD)
 #pragma unroll
   for (int s = 0; s < K; s++)
 #pragma unroll
     for (int r = 0; r < RY; r++) {
-      win[s][0][r] = win[s][1][r] = win[s][2][r] = 0.0f;
-      cw[s][r] = 0.0f;
+      st.win[s][0][r] = st.win[s][1][r] = st.win[s][2][r] = 0.0f;
+      st.cw[s][r] = 0.0f;
     }
-
   for (int i = (int)threadIdx.x; i < 2 * K * FW * 2 * 64; i += 64 * FW) (&edge[0][0][0][0][0])[i] = 0.0f;
   __syncthreads();
-
-  for (int z = zlo - K; z < zhi + K; z++) {
-    const int par = z & 1;
-    // level 0: input plane z
-    {
-      const bool p_in = gz0 + z >= 0 && gz0 + z < nz;
-#pragma unroll
-      for (int r = 0; r < RY; r++) {
-        win[0][0][r] = win[0][1][r];
-        win[0][1][r] = win[0][2][r];
-        win[0][2][r] = (p_in && row_in[r]) ? in[(ptrdiff_t)z * plane + col0 + (ptrdiff_t)r * nx] : 0.0f;
-      }
-    }
-    if (FIELD) {
-      const int p = z - 1;
-      const bool p_in = gz0 + p >= 0 && gz0 + p < nz;
-#pragma unroll
-      for (int s = K - 1; s > 0; s--)
-#pragma unroll
-        for (int r = 0; r < RY; r++) cw[s][r] = cw[s - 1][r];
-#pragma unroll
-      for (int r = 0; r < RY; r++)
-        cw[0][r] = (p_in && row_in[r]) ? c0f[(ptrdiff_t)p * plane + col0 + (ptrdiff_t)r * nx] : 0.0f;
-    }
-    // levels 1..K: plane z - s from level s-1's window
-#pragma unroll
-    for (int s = 1; s <= K; s++) {
-      const int p = z - s;
-      const bool p_in = gz0 + p >= 0 && gz0 + p < nz;
-      const float(&lo)[3][RY] = win[s - 1];
-      // y neighbours across the strip ends: the adjacent waves' edge rows of
-      // level s-1 at plane p, published at the end of the previous plane
-      const float up = w > 0 ? edge[par ^ 1][s - 1][w - 1][1][lane] : 0.0f;
-      const float dn = w < FW - 1 ? edge[par ^ 1][s - 1][w + 1][0][lane] : 0.0f;
-      float nv[RY];
-#pragma unroll
-      for (int r = 0; r < RY; r++) {
-        const float cur = lo[1][r];
-        const float xm = lane_from_left(cur);
-        const float xp = lane_from_right(cur);
-        const float ym = r > 0 ? lo[1][r - 1] : up;
-        const float yp = r < RY - 1 ? lo[1][r + 1] : dn;
-        const float c0 = FIELD ? cw[s - 1][r] : c.c0;
-        const float v = star7_point(c0, cur, xm, xp, ym, yp, lo[0][r], lo[2][r], c);
-        nv[r] = (p_in && row_in[r]) ? v : 0.0f;
-      }
-      if (s < K) {
-#pragma unroll
-        for (int r = 0; r < RY; r++) {
-          win[s][0][r] = win[s][1][r];
-          win[s][1][r] = win[s][2][r];
-          win[s][2][r] = nv[r];
-        }
-      } else if (p >= zlo && p < zhi) {
-#pragma unroll
-        for (int r = 0; r < RY; r++)
-          if (row_out[r]) out[(ptrdiff_t)p * plane + col0 + (ptrdiff_t)r * nx] = nv[r];
-      }
-    }
-    // publish the edge rows of the planes just made (levels 0..K-1)
-#pragma unroll
-    for (int s = 0; s < K; s++) {
-      edge[par][s][w][0][lane] = win[s][2][0];
-      edge[par][s][w][1][lane] = win[s][2][RY - 1];
-    }
-    __syncthreads();
-  }
+  // the whole tile and its planes inside the grid: no boundary masking
+  const bool interior = xt >= 0 && xt + 64 <= nx && yt >= 0 && yt + FTY <= ny && gz0 + zlo - K >= 0 &&
+                        gz0 + zhi + K <= nz;
+  if (interior)
+    fused_march<K, FIELD, false>(st, edge, in, out, c0f, plane, col0, nx, gz0, nz, zlo, zhi, lane, w, c);
+  else
+    fused_march<K, FIELD, true>(st, edge, in, out, c0f, plane, col0, nx, gz0, nz, zlo, zhi, lane, w, c);
 }
 
 template <int K>
@@ -235,7 +286,7 @@ hipError_t launch_fused(const float *in, float *out, const float *c0f, int64_t n
   // z chunk: enough workgroups to cover the chip about twice
   const int64_t nz_out = zo_hi - zo_lo;
   const int64_t xy = (int64_t)nbx * nby;
-  int64_t nbz = std::max<int64_t>(1, std::min<int64_t>(nz_out / (2 * K), (512 + xy - 1) / xy));
+  int64_t nbz = std::max<int64_t>(1, std::min<int64_t>(nz_out / (2 * K), (kFusedTargetWgs + xy - 1) / xy));
   const int fz = (int)((nz_out + nbz - 1) / nbz);
   nbz = (nz_out + fz - 1) / fz;
   const int64_t nb = xy * nbz;
