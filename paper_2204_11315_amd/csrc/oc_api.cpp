@@ -113,6 +113,7 @@ oc::PlanInput plan_input(const oc_grid *g, const oc_stencil *st, const oc_config
   in.slots = c->ring_slots ? c->ring_slots : 3;
   in.prefetch = c->prefetch ? c->prefetch : -1;
   in.fuse = c->fuse_steps ? c->fuse_steps : oc::kMaxFused;
+  in.share = c->share_overlap >= 0;
   return in;
 }
 

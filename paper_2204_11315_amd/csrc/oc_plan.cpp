@@ -152,6 +152,12 @@ int make_plan(const PlanInput &in, Plan *out) {
   p.host_aux_bytes = 0;
   if (in.kind == KIND_WAVE25) p.host_aux_bytes = p.host_field_bytes;
   if (in.c0_field) p.host_aux_bytes = (size_t)cells * 4u;
+  // region sharing (Sec. 3.1, Fig. 2): consecutive slabs of a sweep both load
+  // the 2h planes around their common face; the later one takes them from the
+  // earlier one's input on the device.  The earlier input must survive its own
+  // kernels: coded inputs live in the staging slot, past the encoder's output;
+  // raw inputs survive only when one stencil launch covers all k steps.
+  p.share = in.share && in.kind == KIND_STAR7 && p.slabs.size() >= 2 && (p.coded || in.k <= in.fuse);
   *out = p;
   return ST_OK;
 }
@@ -261,6 +267,9 @@ void build_ops(const Plan &p, int64_t sweeps, int steps_last, int src, int64_t s
     int t, j, q, srcl, dstl, ks;
     int64_t loc0, nload, nz_int;
     const Slab *sl;
+    int64_t sh;       // planes taken from the previous slab's input (region sharing)
+    int pq;           // previous slab's slot
+    int64_t sh_src;   // local plane of the shared planes in the previous slab's buffer
   };
   auto geo = [&](int64_t g) {
     Geo x;
@@ -274,8 +283,19 @@ void build_ops(const Plan &p, int64_t sweeps, int steps_last, int src, int64_t s
     x.loc0 = x.sl->l0 - x.sl->gz0;   // local plane of the first loaded plane
     x.nload = x.sl->l1 - x.sl->l0;
     x.nz_int = x.sl->z1 - x.sl->z0;
+    x.pq = (int)((g + NQ - 1) % NQ);
+    x.sh = 0;
+    x.sh_src = 0;
+    if (p.share && x.j > 0) {
+      const Slab &pv = p.slabs[(size_t)x.j - 1];
+      x.sh = std::max<int64_t>(0, std::min(pv.l1, x.sl->l1) - x.sl->l0);
+      x.sh_src = x.sl->l0 - pv.gz0;
+    }
     return x;
   };
+  // slab g's slot is next written by the copy-in of slab g + NQ; the shared
+  // planes of slab g are read by slab g + 1's overlap copy
+  auto has_share_copy = [&](int64_t g) { return p.share && g >= 0 && g < total && g % ns != 0; };
   // fields copied in: (host store, base offset, working buffer, coded?)
   struct In { int host_id; size_t host_base; int buf; bool coded; };
   auto inputs = [&](const Geo &x, In *fin) {
@@ -299,6 +319,13 @@ void build_ops(const Plan &p, int64_t sweeps, int steps_last, int src, int64_t s
     const int nin = inputs(x, fin);
     std::vector<int> w;
     if (g >= NQ) w.push_back(B.ev.free(x.q));        // slot's previous copy-back done
+    if (g >= NQ && has_share_copy(g - NQ + 1)) {
+      // the slot's previous slab passed planes on to the next slab; wait for
+      // that copy if this copy-in overwrites any of them
+      const Geo nx1 = geo(g - NQ + 1);
+      const int64_t wlo = x.loc0 + x.sh, whi = x.loc0 + x.nload;
+      if (wlo < whi && wlo < nx1.sh_src + nx1.sh && nx1.sh_src < whi) w.push_back(B.ev.shr(x.q));
+    }
     if (x.t > 0) {                                   // planes written by last sweep's copy-backs
       B.writers_of(x.sl->l0, x.sl->l1, &nb);
       for (int jj : nb) w.push_back(B.ev.d2h((x.t - 1) & 1, jj));
@@ -308,23 +335,28 @@ void build_ops(const Plan &p, int64_t sweeps, int steps_last, int src, int64_t s
     for (int f = 0; f < nin; f++) {
       Op o = B.blank(OP_H2D, S_IN);
       o.host_id = (int8_t)fin[f].host_id;
+      // the main field skips the planes the overlap copy brings (f == 0)
+      const int64_t skip = f == 0 ? x.sh : 0;
       if (fin[f].coded) {
-        o.dev_dst = (int64_t)(p.off_stage[x.q] + (size_t)ncoded * (size_t)(x.nload / 4) * p.layer_bytes);
-        o.host_off = (int64_t)(fin[f].host_base + (size_t)(x.sl->l0 / 4) * p.layer_bytes);
-        o.bytes = (int64_t)((size_t)(x.nload / 4) * p.layer_bytes);
+        // staging slot: layer of local plane z at position z / 4, so the
+        // planes shared with the next slab lie past the encoder's output
+        o.dev_dst = (int64_t)(p.off_stage[x.q] + (size_t)ncoded * (size_t)(x.sl->planes / 4) * p.layer_bytes +
+                              (size_t)((x.loc0 + skip) / 4) * p.layer_bytes);
+        o.host_off = (int64_t)(fin[f].host_base + (size_t)((x.sl->l0 + skip) / 4) * p.layer_bytes);
+        o.bytes = (int64_t)((size_t)((x.nload - skip) / 4) * p.layer_bytes);
         ncoded++;
       } else if (c0_staged && fin[f].buf == 2) {
         o.dev_dst = (int64_t)(p.off_ro_stage[x.q] + (size_t)x.loc0 * p.plane_bytes);
         o.host_off = (int64_t)((size_t)x.sl->l0 * p.plane_bytes);
         o.bytes = (int64_t)((size_t)x.nload * p.plane_bytes);
       } else {
-        o.dev_dst = (int64_t)(B.work(x.q, fin[f].buf) + (size_t)x.loc0 * p.plane_bytes);
-        o.host_off = (int64_t)(fin[f].host_base + (size_t)x.sl->l0 * p.plane_bytes);
-        o.bytes = (int64_t)((size_t)x.nload * p.plane_bytes);
+        o.dev_dst = (int64_t)(B.work(x.q, fin[f].buf) + (size_t)(x.loc0 + skip) * p.plane_bytes);
+        o.host_off = (int64_t)(fin[f].host_base + (size_t)(x.sl->l0 + skip) * p.plane_bytes);
+        o.bytes = (int64_t)((size_t)(x.nload - skip) * p.plane_bytes);
       }
       o.slab = x.j;
       o.sweep = x.t;
-      B.push(o);
+      if (o.bytes > 0) B.push(o);
     }
     B.rec(S_IN, B.ev.in(x.q));
     B.rec(S_IN, B.ev.h2d(x.t & 1, x.j));
@@ -337,11 +369,32 @@ void build_ops(const Plan &p, int64_t sweeps, int steps_last, int src, int64_t s
     In fin[3];
     const int nin = inputs(x, fin);
     B.wait(S_COMPUTE, B.ev.in(x.q));
+    if (x.sh > 0) {
+      // region sharing: the planes around the common face come from the
+      // previous slab's input (device-to-device move, raw marker z_hi < 0)
+      Op o = B.blank(OP_DEC, S_COMPUTE);
+      if (p.coded) {
+        o.dev_src = (int64_t)(p.off_stage[x.pq] + (size_t)(x.sh_src / 4) * p.layer_bytes);
+        o.dev_dst = (int64_t)(p.off_stage[x.q] + (size_t)(x.loc0 / 4) * p.layer_bytes);
+        o.bytes = (int64_t)((size_t)(x.sh / 4) * p.layer_bytes);
+      } else {
+        o.dev_src = (int64_t)(B.work(x.pq, 0) + (size_t)x.sh_src * p.plane_bytes);
+        o.dev_dst = (int64_t)(B.work(x.q, 0) + (size_t)x.loc0 * p.plane_bytes);
+        o.bytes = (int64_t)((size_t)x.sh * p.plane_bytes);
+      }
+      o.z_hi = -1;
+      o.planes = x.sh;
+      o.slab = x.j;
+      o.sweep = x.t;
+      B.push(o);
+      B.rec(S_COMPUTE, B.ev.shr(x.pq));
+    }
     int ncoded = 0;
     for (int f = 0; f < nin; f++) {
       if (fin[f].coded) {
         Op o = B.blank(OP_DEC, S_COMPUTE);
-        o.dev_src = (int64_t)(p.off_stage[x.q] + (size_t)ncoded * (size_t)(x.nload / 4) * p.layer_bytes);
+        o.dev_src = (int64_t)(p.off_stage[x.q] + (size_t)ncoded * (size_t)(x.sl->planes / 4) * p.layer_bytes +
+                              (size_t)(x.loc0 / 4) * p.layer_bytes);
         o.dev_dst = (int64_t)(B.work(x.q, fin[f].buf) + (size_t)x.loc0 * p.plane_bytes);
         o.z_hi = x.nload / 4;
         o.planes = x.nload;
@@ -447,8 +500,15 @@ void build_ops(const Plan &p, int64_t sweeps, int steps_last, int src, int64_t s
   // depends on have been issued (with few slabs per sweep that limits the
   // look-ahead), since a wait can only name an event already recorded.
   const int L = p.prefetch;
-  int64_t next_in = 0, outs_issued = 0;
+  int64_t next_in = 0, outs_issued = 0, computes_issued = 0;
   auto in_ready = [&](int64_t gi) {
+    // with region sharing, the copy-in that reuses a slot waits for the
+    // overlap copy of the slab after the slot's previous one
+    if (gi >= NQ && has_share_copy(gi - NQ + 1) && gi - NQ + 1 >= computes_issued) {
+      const Geo xi = geo(gi), nx1 = geo(gi - NQ + 1);
+      const int64_t wlo = xi.loc0 + xi.sh, whi = xi.loc0 + xi.nload;
+      if (wlo < whi && wlo < nx1.sh_src + nx1.sh && nx1.sh_src < whi) return false;
+    }
     const int t = (int)(gi / ns);
     if (t == 0) return true;
     const Slab &sl = p.slabs[(size_t)(gi % ns)];
@@ -461,6 +521,7 @@ void build_ops(const Plan &p, int64_t sweeps, int steps_last, int src, int64_t s
     while (next_in < total && next_in <= g + L && in_ready(next_in)) issue_in(next_in++);
     int res[2];
     issue_compute(g, res);
+    computes_issued = g + 1;
     issue_out(g, res);
     outs_issued = g + 1;
   }

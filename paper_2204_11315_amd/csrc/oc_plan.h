@@ -68,6 +68,7 @@ struct PlanInput {
   int slots = 3;          // staging ring slots (2..8)
   int prefetch = -1;      // copy-ins issued ahead of the kernels (-1 = slots - 1)
   int fuse = 4;           // STAR7: time steps per stencil launch (1..kMaxFused)
+  bool share = false;     // keep the overlap of consecutive slabs on the device
 };
 
 constexpr int kMaxSlots = 8;
@@ -85,6 +86,7 @@ struct Plan {
   bool ro_coded = false;   // read-only field kept coded on the host
   size_t plane_bytes = 0;  // nx*ny*4
   size_t layer_bytes = 0;  // coded bytes of 4 planes
+  bool share = false;      // region sharing in effect (STAR7; raw only with one stencil group)
   int slots = 3;           // staging ring slots
   int prefetch = 2;        // copy-ins issued ahead
   int n_work_sets = 1;     // working-buffer sets (1 shared, or one per ring slot)
@@ -123,9 +125,10 @@ struct EventIds {
   int in(int q) const { return q; }
   int out(int q) const { return kMaxSlots + q; }
   int free(int q) const { return 2 * kMaxSlots + q; }
-  int h2d(int parity, int j) const { return 3 * kMaxSlots + parity * n_slabs + j; }
-  int d2h(int parity, int j) const { return 3 * kMaxSlots + 2 * n_slabs + parity * n_slabs + j; }
-  int count() const { return 3 * kMaxSlots + 4 * n_slabs; }
+  int shr(int q) const { return 3 * kMaxSlots + q; }   // slot q's overlap copied onward
+  int h2d(int parity, int j) const { return 4 * kMaxSlots + parity * n_slabs + j; }
+  int d2h(int parity, int j) const { return 4 * kMaxSlots + 2 * n_slabs + parity * n_slabs + j; }
+  int count() const { return 4 * kMaxSlots + 4 * n_slabs; }
 };
 
 // Operation list of `sweeps` consecutive sweeps starting from host level `src`

@@ -46,7 +46,8 @@ class Config(ctypes.Structure):
                 ("slab_planes", ctypes.c_int32), ("rate_bits", ctypes.c_int32),
                 ("single_buffer", ctypes.c_int32), ("timing", ctypes.c_int32),
                 ("ring_slots", ctypes.c_int32), ("prefetch", ctypes.c_int32),
-                ("fuse_steps", ctypes.c_int32), ("copy_back", ctypes.c_int32)]
+                ("fuse_steps", ctypes.c_int32), ("copy_back", ctypes.c_int32),
+                ("share_overlap", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -176,7 +177,8 @@ def host_aux_bytes(shape, stencil: Stencil, rate: int) -> int:
 
 
 def plan_config(k: int, slab_planes: int, rate: int, single_buffer: bool = True,
-                budget: int = 0, ring_slots: int = 0, prefetch: int = 0, fuse: int = 0) -> Config:
+                budget: int = 0, ring_slots: int = 0, prefetch: int = 0, fuse: int = 0,
+                share: bool = False) -> Config:
     """A Config carrying only the plan fields."""
     cfg = Config()
     cfg.k = int(k)
@@ -187,31 +189,32 @@ def plan_config(k: int, slab_planes: int, rate: int, single_buffer: bool = True,
     cfg.ring_slots = int(ring_slots)
     cfg.prefetch = int(prefetch)
     cfg.fuse_steps = int(fuse)
+    cfg.share_overlap = 1 if share else -1
     return cfg
 
 
 def plan_bytes(shape, stencil: Stencil, k: int, slab_planes: int, rate: int,
                single_buffer: bool = True, budget: int = 0, ring_slots: int = 0,
-               prefetch: int = 0, fuse: int = 0) -> int:
+               prefetch: int = 0, fuse: int = 0, share: bool = False) -> int:
     g = make_grid(shape)
-    cfg = plan_config(k, slab_planes, rate, single_buffer, budget, ring_slots, prefetch, fuse)
+    cfg = plan_config(k, slab_planes, rate, single_buffer, budget, ring_slots, prefetch, fuse, share)
     return int(lib().oc_plan_bytes(_ref(g), _ref(stencil), _ref(cfg)))
 
 
 def check_plan(shape, stencil: Stencil, k: int, slab_planes: int, rate: int, sweeps: int,
                single_buffer: bool = True, budget: int = 0, mutate: int = 0, i: int = 0,
-               ring_slots: int = 0, prefetch: int = 0, fuse: int = 0) -> int:
+               ring_slots: int = 0, prefetch: int = 0, fuse: int = 0, share: bool = False) -> int:
     g = make_grid(shape)
-    cfg = plan_config(k, slab_planes, rate, single_buffer, budget, ring_slots, prefetch, fuse)
+    cfg = plan_config(k, slab_planes, rate, single_buffer, budget, ring_slots, prefetch, fuse, share)
     return int(lib().oc_debug_check_plan(_ref(g), _ref(stencil), _ref(cfg), int(sweeps),
                                          int(mutate), int(i)))
 
 
 def plan_ops(shape, stencil: Stencil, k: int, slab_planes: int, rate: int, sweeps: int,
              single_buffer: bool = True, budget: int = 0, ring_slots: int = 0, prefetch: int = 0,
-             fuse: int = 0):
+             fuse: int = 0, share: bool = False):
     g = make_grid(shape)
-    cfg = plan_config(k, slab_planes, rate, single_buffer, budget, ring_slots, prefetch, fuse)
+    cfg = plan_config(k, slab_planes, rate, single_buffer, budget, ring_slots, prefetch, fuse, share)
     nw = ctypes.c_int64(0)
     n = int(lib().oc_debug_plan_ops(_ref(g), _ref(stencil), _ref(cfg), int(sweeps), _ref(nw)))
     return n, int(nw.value)
@@ -219,10 +222,10 @@ def plan_ops(shape, stencil: Stencil, k: int, slab_planes: int, rate: int, sweep
 
 def plan_dump(shape, stencil: Stencil, k: int, slab_planes: int, rate: int, sweeps: int,
               single_buffer: bool = True, budget: int = 0, ring_slots: int = 0,
-              prefetch: int = 0, fuse: int = 0) -> str:
+              prefetch: int = 0, fuse: int = 0, share: bool = False) -> str:
     """Text listing of the operation list the executor would issue."""
     g = make_grid(shape)
-    cfg = plan_config(k, slab_planes, rate, single_buffer, budget, ring_slots, prefetch, fuse)
+    cfg = plan_config(k, slab_planes, rate, single_buffer, budget, ring_slots, prefetch, fuse, share)
     n = int(lib().oc_debug_plan_dump(_ref(g), _ref(stencil), _ref(cfg), int(sweeps), None, 0))
     if n < 0:
         raise OCError(n, "oc_debug_plan_dump", status_str(n))
@@ -352,12 +355,15 @@ class OutOfCore:
     budget = bytes of device memory the library may use (one torch allocation).
     rate = 0 keeps raw FP32 on the host; 1..32 keeps fixed-rate codes.  k =
     steps per residency; slab_planes = S (0 = largest that fits the budget).
+    fuse = 7-point steps per stencil launch (0 = 4); copy_back = workgroups of
+    the copy-back kernel (0 = 4, -1 = runtime copies); share = region sharing
+    (the overlap of consecutive slabs stays on the device).
     """
 
     def __init__(self, shape, c=C_CONFIG1, k: int = 4, rate: int = 0, budget: int = 512 << 20,
                  slab_planes: int = 0, single_buffer: bool = True, c0_field: bool = False,
                  timing: bool = False, ring_slots: int = 0, prefetch: int = 0, device=None,
-                 stencil: Stencil = None, fuse: int = 0, copy_back: int = 0):
+                 stencil: Stencil = None, fuse: int = 0, copy_back: int = 0, share: bool = True):
         torch = _torch()
         self.shape = tuple(int(v) for v in shape)
         self.rate = int(rate)
@@ -367,7 +373,7 @@ class OutOfCore:
         self.grid = make_grid(self.shape)
         self.device = torch.device(device if device is not None else "cuda")
         need = plan_bytes(self.shape, self.stencil, k, slab_planes, rate, single_buffer, budget,
-                          ring_slots, prefetch, fuse)
+                          ring_slots, prefetch, fuse, share)
         if need == 0:
             raise OCError(OC_ERR_BUDGET, "plan", "no slab depth fits the budget")
         self.arena = torch.empty(int(budget), dtype=torch.uint8, device=self.device)
@@ -395,6 +401,7 @@ class OutOfCore:
         cfg.prefetch = int(prefetch)
         cfg.fuse_steps = int(fuse)
         cfg.copy_back = int(copy_back)
+        cfg.share_overlap = 1 if share else -1
         self.cfg = cfg
         h = ctypes.c_void_p()
         torch.cuda.synchronize(self.device)

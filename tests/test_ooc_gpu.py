@@ -141,9 +141,41 @@ def test_fused_stencil_launches_equal_single_steps_bitwise(fuse, R):
     assert st["n_stencil"] == 6 * -(-3 // fuse)      # the short sweep of 3 steps
 
 
+@pytest.mark.parametrize("k,S,steps", [(4, 8, 10), (4, 4, 8), (3, 12, 7), (1, 12, 3), (2, 20, 6)])
+def test_region_sharing_uncompressed_equals_incore_bitwise(k, S, steps):
+    u0 = inputs.modes_field(SHAPE, seed=14)
+    got, st = run_ooc(u0, steps, k=k, rate=0, slab_planes=S, share=True)
+    want = oc.star7_incore(_dev(u0), C, steps).cpu().numpy()
+    assert np.array_equal(got.view(np.uint32), want.view(np.uint32))
+    unshared, st0 = run_ooc(u0, steps, k=k, rate=0, slab_planes=S, share=False)
+    assert np.array_equal(got.view(np.uint32), unshared.view(np.uint32))
+    assert st["bytes_h2d"] < st0["bytes_h2d"]
+
+
+@pytest.mark.parametrize("R", [8, 16])
+@pytest.mark.parametrize("swb", [True, False])
+@pytest.mark.parametrize("k,S,steps", [(4, 8, 12), (3, 12, 7), (4, 4, 8)])
+def test_region_sharing_compressed_equals_incore_composition_bitwise(R, swb, k, S, steps):
+    u0 = inputs.grf_field(SHAPE, seed=15)
+    got, st = run_ooc(u0, steps, k=k, rate=R, slab_planes=S, single_buffer=swb, budget=64 << 20,
+                      share=True)
+    want = gpu_compressed_incore(u0, R, k, steps)
+    assert np.array_equal(got.view(np.uint32), want.view(np.uint32))
+
+
+def test_region_sharing_with_c0_field_and_split_runs():
+    u0 = inputs.grf_field(SHAPE, seed=16)
+    c0 = inputs.c0_field(SHAPE, seed=17)
+    for R in (0, 8):
+        kw = dict(k=4, rate=R, slab_planes=8, c0_field=True, runs=[5, 8])
+        a, _ = run_ooc(u0, 0, c0, share=True, **kw)
+        b, _ = run_ooc(u0, 0, c0, share=False, **kw)
+        assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+
+
 def test_stats_bytes_and_visits():
     u0 = inputs.modes_field(SHAPE, seed=10)
-    _, st = run_ooc(u0, 8, k=4, rate=8, slab_planes=8, timing=True)
+    _, st = run_ooc(u0, 8, k=4, rate=8, slab_planes=8, timing=True, share=False)
     lb = oc.codec_bytes(SHAPE, 8)
     layer = lb // (SHAPE[0] // 4)
     assert st["slab_visits"] == 2 * 6

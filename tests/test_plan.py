@@ -215,3 +215,72 @@ def test_adjoint_operation_list_race_free_and_minimal(shape, S, R, steps, every)
     assert oc.check_adjoint_plan(shape, st, steps, every, R, slab_planes=S) == 0
     for i in range(nw):
         assert oc.check_adjoint_plan(shape, st, steps, every, R, slab_planes=S, mutate=1, i=i) > 0
+
+
+SHARE_CASES = [((40, 12, 16), 4, 8), ((44, 8, 8), 4, 12), ((16, 8, 8), 4, 4), ((36, 8, 12), 3, 8),
+               ((44, 24, 40), 4, 8), ((48, 8, 8), 4, 4), ((24, 8, 8), 1, 12)]
+
+
+def _h2d_bytes(dump):
+    return sum(int(line.split("bytes=")[1].split()[0]) for line in dump.splitlines() if " H2D " in line)
+
+
+def _expected_h2d(shape, k, S, R, sweeps, share):
+    """Copy-in bytes from the slab geometry: each slab loads [z0 - h, z1 + h)
+    clipped to the grid; with region sharing a slab after the first of its
+    sweep skips the planes it shares with the previous slab."""
+    nz, ny, nx = shape
+    h = k if R == 0 else -(-k // 4) * 4
+    unit = nx * ny * 4 if R == 0 else oc.codec_bytes((4, ny, nx), R) / 4
+    slabs = [(z0, min(z0 + S, nz)) for z0 in range(0, nz, S)]
+    total = 0
+    for j, (z0, z1) in enumerate(slabs):
+        l0, l1 = max(0, z0 - h), min(nz, z1 + h)
+        sh = 0
+        if share and j > 0:
+            pz0, pz1 = slabs[j - 1]
+            sh = max(0, min(min(nz, pz1 + h), l1) - l0)
+        total += (l1 - l0 - sh) * unit
+    return int(total * sweeps)
+
+
+@pytest.mark.parametrize("shape,k,S", SHARE_CASES)
+@pytest.mark.parametrize("R", [0, 8])
+def test_region_sharing_race_free_and_minimal(shape, k, S, R):
+    for slots, pre in ((0, 0), (2, 1), (4, 3)):
+        kw = dict(ring_slots=slots, prefetch=pre, share=True)
+        n, nw = oc.plan_ops(shape, ST, k, S, R, 3, **kw)
+        assert oc.check_plan(shape, ST, k, S, R, 3, **kw) == 0
+        for i in range(nw):
+            assert oc.check_plan(shape, ST, k, S, R, 3, mutate=1, i=i, **kw) > 0, (slots, pre, i)
+        dump = oc.plan_dump(shape, ST, k, S, R, 3, **kw)
+        assert _h2d_bytes(dump) == _expected_h2d(shape, k, S, R, 3, True)
+        # one overlap copy per slab after the first of each sweep
+        copies = sum(" DEC " in line and "z=[0,-1)" in line for line in dump.splitlines())
+        assert copies == 3 * (len(range(0, shape[0], S)) - 1)
+    # the unshared plan loads every halo; the arena does not change
+    assert _h2d_bytes(oc.plan_dump(shape, ST, k, S, R, 3)) == _expected_h2d(shape, k, S, R, 3, False)
+    assert oc.plan_bytes(shape, ST, k, S, R, share=True) == oc.plan_bytes(shape, ST, k, S, R)
+
+
+def test_region_sharing_needs_an_intact_input():
+    # uncompressed with two stencil launches per slab: the first overwrites the
+    # input the next slab would share, so sharing stays off
+    shape, k, S = (40, 12, 16), 4, 8
+    d = oc.plan_dump(shape, ST, k, S, 0, 2, fuse=2, share=True)
+    assert "z=[0,-1)" not in d
+    assert _h2d_bytes(d) == _expected_h2d(shape, k, S, 0, 2, False)
+    # the 25-point wave keeps its halos
+    wst = oc.make_wave25(10.0, 1e-3, (4, 4, 4), 15.0, 1.0 / 15)
+    d = oc.plan_dump((32, 8, 8), wst, 2, 8, 8, 1, share=True)
+    assert "z=[0,-1)" not in d
+
+
+def test_region_sharing_cuts_config3_copy_ins_by_eleven_percent():
+    shape, k, S = (2048, 512, 512), 4, 64
+    for R in (8, 9, 16):
+        a = _h2d_bytes(oc.plan_dump(shape, ST, k, S, R, 1, budget=512 * MiB, share=True))
+        b = _h2d_bytes(oc.plan_dump(shape, ST, k, S, R, 1, budget=512 * MiB))
+        # 18 block layers per interior slab become 16 (the first slab of a
+        # sweep loads 17, the last 17 of which 2 are shared): 512 / 574
+        assert a / b == pytest.approx((17 + 30 * 16 + 15) / (17 + 30 * 18 + 17), rel=1e-12)
