@@ -193,11 +193,14 @@ def roofline_of(kern):
 
 def link_probe(reps=8, nbytes=64 << 20):
     """Pinned host<->device copy rates (GB/s) on this machine: each direction alone
-    and both directions at once (runtime copies on two streams)."""
+    and both directions at once (runtime copies on the pipeline's copy-in and
+    copy-back streams; a new stream could take the copy-back stream's hardware
+    queue away from it)."""
     import torch
+    from paper_2204_11315_amd import oc
     h = [torch.empty(nbytes, dtype=torch.uint8, pin_memory=True) for _ in range(2)]
     d = [torch.empty(nbytes, dtype=torch.uint8, device="cuda") for _ in range(2)]
-    s_in, s_out = torch.cuda.Stream(), torch.cuda.Stream()
+    s_in, _, s_out = oc.pipeline_streams()
 
     def run(up, down):
         torch.cuda.synchronize()
@@ -434,6 +437,7 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
     oc.lib()
+    oc.pipeline_streams()   # the pipeline's streams take their hardware queues first
     if args.kernels:
         kernel_probe(args.rate or 16)
         return

@@ -82,6 +82,7 @@ def _load():
             "ocref_inv_xform": (None, [P]),
             "ocref_to_negabinary": (ctypes.c_uint32, [ctypes.c_int32]),
             "ocref_from_negabinary": (ctypes.c_int32, [ctypes.c_uint32]),
+            "ocref_unread_mean": (ctypes.c_int32, [ctypes.c_int]),
             "ocref_sequency_order": (None, [P]),
             "ocref_quantize": (ctypes.c_int, [P, P, P]),
         }
@@ -232,6 +233,11 @@ def to_negabinary(c: int) -> int:
 
 def from_negabinary(u: int) -> int:
     return int(_load().ocref_from_negabinary(int(u)))
+
+
+def unread_mean(d: int) -> int:
+    """Value added at decode to a significant coefficient with d unread digits."""
+    return int(_load().ocref_unread_mean(int(d)))
 
 
 def sequency_order() -> np.ndarray:

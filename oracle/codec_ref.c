@@ -29,6 +29,14 @@
  *  7. Embedded coding of the 64 words, bit plane 31 down to 0, into the
  *     remaining B-8 bits (see encode_planes).  Coding stops the moment the
  *     budget is spent; unused slot bits are 0.
+ *  7'. Decoding reads the stream back.  Where the budget ended it before plane
+ *     0, a coefficient whose digits of planes d-1 .. 0 were never read but
+ *     which has a 1 among the digits that were read is reconstructed at the
+ *     mean of its unread digits: it gets floor((1 - (-2)^d) / 6) added, the
+ *     mean of sum_{j<d} b_j (-2)^j over equally likely digits b_j (the paper
+ *     fixes only the rate, Sec. 5; filling the unread digits with zeros
+ *     instead leaves a bias that piles up over repeated re-encodes).
+ *     Coefficients with no 1 read stay 0.
  *  8. Reconstruction: v = ldexp((float)q, Eb - 153), (float) rounding to
  *     nearest even, IEEE gradual underflow.
  */
@@ -174,14 +182,19 @@ static void encode_planes(const uint32_t *u, bitw_t *w) {
   }
 }
 /* mirror of encode_planes; stops at the budget, leaving unread bits 0 */
-static void decode_planes(uint32_t *u, bitr_t *r) {
+/* Decodes the planes into u; low[q] receives the lowest plane whose digit of
+ * coefficient q is known (32 = none): read verbatim or in a run, or known to
+ * be 0 from a closing group bit. */
+static void decode_planes(uint32_t *u, int *low, bitr_t *r) {
   int n = 0;
   memset(u, 0, 64 * sizeof(uint32_t));
+  for (int q = 0; q < 64; q++) low[q] = 32;
   for (int p = 31; p >= 0; p--) {
     for (int q = 0; q < n; q++) {
       int b = get_bit(r);
       if (b < 0) return;
       u[q] |= (uint32_t)b << p;
+      low[q] = p;
     }
     while (n < 64) {
       int g = get_bit(r);
@@ -191,11 +204,20 @@ static void decode_planes(uint32_t *u, bitr_t *r) {
         int b = get_bit(r);
         if (b < 0) return;
         u[n] |= (uint32_t)b << p;
+        low[n] = p;
         n++;
         if (b) break;
       }
     }
+    for (int q = n; q < 64; q++) low[q] = p;   /* closed by a group bit 0 (or n == 64) */
   }
+}
+
+/* floor((1 - (-2)^d) / 6): the mean of d unread negabinary digits, rounded down */
+int32_t ocref_unread_mean(int d) {
+  const int64_t pw = (int64_t)1 << d;
+  const int64_t num = 1 - ((d & 1) ? -pw : pw);
+  return (int32_t)(num >= 0 ? num / 6 : -((-num + 5) / 6));
 }
 
 /* ---- whole block -------------------------------------------------------- */
@@ -224,11 +246,17 @@ int ocref_block_decode(const uint8_t *slot, int R, float *v) {
   int Eb = 0;
   for (int b = 0; b < 8; b++) Eb |= get_bit(&r) << b;
   uint32_t u[64];
-  decode_planes(u, &r);
+  int low[64];
+  decode_planes(u, low, &r);
   int perm[64];
   ocref_sequency_order(perm);
   int32_t q[64];
-  for (int p = 0; p < 64; p++) q[perm[p]] = ocref_from_negabinary(u[p]);
+  for (int p = 0; p < 64; p++) {
+    int32_t c = ocref_from_negabinary(u[p]);
+    if (u[p] != 0 && low[p] > 0 && low[p] < 32)   /* step 7' */
+      c = (int32_t)((uint32_t)c + (uint32_t)ocref_unread_mean(low[p]));
+    q[perm[p]] = c;
+  }
   ocref_inv_xform(q);
   for (int t = 0; t < 64; t++) v[t] = ldexpf((float)q[t], Eb - 153);   /* step 8 */
   return OCREF_OK;

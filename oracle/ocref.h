@@ -72,6 +72,9 @@ void ocref_fwd_xform(int32_t *q);
 void ocref_inv_xform(int32_t *q);
 uint32_t ocref_to_negabinary(int32_t c);
 int32_t ocref_from_negabinary(uint32_t u);
+/* floor((1 - (-2)^d) / 6), 0 <= d <= 31: the value added at decode to a
+ * significant coefficient whose d lowest digits were not read (step 7') */
+int32_t ocref_unread_mean(int d);
 void ocref_sequency_order(int *perm);
 int ocref_quantize(const float *v, int32_t *q, int *Eb);
 

@@ -17,7 +17,9 @@
 // emits each plane in closed form: n verbatim bits, then one "group" token
 // per newly significant coefficient (found with a count-trailing-zeros on the
 // plane word shifted by n), then a closing 0 unless all 64 are significant.
-// The decoder mirrors it, reading 64-bit windows of its slot.
+// The decoder mirrors it, reading 64-bit windows of its slot; where the
+// budget cut the stream, a coefficient with a 1 read gets the mean of its
+// unread digits added (as the reference decoder does).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -152,6 +154,16 @@ __device__ __forceinline__ void bit_transpose32(uint32_t *A) {
     A[r] ^= t << 1;
     A[r + 1] ^= t;
   }
+}
+
+// floor((1 - (-2)^d) / 6): the mean of d unread negabinary digits, rounded
+// down.  d = 0 (nothing unread) and d = 32 (nothing read, so no 1 read either)
+// add nothing.
+__device__ __forceinline__ int32_t unread_mean(int d) {
+  if (d <= 0 || d >= 32) return 0;
+  const int64_t pw = (int64_t)1 << d;
+  const int64_t num = 1 - ((d & 1) ? -pw : pw);
+  return (int32_t)(num >= 0 ? num / 6 : -((-num + 5) / 6));
 }
 
 __device__ __forceinline__ uint64_t lowmask64(int n) {
@@ -389,31 +401,57 @@ __global__ __launch_bounds__(256) void k_decode(const uint32_t *__restrict__ in,
   uint32_t lo[32], hi[32];
   int n = 0;
   bool done = false;
+  // where the budget ended the stream: plane cut_p, with the digits of
+  // coefficients [0, cut_m) of that plane read (cut_p = -1: every plane read)
+  int cut_p = -1, cut_m = 0;
 #pragma unroll
   for (int p = 31; p >= 0; p--) {
     uint64_t x = 0;
     if (!done) {
+      const int pos0 = r.pos();
       x = r.get64(n);
-      while (n < 64) {
-        if (r.pos() >= BITS) { done = true; break; }
-        if (!r.get(1)) break;
-        int run = r.zero_run(64 - n);
-        if (run < 0) { done = true; break; }
-        x |= 1ull << (n + run);
-        n += run + 1;
+      int m = -1;   // -1: plane p complete
+      if (pos0 + n > BITS) {
+        m = BITS - pos0;   // cut inside the verbatim digits
+      } else {
+        while (n < 64) {
+          if (r.pos() >= BITS) { m = n; break; }   // no room for the group bit
+          if (!r.get(1)) break;                    // closing group bit
+          const int rs = r.pos();
+          const int run = r.zero_run(64 - n);
+          if (run < 0) { m = n + min(64 - n, BITS - rs); break; }   // cut inside a run
+          x |= 1ull << (n + run);
+          n += run + 1;
+        }
       }
-      if (r.pos() >= BITS) done = true;
+      if (m >= 0) {
+        done = true;
+        cut_p = p;
+        cut_m = m;
+      } else if (r.pos() >= BITS) {
+        done = true;
+        cut_p = p - 1;
+        cut_m = 0;
+      }
     }
     lo[p] = (uint32_t)x;
     hi[p] = (uint32_t)(x >> 32);
   }
   bit_transpose32(lo);
   bit_transpose32(hi);
+  // a coefficient with a 1 read gets the mean of its unread digits: its lowest
+  // read plane is cut_p below position cut_m, cut_p + 1 from there on
+  const int32_t mean_in = cut_p >= 0 ? unread_mean(cut_p) : 0;
+  const int32_t mean_out = cut_p >= 0 ? unread_mean(cut_p + 1) : 0;
   int32_t q[64];
 #pragma unroll
   for (int p = 0; p < 32; p++) {
-    q[kSeq.at[p]] = (int32_t)((lo[p] ^ 0xAAAAAAAAu) - 0xAAAAAAAAu);
-    q[kSeq.at[p + 32]] = (int32_t)((hi[p] ^ 0xAAAAAAAAu) - 0xAAAAAAAAu);
+    const int32_t a = (int32_t)((lo[p] ^ 0xAAAAAAAAu) - 0xAAAAAAAAu);
+    const int32_t b = (int32_t)((hi[p] ^ 0xAAAAAAAAu) - 0xAAAAAAAAu);
+    const int32_t ma = lo[p] ? (p < cut_m ? mean_in : mean_out) : 0;
+    const int32_t mb = hi[p] ? (p + 32 < cut_m ? mean_in : mean_out) : 0;
+    q[kSeq.at[p]] = (int32_t)((uint32_t)a + (uint32_t)ma);
+    q[kSeq.at[p + 32]] = (int32_t)((uint32_t)b + (uint32_t)mb);
   }
   xform_inv(q);
   float *base = out + ((4 * bz) * ny + 4 * by) * nx + 4 * bx;

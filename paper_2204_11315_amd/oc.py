@@ -268,8 +268,10 @@ _stream_pool = {}
 def pipeline_streams(device=None):
     """The three streams (copy-in, kernels, copy-back) every handle on `device`
     shares.  Created once per process: each new stream takes a hardware queue,
-    and once there are more streams than queues, streams share queues and the
-    copy-in stream would end up ordered behind unrelated copy-back work."""
+    and once there are more streams than queues, streams share queues; the
+    kernel and copy-back streams must not share one (the copy-back kernel
+    would then run in line with the decode / stencil / encode kernels), so a
+    program should call this before it creates streams of its own."""
     torch = _torch()
     dev = torch.device(device if device is not None else "cuda")
     if dev.index is None:

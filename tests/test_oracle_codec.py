@@ -4,8 +4,10 @@ Each step of the fixed-rate format is tied to something other than the C code:
 exact invertibility, the linear Haar map on inputs whose shifts are exact, the
 definition of base -2, the sort key of the coefficient order, an independent
 closed form of the embedded coder's stream length per bit plane, the embedded
-prefix property across rates, exact reconstruction of zero / constant blocks,
-the lossless bound, and the block layout of a field.
+prefix property across rates, the reconstruction of digits a budget cut off
+(against an independent model of the coder and the exact mean of the unread
+digits), exact reconstruction of zero / constant blocks, the lossless bound,
+and the block layout of a field.
 """
 import math
 
@@ -204,6 +206,103 @@ def test_decoder_on_streams_cut_at_plane_boundaries():
             qh = oracle.inv_xform(c)
             want = np.ldexp(qh.astype(np.float32), eb - 153).astype(np.float32)
             assert np.array_equal(got.view(np.uint32), want.view(np.uint32))
+
+
+# ---- step 7': reconstruction of digits the budget cut off ------------------------------
+def test_unread_mean_is_the_floored_mean_of_the_unread_digits():
+    from fractions import Fraction
+    # exhaustive for small d: average of sum_j b_j (-2)^j over all 2^d digit patterns
+    for d in range(0, 17):
+        total = 0
+        for pat in range(1 << d):
+            total += sum(((pat >> j) & 1) * (-2) ** j for j in range(d))
+        mean = Fraction(total, 1 << d)
+        assert oracle.unread_mean(d) == math.floor(mean), d
+    # larger d: each further digit adds its own mean (-2)^d / 2
+    mean = Fraction(0)
+    for d in range(0, 32):
+        assert oracle.unread_mean(d) == math.floor(mean), d
+        mean += Fraction((-2) ** d, 2)
+
+
+def coded_bits(u, budget):
+    """Independent model of step 7 (bit plane coding with group tests), cut at
+    `budget` bits: returns, per coefficient, the digits known to the decoder
+    (as a mask of planes) and the lowest known plane (32 = none)."""
+    known = [0] * 64
+    low = [32] * 64
+    used = 0
+    n = 0
+    for p in range(31, -1, -1):
+        x = sum(((u[q] >> p) & 1) << q for q in range(64))
+        for q in range(n):                          # verbatim digits
+            if used == budget:
+                return known, low
+            used += 1
+            known[q] |= 1 << p
+            low[q] = p
+        while n < 64:
+            if used == budget:                      # group bit
+                return known, low
+            used += 1
+            if (x >> n) == 0:
+                break
+            while True:                             # run up to the next 1
+                if used == budget:
+                    return known, low
+                used += 1
+                bit = (x >> n) & 1
+                known[n] |= 1 << p
+                low[n] = p
+                n += 1
+                if bit:
+                    break
+        for q in range(n, 64):                      # closed: the rest is 0 in plane p
+            known[q] |= 1 << p
+            low[q] = p
+    return known, low
+
+
+def test_budget_cut_reconstruction_matches_an_independent_model():
+    perm = oracle.sequency_order()
+    for v in rand_blocks(40, rng=np.random.default_rng(77)):
+        u, eb = plane_coefficients(v)
+        for R in (1, 2, 3, 5, 8, 9, 12, 16):
+            known, low = coded_bits(u, 64 * R - 8)
+            c = np.zeros(64, dtype=np.int32)
+            for o in range(64):
+                w = u[o] & known[o]
+                val = oracle.from_negabinary(w)
+                if w and 0 < low[o] < 32:
+                    val = (val + oracle.unread_mean(low[o]) + 2 ** 31) % 2 ** 32 - 2 ** 31
+                c[perm[o]] = val
+            want = np.ldexp(oracle.inv_xform(c).astype(np.float32), eb - 153).astype(np.float32)
+            slot, _ = oracle.block_encode(v, R)
+            got = oracle.block_decode(slot, R)
+            assert np.array_equal(got.view(np.uint32), want.view(np.uint32)), R
+
+
+def test_unread_mean_lowers_the_error_of_cut_streams():
+    """Smooth blocks at 8 bits per value: reconstructing the unread digits at
+    their mean gives a smaller squared error than filling them with zeros."""
+    perm = oracle.sequency_order()
+    rng = np.random.default_rng(5)
+    t = np.arange(64)
+    i, j, k = t % 4, (t // 4) % 4, t // 16
+    e_mean = e_zero = 0.0
+    for _ in range(60):
+        v = (np.sin(0.4 * i + 0.3 * j + 0.2 * k + rng.uniform(0, 6)) + 0.05 * rng.standard_normal(64))
+        v = v.astype(np.float32)
+        u, eb = plane_coefficients(v)
+        known, _ = coded_bits(u, 64 * 8 - 8)
+        c = np.zeros(64, dtype=np.int32)
+        for o in range(64):
+            c[perm[o]] = oracle.from_negabinary(u[o] & known[o])
+        zero = np.ldexp(oracle.inv_xform(c).astype(np.float32), eb - 153)
+        got = oracle.block_decode(oracle.block_encode(v, 8)[0], 8)
+        e_mean += float(np.sum((got.astype(np.float64) - v) ** 2))
+        e_zero += float(np.sum((zero.astype(np.float64) - v) ** 2))
+    assert e_mean < 0.8 * e_zero
 
 
 # ---- special cases and bounds ----------------------------------------------------------
