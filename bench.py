@@ -125,18 +125,19 @@ HBM_PEAK_GBS = 8000.0
 ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 
 # Per-kernel work figures measured with rocprofv3 on the slab-shaped kernel
-# probe (`bench.py --kernels --rate R`), one figure per code rate:
-# VALU wave-instructions per wave of 64 blocks (SQ_INSTS_VALU / SQ_WAVES).
-VALU_PER_WAVE = {("decode", 9): 4384.6, ("encode", 9): 5624.2,
-                 ("decode", 16): 4794.2, ("encode", 16): 6068.8}
-# HBM bytes per launch relative to the algorithmic bytes: FETCH_SIZE and
-# WRITE_SIZE of the slab-shaped probe launches (72 planes of 512 x 512), each
-# scaled by what the counter reads for a plain 256 MiB device copy (FETCH x 2,
-# WRITE x 1 KiB per unit).  Single-step stencil: 84.8 MB fetched for 75.5 MB
-# read, 75.5 MB written for 75.5 MB -> 1.06.  Decode at R = 16: 1.02 / 1.00;
-# encode at R = 16: 1.01 / 1.01.  None = not measured for the kernel as it
-# stands at this rate.
-TRAFFIC_RATIO = {"stencil": 1.06, "decode": None, "encode": None}
+# probe (`bench.py --kernels --rate R`, 512 x 512 planes), one figure per code
+# rate: VALU wave-instructions per wave of 64 blocks (SQ_INSTS_VALU / SQ_WAVES).
+VALU_PER_WAVE = {("decode", 8): 5336.0, ("encode", 8): 5540.0,
+                 ("decode", 9): 5430.0, ("encode", 9): 5624.0,
+                 ("decode", 16): 5985.0, ("encode", 16): 6069.0}
+# HBM bytes per launch over the algorithmic bytes, from FETCH_SIZE and
+# WRITE_SIZE of the same probe launches (each scaled by what it reads for a
+# plain 256 MiB device copy: FETCH x 2, WRITE x 1 KiB per unit), read and write
+# weighted by their algorithmic bytes.  Four fused 7-point steps over 72
+# planes: fetch 1.38 (tile halos and z-chunk overlap), write 1.01 -> 1.195.
+# Decode at R = 8: 1.04 of 18 MiB, 1.00 of 72 MiB -> 1.008; encode: 1.01 of
+# 64 MiB, 1.00 of 16 MiB -> 1.008.
+TRAFFIC_RATIO = {"stencil": 1.195, "decode": 1.008, "encode": 1.008}
 
 
 def kernel_roofline(stats, rate):
