@@ -88,11 +88,11 @@ typedef struct {
   int32_t copy_back;       /* device-to-host copies: n > 0 = a copy kernel of n workgroups
                               (1..1024) storing into the mapped pinned host pages; 0 = such a
                               kernel with 4 workgroups; -1 = the runtime's hipMemcpyAsync   */
-  int32_t share_overlap;   /* 7-point region sharing (Sec. 3.1, Fig. 2): a slab takes the
-                              2h planes around its lower face from the previous slab's
-                              input on the device instead of the host (coded runs, and
-                              uncompressed runs with k <= fuse_steps); 0 or 1 = on where it
-                              applies, -1 = off (every slab loads both halos)              */
+  int32_t share_overlap;   /* region sharing (Sec. 3.1, Fig. 2): a slab takes the 2h planes
+                              around its lower face from the previous slab's input on the
+                              device instead of the host (coded runs of both stencils, and
+                              uncompressed 7-point runs with k <= fuse_steps); 0 or 1 = on
+                              where it applies, -1 = off (every slab loads both halos)     */
 } oc_config;
 
 typedef struct {

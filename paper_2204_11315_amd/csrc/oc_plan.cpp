@@ -157,7 +157,10 @@ int make_plan(const PlanInput &in, Plan *out) {
   // earlier one's input on the device.  The earlier input must survive its own
   // kernels: coded inputs live in the staging slot, past the encoder's output;
   // raw inputs survive only when one stencil launch covers all k steps.
-  p.share = in.share && in.kind == KIND_STAR7 && p.slabs.size() >= 2 && (p.coded || in.k <= in.fuse);
+  // (the 25-point wave updates its raw inputs in place, so it shares only coded)
+  p.share = in.share && p.slabs.size() >= 2 &&
+            ((in.kind == KIND_STAR7 && (p.coded || in.k <= in.fuse)) ||
+             (in.kind == KIND_WAVE25 && p.coded && p.ro_coded));
   *out = p;
   return ST_OK;
 }
@@ -270,6 +273,7 @@ void build_ops(const Plan &p, int64_t sweeps, int steps_last, int src, int64_t s
     int64_t sh;       // planes taken from the previous slab's input (region sharing)
     int pq;           // previous slab's slot
     int64_t sh_src;   // local plane of the shared planes in the previous slab's buffer
+    int64_t pv_planes;   // the previous slab's buffer planes (its field stride in the slot)
   };
   auto geo = [&](int64_t g) {
     Geo x;
@@ -286,10 +290,12 @@ void build_ops(const Plan &p, int64_t sweeps, int steps_last, int src, int64_t s
     x.pq = (int)((g + NQ - 1) % NQ);
     x.sh = 0;
     x.sh_src = 0;
+    x.pv_planes = 0;
     if (p.share && x.j > 0) {
       const Slab &pv = p.slabs[(size_t)x.j - 1];
       x.sh = std::max<int64_t>(0, std::min(pv.l1, x.sl->l1) - x.sl->l0);
       x.sh_src = x.sl->l0 - pv.gz0;
+      x.pv_planes = pv.planes;
     }
     return x;
   };
@@ -335,8 +341,9 @@ void build_ops(const Plan &p, int64_t sweeps, int steps_last, int src, int64_t s
     for (int f = 0; f < nin; f++) {
       Op o = B.blank(OP_H2D, S_IN);
       o.host_id = (int8_t)fin[f].host_id;
-      // the main field skips the planes the overlap copy brings (f == 0)
-      const int64_t skip = f == 0 ? x.sh : 0;
+      // shared inputs (the coded fields, or the raw 7-point field) skip the
+      // planes the overlap copy brings
+      const int64_t skip = (fin[f].coded || (!p.coded && f == 0)) ? x.sh : 0;
       if (fin[f].coded) {
         // staging slot: layer of local plane z at position z / 4, so the
         // planes shared with the next slab lie past the encoder's output
@@ -371,22 +378,30 @@ void build_ops(const Plan &p, int64_t sweeps, int steps_last, int src, int64_t s
     B.wait(S_COMPUTE, B.ev.in(x.q));
     if (x.sh > 0) {
       // region sharing: the planes around the common face come from the
-      // previous slab's input (device-to-device move, raw marker z_hi < 0)
-      Op o = B.blank(OP_DEC, S_COMPUTE);
-      if (p.coded) {
-        o.dev_src = (int64_t)(p.off_stage[x.pq] + (size_t)(x.sh_src / 4) * p.layer_bytes);
-        o.dev_dst = (int64_t)(p.off_stage[x.q] + (size_t)(x.loc0 / 4) * p.layer_bytes);
-        o.bytes = (int64_t)((size_t)(x.sh / 4) * p.layer_bytes);
-      } else {
-        o.dev_src = (int64_t)(B.work(x.pq, 0) + (size_t)x.sh_src * p.plane_bytes);
-        o.dev_dst = (int64_t)(B.work(x.q, 0) + (size_t)x.loc0 * p.plane_bytes);
-        o.bytes = (int64_t)((size_t)x.sh * p.plane_bytes);
+      // previous slab's input (device-to-device moves, raw marker z_hi < 0):
+      // each coded field at its stride in the staging slot, or the raw field
+      int nsh = 0;
+      for (int f = 0; f < nin; f++) {
+        if (!(fin[f].coded || (!p.coded && f == 0))) continue;
+        Op o = B.blank(OP_DEC, S_COMPUTE);
+        if (p.coded) {
+          o.dev_src = (int64_t)(p.off_stage[x.pq] + (size_t)nsh * (size_t)(x.pv_planes / 4) * p.layer_bytes +
+                                (size_t)(x.sh_src / 4) * p.layer_bytes);
+          o.dev_dst = (int64_t)(p.off_stage[x.q] + (size_t)nsh * (size_t)(x.sl->planes / 4) * p.layer_bytes +
+                                (size_t)(x.loc0 / 4) * p.layer_bytes);
+          o.bytes = (int64_t)((size_t)(x.sh / 4) * p.layer_bytes);
+        } else {
+          o.dev_src = (int64_t)(B.work(x.pq, 0) + (size_t)x.sh_src * p.plane_bytes);
+          o.dev_dst = (int64_t)(B.work(x.q, 0) + (size_t)x.loc0 * p.plane_bytes);
+          o.bytes = (int64_t)((size_t)x.sh * p.plane_bytes);
+        }
+        o.z_hi = -1;
+        o.planes = x.sh;
+        o.slab = x.j;
+        o.sweep = x.t;
+        B.push(o);
+        nsh++;
       }
-      o.z_hi = -1;
-      o.planes = x.sh;
-      o.slab = x.j;
-      o.sweep = x.t;
-      B.push(o);
       B.rec(S_COMPUTE, B.ev.shr(x.pq));
     }
     int ncoded = 0;
@@ -453,7 +468,9 @@ void build_ops(const Plan &p, int64_t sweeps, int steps_last, int src, int64_t s
       for (int f = 0; f < p.n_rw; f++) {
         Op o = B.blank(OP_ENC, S_COMPUTE);
         o.dev_src = (int64_t)(B.work(x.q, res[f]) + (size_t)p.halo * p.plane_bytes);
-        o.dev_dst = (int64_t)(p.off_stage[x.q] + (size_t)f * (size_t)(x.nz_int / 4) * p.layer_bytes);
+        // field f at its input stride, so the shared layers past each
+        // field's output survive for the next slab
+        o.dev_dst = (int64_t)(p.off_stage[x.q] + (size_t)f * (size_t)(x.sl->planes / 4) * p.layer_bytes);
         o.z_hi = x.nz_int / 4;
         o.planes = x.nz_int;
         o.slab = x.j;
@@ -477,7 +494,7 @@ void build_ops(const Plan &p, int64_t sweeps, int steps_last, int src, int64_t s
       Op o = B.blank(OP_D2H, S_OUT);
       o.host_id = (int8_t)x.dstl;
       if (p.coded) {
-        o.dev_src = (int64_t)(p.off_stage[x.q] + (size_t)f * (size_t)(x.nz_int / 4) * p.layer_bytes);
+        o.dev_src = (int64_t)(p.off_stage[x.q] + (size_t)f * (size_t)(x.sl->planes / 4) * p.layer_bytes);
         o.host_off = (int64_t)((size_t)f * p.host_field_bytes + (size_t)(x.sl->z0 / 4) * p.layer_bytes);
         o.bytes = (int64_t)((size_t)(x.nz_int / 4) * p.layer_bytes);
       } else {

@@ -156,6 +156,22 @@ def test_fused_stencil_launches_race_free(fuse, k):
         assert launches == 5 * -(-k // fuse)
 
 
+def test_create_checks_its_arguments_before_touching_a_device():
+    # argument errors come back from oc_create before any buffer is looked at
+    import ctypes
+    g = oc.make_grid((40, 12, 16))
+    h = ctypes.c_void_p()
+    for cb in (-2, 1025):
+        cfg = oc.plan_config(4, 8, 8)
+        cfg.copy_back = cb
+        st = oc.lib().oc_create(oc._ref(g), oc._ref(ST), oc._ref(cfg), oc._ref(h))
+        assert st == oc.OC_ERR_ARG and not h.value
+    # a valid configuration without buffers is a budget error (no arena)
+    cfg = oc.plan_config(4, 8, 8)
+    assert oc.lib().oc_create(oc._ref(g), oc._ref(ST), oc._ref(cfg), oc._ref(h)) == oc.OC_ERR_BUDGET
+    assert oc.lib().oc_create(None, oc._ref(ST), oc._ref(cfg), oc._ref(h)) == oc.OC_ERR_ARG
+
+
 def test_invalid_ring_parameters():
     assert oc.plan_bytes((40, 12, 16), ST, 4, 8, 8, ring_slots=9) == 0
     assert oc.plan_bytes((40, 12, 16), ST, 4, 8, 8, ring_slots=1) == 0
@@ -270,10 +286,28 @@ def test_region_sharing_needs_an_intact_input():
     d = oc.plan_dump(shape, ST, k, S, 0, 2, fuse=2, share=True)
     assert "z=[0,-1)" not in d
     assert _h2d_bytes(d) == _expected_h2d(shape, k, S, 0, 2, False)
-    # the 25-point wave keeps its halos
+    # the uncompressed 25-point wave updates its inputs in place: no sharing
     wst = oc.make_wave25(10.0, 1e-3, (4, 4, 4), 15.0, 1.0 / 15)
-    d = oc.plan_dump((32, 8, 8), wst, 2, 8, 8, 1, share=True)
+    d = oc.plan_dump((32, 8, 8), wst, 2, 8, 0, 1, share=True)
     assert "z=[0,-1)" not in d
+
+
+@pytest.mark.parametrize("shape,k,S", [((32, 8, 8), 2, 8), ((48, 8, 12), 2, 16), ((40, 8, 8), 1, 8),
+                                       ((36, 12, 8), 2, 12)])
+def test_region_sharing_coded_wave_race_free_and_minimal(shape, k, S):
+    wst = oc.make_wave25(10.0, 1e-3, (4, 4, 4), 15.0, 1.0 / 15)
+    for slots, pre in ((0, 0), (4, 3)):
+        kw = dict(ring_slots=slots, prefetch=pre, share=True)
+        n, nw = oc.plan_ops(shape, wst, k, S, 8, 2, **kw)
+        assert oc.check_plan(shape, wst, k, S, 8, 2, **kw) == 0
+        for i in range(nw):
+            assert oc.check_plan(shape, wst, k, S, 8, 2, mutate=1, i=i, **kw) > 0, (slots, pre, i)
+        d = oc.plan_dump(shape, wst, k, S, 8, 2, **kw)
+        # three coded fields (p^n, p^{n-1}, velocity) move their shared layers per slab
+        copies = sum(" DEC " in line and "z=[0,-1)" in line for line in d.splitlines())
+        assert copies == 3 * 2 * (len(range(0, shape[0], S)) - 1)
+        d0 = oc.plan_dump(shape, wst, k, S, 8, 2, ring_slots=slots, prefetch=pre)
+        assert _h2d_bytes(d) < _h2d_bytes(d0)
 
 
 def test_region_sharing_cuts_config3_copy_ins_by_eleven_percent():
