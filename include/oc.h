@@ -24,7 +24,8 @@
  *  - "device" pointers are HIP device memory of the current device; "host"
  *    pointers are process memory (pinned memory makes copies asynchronous).
  *  - A handle is not thread-safe.  After OC_ERR_HIP the handle may only be
- *    destroyed; the host level that held the last complete sweep is intact.
+ *    destroyed; with two host levels the one that held the last complete
+ *    sweep is intact (with in_place the level may be partly updated).
  *  - Ghost cells outside the grid are zero (zero Dirichlet boundary).
  */
 #ifndef OC_H
@@ -93,6 +94,12 @@ typedef struct {
                               device instead of the host (coded runs of both stencils, and
                               uncompressed 7-point runs with k <= fuse_steps); 0 or 1 = on
                               where it applies, -1 = off (every slab loads both halos)     */
+  int32_t in_place;        /* 1 = one host level, host_level[0], updated in place by every
+                              sweep (Algorithm 1, Ensure); host_level[1] is ignored and may
+                              be NULL.  Needs region sharing in effect, or a single slab;
+                              otherwise oc_create returns OC_ERR_ARG.  A run that fails
+                              mid-sweep leaves that level partly updated.  0 = two levels
+                              that alternate as source and destination                      */
 } oc_config;
 
 typedef struct {
@@ -221,11 +228,15 @@ const char *oc_status_str(int status);
 int oc_debug_fail_after(oc_handle *h, int64_t n);
 /* Builds the operation list of `sweeps` sweeps (k steps each) for the plan
  * of (g, st, cfg) (plan fields only, as oc_plan_bytes), without a GPU, and runs the happens-before checker
- * over it: returns the number of unordered conflicting accesses plus sweeps
- * whose write-back does not cover the level (0 = race free and complete), or a
- * negative OC_ERR_* for a plan that cannot be made.
+ * over it: returns the number of unordered conflicting accesses, plus
+ * copy-ins that read host planes not last written by the previous sweep, plus
+ * sweeps whose write-back does not cover the level (0 = race free, reads the
+ * right state, complete), or a negative OC_ERR_* for a plan that cannot be made.
  * mutate: 0 none; 1 drop the i-th wait; 2 drop the epilogue (the last slab's
- * write-back); 3 swap op i with the next op of the same stream. */
+ * write-back); 3 swap op i with the next op of the same stream; 4 (in_place
+ * plans) turn region sharing off, so slabs copy their halos from the level
+ * being updated; 5 (two levels, sweeps >= 2) the second sweep copies in from
+ * the level the first sweep read. */
 int64_t oc_debug_check_plan(const oc_grid *g, const oc_stencil *st, const oc_config *cfg,
                             int64_t sweeps, int32_t mutate, int64_t i);
 /* Writes a text listing of that operation list (one op per line) into buf

@@ -114,6 +114,7 @@ oc::PlanInput plan_input(const oc_grid *g, const oc_stencil *st, const oc_config
   in.prefetch = c->prefetch ? c->prefetch : -1;
   in.fuse = c->fuse_steps ? c->fuse_steps : oc::kMaxFused;
   in.share = c->share_overlap >= 0;
+  in.in_place = c->in_place != 0;
   return in;
 }
 
@@ -576,7 +577,8 @@ int oc_create(const oc_grid *g, const oc_stencil *st, const oc_config *cfg, oc_h
   int r = oc::make_plan(plan_input(g, st, cfg), &p);
   if (r != oc::ST_OK) return r;
   if (!cfg->dev_arena || p.arena_bytes > cfg->dev_budget) return OC_ERR_BUDGET;
-  if (!cfg->host_level[0] || !cfg->host_level[1] || cfg->host_level_bytes < p.host_level_bytes)
+  if (!cfg->host_level[0] || (!p.in_place && !cfg->host_level[1]) ||
+      cfg->host_level_bytes < p.host_level_bytes)
     return OC_ERR_BUDGET;
   if (p.host_aux_bytes && (!cfg->host_aux || cfg->host_aux_bytes < p.host_aux_bytes))
     return OC_ERR_BUDGET;
@@ -592,7 +594,7 @@ int oc_create(const oc_grid *g, const oc_stencil *st, const oc_config *cfg, oc_h
   h->timing = cfg->timing != 0;
   h->arena = (uint8_t *)cfg->dev_arena;
   h->host[0] = (uint8_t *)cfg->host_level[0];
-  h->host[1] = (uint8_t *)cfg->host_level[1];
+  h->host[1] = p.in_place ? nullptr : (uint8_t *)cfg->host_level[1];
   h->host[2] = (uint8_t *)cfg->host_aux;
   for (int i = 0; i < 3; i++) h->host_dev[i] = mapped_host(h->host[i]);
   h->ckpt_valid = false;
@@ -656,7 +658,7 @@ int oc_run(oc_handle *h, int64_t steps) {
   auto t1 = std::chrono::steady_clock::now();
   if (r) return r;
   int cr = p.coded ? codec_check_and_clear() : OC_OK;
-  h->cur = (int)((h->cur + sweeps) & 1);
+  if (!p.in_place) h->cur = (int)((h->cur + sweeps) & 1);
   h->time_index += steps;
   double wall = std::chrono::duration<double>(t1 - t0).count();
   h->stats.wall_s = wall;
@@ -702,6 +704,8 @@ int adj_plan_for(const oc_handle *h, int64_t steps, int32_t every, int32_t rate,
   if (h->plan.coded) return OC_ERR_UNSUPPORTED;     // the forward of the adjoint runs raw
   if (steps < 1 || every < 1 || rate < 0 || rate > 32) return OC_ERR_ARG;
   oc::PlanInput in = h->plan.in;
+  in.share = false;       // the reverse sweeps keep their own two lambda levels
+  in.in_place = false;
   in.rate = rate;
   in.slab_planes = 0;
   in.budget = h->cfg.dev_budget;
@@ -937,6 +941,10 @@ int64_t oc_debug_check_plan(const oc_grid *g, const oc_stencil *st, const oc_con
   oc::Plan p;
   int r = oc::make_plan(plan_input(g, st, cfg), &p);
   if (r != oc::ST_OK) return r;
+  if (mutate == 4) {  // in place without region sharing: slabs reread updated planes
+    if (!p.in_place) return OC_ERR_ARG;
+    p.share = false;
+  }
   std::vector<oc::Op> ops;
   oc::build_ops(p, sweeps, p.in.k, 0, 0, &ops);
   if (mutate == 1) {  // drop the i-th wait
@@ -961,7 +969,11 @@ int64_t oc_debug_check_plan(const oc_grid *g, const oc_stencil *st, const oc_con
         std::swap(ops[(size_t)i], ops[j]);
         break;
       }
-  } else if (mutate != 0) {
+  } else if (mutate == 5) {  // second sweep copies in from the level the first one read
+    if (p.in_place || sweeps < 2) return OC_ERR_ARG;
+    for (auto &o : ops)
+      if (o.type == oc::OP_H2D && o.sweep == 1 && o.host_id <= oc::HOST_LEVEL1) o.host_id ^= 1;
+  } else if (mutate != 0 && mutate != 4) {
     return OC_ERR_ARG;
   }
   std::string why;

@@ -161,6 +161,12 @@ int make_plan(const PlanInput &in, Plan *out) {
   p.share = in.share && p.slabs.size() >= 2 &&
             ((in.kind == KIND_STAR7 && (p.coded || in.k <= in.fuse)) ||
              (in.kind == KIND_WAVE25 && p.coded && p.ro_coded));
+  // one host level updated in place (the Ensure clause of Algorithm 1): a
+  // slab's copy-back overwrites its interior planes, which the next slab of
+  // the sweep still needs as old values around their common face, so every
+  // face must be shared on the device (or there is only one slab)
+  if (in.in_place && !(p.share || p.slabs.size() == 1)) return ST_ARG;
+  p.in_place = in.in_place;
   *out = p;
   return ST_OK;
 }
@@ -281,8 +287,8 @@ void build_ops(const Plan &p, int64_t sweeps, int steps_last, int src, int64_t s
     x.j = (int)(g % ns);
     x.q = (int)(g % NQ);
     x.sl = &p.slabs[x.j];
-    x.srcl = (src + x.t) & 1;
-    x.dstl = (src + x.t + 1) & 1;
+    x.srcl = p.in_place ? 0 : (src + x.t) & 1;
+    x.dstl = p.in_place ? 0 : (src + x.t + 1) & 1;
     x.ks = (x.t == sweeps - 1) ? steps_last : p.in.k;
     x.loc0 = x.sl->l0 - x.sl->gz0;   // local plane of the first loaded plane
     x.nload = x.sl->l1 - x.sl->l0;
@@ -931,6 +937,48 @@ int64_t check_ops(const Plan &p, const std::vector<Op> &ops, std::string *why,
       }
     }
     for (const Access &a : acc) hist.push_back({st, a});
+  }
+  // every copy-in of sweep t must read the state sweep t-1 wrote (or the
+  // loaded state when t = 0), never a plane this sweep has already written
+  // back: with a single host level this is what makes the in-place update
+  // correct.  Conflicting host accesses are ordered (checked above), and a
+  // wait names only events recorded earlier in the list, so list order is
+  // their execution order.
+  if (check_writeback) {
+    // per host level: sorted, disjoint [lo, hi) segments with the sweep that last wrote them
+    struct Seg { int64_t lo, hi; int v; };
+    std::vector<Seg> ver[2] = {{{0, (int64_t)p.host_level_bytes, -1}},
+                               {{0, (int64_t)p.host_level_bytes, -1}}};
+    for (size_t i = 0; i < ops.size(); i++) {
+      const Op &o = ops[i];
+      if ((o.type != OP_H2D && o.type != OP_D2H) || o.host_id < 0 || o.host_id > 1 || o.bytes <= 0)
+        continue;
+      std::vector<Seg> &vs = ver[o.host_id];
+      const int64_t lo = o.host_off, hi = o.host_off + o.bytes;
+      if (o.type == OP_H2D) {
+        for (const Seg &g : vs)
+          if (g.lo < hi && lo < g.hi && g.v != o.sweep - 1) {
+            bad++;
+            if (why && why->empty())
+              *why = "op " + std::to_string(i) + " (sweep " + std::to_string(o.sweep) +
+                     ") reads host bytes last written by sweep " + std::to_string(g.v);
+            break;
+          }
+        continue;
+      }
+      std::vector<Seg> nv;
+      for (const Seg &g : vs) {
+        if (g.hi <= lo || hi <= g.lo) {
+          nv.push_back(g);
+          continue;
+        }
+        if (g.lo < lo) nv.push_back({g.lo, lo, g.v});
+        if (hi < g.hi) nv.push_back({hi, g.hi, g.v});
+      }
+      nv.push_back({lo, hi, (int)o.sweep});
+      std::sort(nv.begin(), nv.end(), [](const Seg &a, const Seg &b) { return a.lo < b.lo; });
+      vs.swap(nv);
+    }
   }
   // every sweep must write back each host store it writes, whole and once
   if (check_writeback) {

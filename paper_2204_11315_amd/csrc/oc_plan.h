@@ -69,6 +69,7 @@ struct PlanInput {
   int prefetch = -1;      // copy-ins issued ahead of the kernels (-1 = slots - 1)
   int fuse = 4;           // STAR7: time steps per stencil launch (1..kMaxFused)
   bool share = false;     // keep the overlap of consecutive slabs on the device
+  bool in_place = false;  // one host level, updated in place (needs sharing or one slab)
 };
 
 constexpr int kMaxSlots = 8;
@@ -87,6 +88,7 @@ struct Plan {
   size_t plane_bytes = 0;  // nx*ny*4
   size_t layer_bytes = 0;  // coded bytes of 4 planes
   bool share = false;      // region sharing in effect (STAR7; raw only with one stencil group)
+  bool in_place = false;   // every sweep reads and writes host level 0
   int slots = 3;           // staging ring slots
   int prefetch = 2;        // copy-ins issued ahead
   int n_work_sets = 1;     // working-buffer sets (1 shared, or one per ring slot)

@@ -47,7 +47,7 @@ class Config(ctypes.Structure):
                 ("single_buffer", ctypes.c_int32), ("timing", ctypes.c_int32),
                 ("ring_slots", ctypes.c_int32), ("prefetch", ctypes.c_int32),
                 ("fuse_steps", ctypes.c_int32), ("copy_back", ctypes.c_int32),
-                ("share_overlap", ctypes.c_int32)]
+                ("share_overlap", ctypes.c_int32), ("in_place", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -178,7 +178,7 @@ def host_aux_bytes(shape, stencil: Stencil, rate: int) -> int:
 
 def plan_config(k: int, slab_planes: int, rate: int, single_buffer: bool = True,
                 budget: int = 0, ring_slots: int = 0, prefetch: int = 0, fuse: int = 0,
-                share: bool = False) -> Config:
+                share: bool = False, in_place: bool = False) -> Config:
     """A Config carrying only the plan fields."""
     cfg = Config()
     cfg.k = int(k)
@@ -190,6 +190,7 @@ def plan_config(k: int, slab_planes: int, rate: int, single_buffer: bool = True,
     cfg.prefetch = int(prefetch)
     cfg.fuse_steps = int(fuse)
     cfg.share_overlap = 1 if share else -1
+    cfg.in_place = 1 if in_place else 0
     return cfg
 
 
@@ -203,18 +204,22 @@ def plan_bytes(shape, stencil: Stencil, k: int, slab_planes: int, rate: int,
 
 def check_plan(shape, stencil: Stencil, k: int, slab_planes: int, rate: int, sweeps: int,
                single_buffer: bool = True, budget: int = 0, mutate: int = 0, i: int = 0,
-               ring_slots: int = 0, prefetch: int = 0, fuse: int = 0, share: bool = False) -> int:
+               ring_slots: int = 0, prefetch: int = 0, fuse: int = 0, share: bool = False,
+               in_place: bool = False) -> int:
     g = make_grid(shape)
-    cfg = plan_config(k, slab_planes, rate, single_buffer, budget, ring_slots, prefetch, fuse, share)
+    cfg = plan_config(k, slab_planes, rate, single_buffer, budget, ring_slots, prefetch, fuse, share,
+                      in_place)
     return int(lib().oc_debug_check_plan(_ref(g), _ref(stencil), _ref(cfg), int(sweeps),
                                          int(mutate), int(i)))
 
 
 def plan_ops(shape, stencil: Stencil, k: int, slab_planes: int, rate: int, sweeps: int,
              single_buffer: bool = True, budget: int = 0, ring_slots: int = 0, prefetch: int = 0,
-             fuse: int = 0, share: bool = False):
+             fuse: int = 0, share: bool = False,
+             in_place: bool = False):
     g = make_grid(shape)
-    cfg = plan_config(k, slab_planes, rate, single_buffer, budget, ring_slots, prefetch, fuse, share)
+    cfg = plan_config(k, slab_planes, rate, single_buffer, budget, ring_slots, prefetch, fuse, share,
+                      in_place)
     nw = ctypes.c_int64(0)
     n = int(lib().oc_debug_plan_ops(_ref(g), _ref(stencil), _ref(cfg), int(sweeps), _ref(nw)))
     return n, int(nw.value)
@@ -222,10 +227,12 @@ def plan_ops(shape, stencil: Stencil, k: int, slab_planes: int, rate: int, sweep
 
 def plan_dump(shape, stencil: Stencil, k: int, slab_planes: int, rate: int, sweeps: int,
               single_buffer: bool = True, budget: int = 0, ring_slots: int = 0,
-              prefetch: int = 0, fuse: int = 0, share: bool = False) -> str:
+              prefetch: int = 0, fuse: int = 0, share: bool = False,
+              in_place: bool = False) -> str:
     """Text listing of the operation list the executor would issue."""
     g = make_grid(shape)
-    cfg = plan_config(k, slab_planes, rate, single_buffer, budget, ring_slots, prefetch, fuse, share)
+    cfg = plan_config(k, slab_planes, rate, single_buffer, budget, ring_slots, prefetch, fuse, share,
+                      in_place)
     n = int(lib().oc_debug_plan_dump(_ref(g), _ref(stencil), _ref(cfg), int(sweeps), None, 0))
     if n < 0:
         raise OCError(n, "oc_debug_plan_dump", status_str(n))
@@ -359,13 +366,15 @@ class OutOfCore:
     steps per residency; slab_planes = S (0 = largest that fits the budget).
     fuse = 7-point steps per stencil launch (0 = 4); copy_back = workgroups of
     the copy-back kernel (0 = 4, -1 = runtime copies); share = region sharing
-    (the overlap of consecutive slabs stays on the device).
+    (the overlap of consecutive slabs stays on the device); in_place = one host
+    level updated in place (needs sharing, or one slab).
     """
 
     def __init__(self, shape, c=C_CONFIG1, k: int = 4, rate: int = 0, budget: int = 512 << 20,
                  slab_planes: int = 0, single_buffer: bool = True, c0_field: bool = False,
                  timing: bool = False, ring_slots: int = 0, prefetch: int = 0, device=None,
-                 stencil: Stencil = None, fuse: int = 0, copy_back: int = 0, share: bool = True):
+                 stencil: Stencil = None, fuse: int = 0, copy_back: int = 0, share: bool = True,
+                 in_place: bool = False):
         torch = _torch()
         self.shape = tuple(int(v) for v in shape)
         self.rate = int(rate)
@@ -381,7 +390,8 @@ class OutOfCore:
         self.arena = torch.empty(int(budget), dtype=torch.uint8, device=self.device)
         self.streams = pipeline_streams(self.device)
         lb = host_level_bytes(self.shape, self.stencil, rate)
-        self.levels = [torch.empty(lb, dtype=torch.uint8, pin_memory=True) for _ in range(2)]
+        self.levels = [torch.empty(lb, dtype=torch.uint8, pin_memory=True)
+                       for _ in range(1 if in_place else 2)]
         ab = host_aux_bytes(self.shape, self.stencil, rate)
         self.aux = torch.empty(ab, dtype=torch.uint8, pin_memory=True) if ab else None
         cfg = Config()
@@ -390,7 +400,7 @@ class OutOfCore:
         for i, s in enumerate(self.streams):
             cfg.streams[i] = s.cuda_stream
         cfg.host_level[0] = self.levels[0].data_ptr()
-        cfg.host_level[1] = self.levels[1].data_ptr()
+        cfg.host_level[1] = None if in_place else self.levels[1].data_ptr()
         cfg.host_level_bytes = lb
         cfg.host_aux = self.aux.data_ptr() if self.aux is not None else None
         cfg.host_aux_bytes = ab
@@ -404,6 +414,7 @@ class OutOfCore:
         cfg.fuse_steps = int(fuse)
         cfg.copy_back = int(copy_back)
         cfg.share_overlap = 1 if share else -1
+        cfg.in_place = 1 if in_place else 0
         self.cfg = cfg
         h = ctypes.c_void_p()
         torch.cuda.synchronize(self.device)

@@ -173,6 +173,36 @@ def test_region_sharing_with_c0_field_and_split_runs():
         assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
 
 
+@pytest.mark.parametrize("R,k,S,runs", [(0, 4, 8, [10]), (0, 3, 12, [4, 7]), (8, 4, 8, [12]),
+                                         (16, 3, 12, [5, 2]), (8, 4, 4, [8]), (8, 4, 44, [9])])
+def test_in_place_host_level_equals_two_levels_bitwise(R, k, S, runs):
+    # one host level updated in place (Algorithm 1, Ensure) computes exactly
+    # what the two alternating levels compute
+    u0 = inputs.grf_field(SHAPE, seed=18)
+    kw = dict(k=k, rate=R, slab_planes=S, budget=64 << 20, runs=runs)
+    a, st = run_ooc(u0, 0, in_place=True, **kw)
+    b, st2 = run_ooc(u0, 0, in_place=False, **kw)
+    assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+    assert st["bytes_h2d"] == st2["bytes_h2d"] and st["bytes_d2h"] == st2["bytes_d2h"]
+
+
+def test_in_place_with_c0_field_and_single_buffer_off():
+    u0 = inputs.grf_field(SHAPE, seed=19)
+    c0 = inputs.c0_field(SHAPE, seed=20)
+    for R, swb in ((0, True), (8, True), (8, False)):
+        kw = dict(k=4, rate=R, slab_planes=8, c0_field=True, single_buffer=swb, runs=[6, 5],
+                  budget=64 << 20)
+        a, _ = run_ooc(u0, 0, c0, in_place=True, **kw)
+        b, _ = run_ooc(u0, 0, c0, in_place=False, **kw)
+        assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+
+
+def test_in_place_without_sharing_is_rejected():
+    with pytest.raises(oc.OCError) as e:
+        oc.OutOfCore(SHAPE, k=4, rate=8, slab_planes=8, share=False, in_place=True)
+    assert e.value.status == oc.OC_ERR_ARG
+
+
 def test_stats_bytes_and_visits():
     u0 = inputs.modes_field(SHAPE, seed=10)
     _, st = run_ooc(u0, 8, k=4, rate=8, slab_planes=8, timing=True, share=False)

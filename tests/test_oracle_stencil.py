@@ -33,7 +33,7 @@ def test_sine_mode_decays_by_closed_form(m):
     assert rel < 1e-12
 
 
-def test_closed_form_values_match_survey_table():
+def test_closed_form_values_match_decimal_table():
     # independent arithmetic of the same closed form at N = 64 (decimal values)
     lam = mode_eigenvalue((64, 64, 64), (1, 1, 1))
     assert abs(lam - 0.999299336099) < 1e-11

@@ -318,3 +318,75 @@ def test_region_sharing_cuts_config3_copy_ins_by_eleven_percent():
         # 18 block layers per interior slab become 16 (the first slab of a
         # sweep loads 17, the last 17 of which 2 are shared): 512 / 574
         assert a / b == pytest.approx((17 + 30 * 16 + 15) / (17 + 30 * 18 + 17), rel=1e-12)
+
+
+def _host_ids(dump, kind):
+    return {int(line.split("host=")[1].split()[0]) for line in dump.splitlines() if f" {kind} " in line}
+
+
+@pytest.mark.parametrize("shape,k,S", SHARE_CASES)
+@pytest.mark.parametrize("R", [0, 8])
+def test_in_place_host_level_race_free_and_reads_the_right_state(shape, k, S, R):
+    # Algorithm 1 updates the host chunks in place: with region sharing every
+    # sweep reads and writes level 0, no copy-in reads a plane its own sweep
+    # has already written back, and every wait is still needed
+    for slots, pre in ((0, 0), (4, 3)):
+        kw = dict(ring_slots=slots, prefetch=pre, share=True, in_place=True)
+        n, nw = oc.plan_ops(shape, ST, k, S, R, 3, **kw)
+        assert oc.check_plan(shape, ST, k, S, R, 3, **kw) == 0
+        for i in range(nw):
+            assert oc.check_plan(shape, ST, k, S, R, 3, mutate=1, i=i, **kw) > 0, (slots, pre, i)
+        d = oc.plan_dump(shape, ST, k, S, R, 3, **kw)
+        assert _host_ids(d, "H2D") == {0} and _host_ids(d, "D2H") == {0}
+        assert _h2d_bytes(d) == _expected_h2d(shape, k, S, R, 3, True)
+        # the same sweeps without sharing would copy halos from the level being updated
+        assert oc.check_plan(shape, ST, k, S, R, 3, mutate=4, **kw) > 0
+
+
+def test_in_place_needs_sharing_or_one_slab():
+    shape = (40, 12, 16)
+    assert oc.check_plan(shape, ST, 4, 8, 8, 2, in_place=True) == oc.OC_ERR_ARG      # sharing off
+    assert oc.check_plan(shape, ST, 4, 8, 0, 2, fuse=2, share=True, in_place=True) == oc.OC_ERR_ARG
+    assert oc.check_plan(shape, WAVE, 2, 8, 0, 2, share=True, in_place=True) == oc.OC_ERR_ARG
+    # one slab: nothing to share, in place is safe
+    assert oc.check_plan(shape, ST, 4, 40, 0, 3, in_place=True) == 0
+    assert oc.check_plan(shape, ST, 4, 40, 8, 3, in_place=True) == 0
+
+
+@pytest.mark.parametrize("shape,k,S", [((32, 8, 8), 2, 8), ((40, 8, 8), 1, 8), ((36, 12, 8), 2, 12)])
+def test_in_place_coded_wave_race_free(shape, k, S):
+    wst = oc.make_wave25(10.0, 1e-3, (4, 4, 4), 15.0, 1.0 / 15)
+    kw = dict(share=True, in_place=True)
+    n, nw = oc.plan_ops(shape, wst, k, S, 12, 3, **kw)
+    assert oc.check_plan(shape, wst, k, S, 12, 3, **kw) == 0
+    for i in range(nw):
+        assert oc.check_plan(shape, wst, k, S, 12, 3, mutate=1, i=i, **kw) > 0, i
+    assert oc.check_plan(shape, wst, k, S, 12, 3, mutate=4, **kw) > 0
+    d = oc.plan_dump(shape, wst, k, S, 12, 3, **kw)
+    assert _host_ids(d, "H2D") == {0, 2} and _host_ids(d, "D2H") == {0}   # 2 = velocity
+
+
+def test_checker_catches_a_copy_in_from_the_stale_level():
+    # one slab, two levels: the stale read is ordered (no race), so only the
+    # check that copy-ins read the previous sweep's state can catch it
+    for R in (0, 8):
+        assert oc.check_plan((40, 12, 16), ST, 4, 40, R, 2) == 0
+        assert oc.check_plan((40, 12, 16), ST, 4, 40, R, 2, mutate=5) == 1
+        assert oc.check_plan((40, 12, 16), ST, 4, 8, R, 2, mutate=5) > 0
+
+
+def test_create_in_place_takes_a_single_host_level():
+    # argument checks only: with in_place the second level may be NULL; the
+    # call then stops at the missing streams, before any device work
+    import ctypes
+    g = oc.make_grid((40, 12, 16))
+    h = ctypes.c_void_p()
+    lv = (ctypes.c_uint8 * oc.host_level_bytes((40, 12, 16), ST, 8))()
+    for in_place, want in ((0, oc.OC_ERR_BUDGET), (1, oc.OC_ERR_ARG)):
+        cfg = oc.plan_config(4, 8, 8, budget=64 * MiB, share=True, in_place=bool(in_place))
+        cfg.dev_arena = 1 << 40            # never dereferenced by these checks
+        cfg.host_level[0] = ctypes.addressof(lv)
+        cfg.host_level[1] = None
+        cfg.host_level_bytes = ctypes.sizeof(lv)
+        assert oc.lib().oc_create(oc._ref(g), oc._ref(ST), oc._ref(cfg), oc._ref(h)) == want
+        assert not h.value

@@ -94,11 +94,11 @@ def gpu_compressed_composition(p0, pm1, vel, st, R, k, steps):
 
 @pytest.mark.parametrize("R", [12, 16])
 @pytest.mark.parametrize("swb", [True, False])
-@pytest.mark.parametrize("share", [True, False])
-def test_ooc_compressed_equals_incore_composition_bitwise(R, swb, share):
+@pytest.mark.parametrize("share,in_place", [(True, False), (False, False), (True, True)])
+def test_ooc_compressed_equals_incore_composition_bitwise(R, swb, share, in_place):
     vel, dt, st, p0, pm1 = setup()
     o = oc.OutOfCore(SHAPE, k=2, rate=R, slab_planes=8, budget=64 << 20, stencil=st,
-                     single_buffer=swb, share=share)
+                     single_buffer=swb, share=share, in_place=in_place)
     try:
         o.load(p0, pm1, vel)
         o.run(6)
