@@ -219,6 +219,8 @@ struct BitReader {
     win = (uint64_t)fetch(0) | ((uint64_t)fetch(1) << 32);
   }
   __device__ __forceinline__ int pos() const { return 32 * wi + off; }
+  // the next 32 bits of the stream (lowest = next bit)
+  __device__ __forceinline__ uint32_t peek() const { return (uint32_t)(win >> off); }
   __device__ __forceinline__ void advance(int len) {  // off + len < 64
     off += len;
     const bool f = off >= 32;
@@ -350,7 +352,9 @@ __global__ __launch_bounds__(256) void k_encode(const float *__restrict__ in, in
         while (rest && w.pos() < BITS) {
           int tz = __builtin_ctzll(rest);
           // group test 1, then tz zeros and the set bit
-          if (tz < 62) {
+          if (tz < 31) {
+            w.put(1u | (2u << tz), tz + 2);
+          } else if (tz < 62) {
             w.put64(1ull | (2ull << tz), tz + 2);
           } else {
             w.put(1u, 1);
@@ -416,7 +420,22 @@ __global__ __launch_bounds__(256) void k_decode(const uint32_t *__restrict__ in,
       } else {
         while (n < 64) {
           if (r.pos() >= BITS) { m = n; break; }   // no room for the group bit
-          if (!r.get(1)) break;                    // closing group bit
+          const uint32_t w = r.peek();
+          if (!(w & 1u)) {                         // closing group bit
+            r.advance(1);
+            break;
+          }
+          const uint32_t t = w >> 1;
+          if (t) {
+            // group bit, run and its closing 1 all lie in the window: one step
+            const int run = __builtin_ctz(t);
+            if (run >= 64 - n) { m = n + min(64 - n, BITS - (r.pos() + 1)); break; }
+            r.advance(run + 2);
+            x |= 1ull << (n + run);
+            n += run + 1;
+            continue;
+          }
+          r.advance(1);
           const int rs = r.pos();
           const int run = r.zero_run(64 - n);
           if (run < 0) { m = n + min(64 - n, BITS - rs); break; }   // cut inside a run
