@@ -124,12 +124,16 @@ def run_leg(oc, torch, u0, rate, steps, warmup, ref=None, timing=True):
 HBM_PEAK_GBS = 8000.0
 ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 
-# Per-kernel work figures measured with rocprofv3 on the slab-shaped kernel
-# probe (`bench.py --kernels --rate R`, 512 x 512 planes), one figure per code
-# rate: VALU wave-instructions per wave of 64 blocks (SQ_INSTS_VALU / SQ_WAVES).
-VALU_PER_WAVE = {("decode", 8): 5336.0, ("encode", 8): 5540.0,
-                 ("decode", 9): 5430.0, ("encode", 9): 5624.0,
-                 ("decode", 16): 5985.0, ("encode", 16): 6069.0}
+# Per-kernel work figures measured with rocprofv3 on the kernel probe
+# (`bench.py --kernels --rate R`: the job's slab shapes, and the job's data:
+# decodes of states 0, 4, ..., 60 and encodes of states 4, ..., 64 of the
+# seeded field under the 7-point stencil), one figure per code rate: VALU
+# wave-instructions per wave of 64 blocks (SQ_INSTS_VALU / SQ_WAVES), averaged
+# over those states.  The count grows as the field smooths (more bit planes
+# fit the budget): decode 4,559 at state 0 to 7,232 at state 60 (R = 8).
+VALU_PER_WAVE = {("decode", 8): 6706.0, ("encode", 8): 6265.0,
+                 ("decode", 9): 6810.0, ("encode", 9): 6358.0,
+                 ("decode", 16): 7399.0, ("encode", 16): 6829.0}
 # HBM bytes per launch over the algorithmic bytes, from FETCH_SIZE and
 # WRITE_SIZE of the same probe launches (each scaled by what it reads for a
 # plain 256 MiB device copy: FETCH x 2, WRITE x 1 KiB per unit), read and write
@@ -247,20 +251,35 @@ def cpu_baseline(u0, rate):
 
 
 def kernel_probe(rate, reps=20):
-    """Launches each hot kernel at its slab shape `reps` times through the C ABI
-    (no pipeline), plus a plain 256 MiB device copy as the counter reference.
-    Used under rocprofv3 (kernel trace, FETCH_SIZE / WRITE_SIZE counters)."""
+    """Launches each hot kernel through the C ABI (no pipeline) at the bench
+    job's slab shapes and on the data the job meets, for rocprofv3 (kernel
+    trace; FETCH_SIZE / WRITE_SIZE and SQ counters).  The codec's cost depends
+    on the data (a smoother field codes more bit planes within the budget), so
+    the codec launches follow the job's states: a 72-plane slab (64 interior
+    planes and 4-plane halos) in the middle of a 200-plane 512 x 512 seeded GRF
+    grid, evolved four 7-point steps at a time; for t = 0, 4, ..., 60 the
+    slab's codes of state t are decoded (18 block layers, a slab copy-in) and
+    the interior of state t + 4 is encoded (16 layers, a copy-back).  The
+    18-layer encodes that make the decoder's input are helpers.  The grid is
+    evolved through the c0-field stencil kernel (c0 = 0.4 everywhere), a
+    separate kernel from the constant-c0 launches probed on the slab: `reps`
+    single steps and `reps` four-step launches over 72 planes.  Last, `reps`
+    plain 256 MiB device copies as the counter reference."""
     import torch
     from paper_2204_11315_amd import inputs, oc
     P = S + 2 * 4
-    u = torch.from_numpy(inputs.grf_field((P, 512, 512), seed=3)).cuda()
-    codes = oc.compress(u, rate)
-    out = torch.empty_like(u)
+    m = 64                                                     # z faces 64 steps away
+    v = torch.from_numpy(inputs.grf_field((P + 2 * m, 512, 512), seed=3)).cuda()
+    c0 = torch.full_like(v, C[0])
+    out = torch.empty((P, 512, 512), dtype=torch.float32, device="cuda")
+    codes = oc.compress(v[m:m + P].contiguous(), rate)        # helper: codes of state 0
     torch.cuda.synchronize()
-    for _ in range(reps):
-        oc.decompress(codes, u.shape, rate, out=out)           # 18 layers = one slab copy-in
-    for _ in range(reps):
-        oc.compress(u[4:4 + S].contiguous(), rate)             # 16 layers = one slab interior
+    for t in range(0, STEPS, K):
+        oc.decompress(codes, out.shape, rate, out=out)         # decode, state t
+        v = oc.star7_incore(v, C, K, c0f=c0)
+        oc.compress(v[m + 4:m + 4 + S].contiguous(), rate)    # encode, state t + 4
+        codes = oc.compress(v[m:m + P].contiguous(), rate)    # helper
+    u = v[m:m + P].contiguous()
     for _ in range(reps):
         oc.star7_incore(u, C, 1)                               # one step over 72 planes
     for _ in range(reps):
@@ -270,7 +289,7 @@ def kernel_probe(rate, reps=20):
     for _ in range(reps):
         b.copy_(a)                                             # reference: 256 MiB read + write
     torch.cuda.synchronize()
-    print(json.dumps({"kernel_probe": True, "rate": rate, "reps": reps,
+    print(json.dumps({"kernel_probe": True, "rate": rate, "reps": reps, "states": STEPS // K,
                       "decode_blocks": 128 * 128 * (P // 4), "encode_blocks": 128 * 128 * (S // 4),
                       "stencil_cells": 512 * 512 * P, "ref_copy_bytes": 256 << 20}), flush=True)
 
