@@ -34,7 +34,14 @@ def _fields(shape, seed):
     out["signed_zeros"] = z
     const = np.repeat(rng.standard_normal((nz // 4, ny // 4, nx // 4)).astype(np.float32), 4, 0)
     out["blockwise_const"] = np.repeat(np.repeat(const, 4, 1), 4, 2)
+    if out["grf"] is not None:
+        # smoothed by the stencil, as the out-of-core sweeps meet it: more bit
+        # planes fit the budget, long verbatim prefixes, cuts at low planes
+        out["diffused"] = oracle.star7_run(out["grf"], DIFFUSE, 24).astype(np.float32)
     return {k: v for k, v in out.items() if v is not None}
+
+
+DIFFUSE = (0.4, 0.1, 0.1, 0.1, 0.1, 0.1, 0.1)
 
 
 SHAPES = [(12, 20, 44), (8, 64, 1028)]
@@ -94,6 +101,18 @@ def test_bad_arguments_rejected_before_launch():
     small = torch.zeros(16, dtype=torch.uint8, device="cuda")
     with pytest.raises(oc.OCError):
         oc.compress(d, 8, out=small)
+
+
+@pytest.mark.parametrize("R", [8, 16])
+def test_full_slab_shape_diffused_field(R):
+    # a slab-sized piece of the field after 32 stencil steps (the decoder's
+    # longest loops: many planes and significant coefficients per block)
+    f = oracle.star7_run(inputs.grf_field((16, 512, 512), seed=5), DIFFUSE, 32).astype(np.float32)
+    want = oracle.compress(f, R)
+    got = oc.compress(_dev(f), R).cpu().numpy()
+    assert np.array_equal(got, want)
+    back = oc.decompress(_dev(want), f.shape, R).cpu().numpy()
+    assert np.array_equal(back.view(np.uint32), oracle.decompress(want, f.shape, R).view(np.uint32))
 
 
 def test_full_slab_shape_grf_r16():
