@@ -704,8 +704,7 @@ int adj_plan_for(const oc_handle *h, int64_t steps, int32_t every, int32_t rate,
   if (h->plan.coded) return OC_ERR_UNSUPPORTED;     // the forward of the adjoint runs raw
   if (steps < 1 || every < 1 || rate < 0 || rate > 32) return OC_ERR_ARG;
   oc::PlanInput in = h->plan.in;
-  in.share = false;       // the reverse sweeps keep their own two lambda levels
-  in.in_place = false;
+  in.in_place = false;    // the reverse sweeps keep their own two lambda levels
   in.rate = rate;
   in.slab_planes = 0;
   in.budget = h->cfg.dev_budget;

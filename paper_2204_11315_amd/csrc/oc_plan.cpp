@@ -585,12 +585,16 @@ int make_adj_plan(const PlanInput &in0, int m, int64_t steps, AdjPlan *out) {
     p.stage_bytes = p.coded ? align256((size_t)(p.P / 4) * p.layer_bytes) : 0;
     size_t off = 0;
     for (int q = 0; q < 2; q++) {
-      for (int b = 0; b < 7; b++) {
+      for (int b : {A_U0, A_LA, A_LB, A_LC, A_C, A_G}) {
         a.off_buf[q][b] = off;
         off += p.work_bytes;
       }
       a.off_cstage[q] = off;
       off += p.stage_bytes;
+    }
+    for (int b : {A_WA, A_WB}) {   // only kernels touch them: one pair serves both slots
+      a.off_buf[0][b] = a.off_buf[1][b] = off;
+      off += p.work_bytes;
     }
     return off;
   };
@@ -618,6 +622,7 @@ int make_adj_plan(const PlanInput &in0, int m, int64_t steps, AdjPlan *out) {
     sl.planes = (sl.z1 - sl.z0) + 2 * p.halo;
     p.slabs.push_back(sl);
   }
+  p.share = in.share && p.slabs.size() >= 2;
   a.field_bytes = (size_t)in.nx * (size_t)in.ny * (size_t)in.nz * 4u;
   p.host_field_bytes = a.field_bytes;
   p.host_level_bytes = a.field_bytes;   // lambda levels and the gradient store: raw fields
@@ -647,6 +652,9 @@ void build_adjoint_ops(const AdjPlan &a, int lsrc, std::vector<Op> *ops) {
     int t, sg, j, q, lsrc, ldst;
     int64_t n0, len, loc0, nload, nz_int;
     const Slab *sl;
+    int pq;           // previous slab's slot
+    int64_t sh;       // planes taken from the previous slab's buffers (region sharing)
+    int64_t sh_src;   // their local position in the previous slab's buffers
   };
   auto geo = [&](int64_t g) {
     Geo x;
@@ -662,11 +670,22 @@ void build_adjoint_ops(const AdjPlan &a, int lsrc, std::vector<Op> *ops) {
     x.loc0 = x.sl->l0 - x.sl->gz0;
     x.nload = x.sl->l1 - x.sl->l0;
     x.nz_int = x.sl->z1 - x.sl->z0;
+    x.pq = (int)((g + NQ - 1) % NQ);
+    x.sh = 0;
+    x.sh_src = 0;
+    if (p.share && x.j > 0) {
+      const Slab &pv = p.slabs[(size_t)x.j - 1];
+      x.sh = std::max<int64_t>(0, std::min(pv.l1, x.sl->l1) - x.sl->l0);
+      x.sh_src = x.sl->l0 - pv.gz0;
+    }
     return x;
   };
+  // slab g copies planes out of slab g-1's slot at the start of its kernels
+  auto has_share_copy = [&](int64_t g) { return p.share && g >= 0 && g < total && g % ns != 0; };
   const size_t pb = p.plane_bytes;
   auto buf = [&](int q, int b) { return (int64_t)a.off_buf[q][b]; };
   auto h2d = [&](const Geo &x, int host, size_t host_off, int64_t dev, int64_t bytes) {
+    if (bytes <= 0) return;
     Op o = B.blank(OP_H2D, S_IN);
     o.host_id = (int8_t)host;
     o.host_off = (int64_t)host_off;
@@ -680,20 +699,33 @@ void build_adjoint_ops(const AdjPlan &a, int lsrc, std::vector<Op> *ops) {
     const Geo x = geo(g);
     std::vector<int> w;
     if (g >= NQ) w.push_back(B.ev.free(x.q));
+    if (g >= NQ && has_share_copy(g - NQ + 1)) {
+      // the next slab of this slot's previous slab copies planes out of the
+      // slot; wait for that copy if this copy-in overwrites any of them
+      const Geo n1 = geo(g - NQ + 1);
+      const int64_t wlo = x.loc0 + x.sh, whi = x.loc0 + x.nload;
+      if (wlo < whi && wlo < n1.sh_src + n1.sh && n1.sh_src < whi) w.push_back(B.ev.shr(x.q));
+    }
     if (x.t > 0) {
       B.writers_of(x.sl->l0, x.sl->l1, &nb);
       for (int jj : nb) w.push_back(B.ev.d2h((x.t - 1) & 1, jj));
     }
     B.wait_all(S_IN, w);
+    // the state, lambda and c0 planes past the shared ones (the gradient
+    // store: the interior only)
+    const int64_t skip = x.sh;
     if (a.ckpt_coded[(size_t)x.sg])
-      h2d(x, HOST_CKPT, a.ckpt_off[(size_t)x.sg] + (size_t)(x.sl->l0 / 4) * p.layer_bytes,
-          (int64_t)a.off_cstage[x.q], (int64_t)((size_t)(x.nload / 4) * p.layer_bytes));
+      h2d(x, HOST_CKPT, a.ckpt_off[(size_t)x.sg] + (size_t)((x.sl->l0 + skip) / 4) * p.layer_bytes,
+          (int64_t)(a.off_cstage[x.q] + (size_t)(skip / 4) * p.layer_bytes),
+          (int64_t)((size_t)((x.nload - skip) / 4) * p.layer_bytes));
     else
-      h2d(x, HOST_CKPT, a.ckpt_off[(size_t)x.sg] + (size_t)x.sl->l0 * pb,
-          buf(x.q, A_U0) + x.loc0 * (int64_t)pb, x.nload * (int64_t)pb);
-    h2d(x, x.lsrc, (size_t)x.sl->l0 * pb, buf(x.q, A_LA) + x.loc0 * (int64_t)pb, x.nload * (int64_t)pb);
+      h2d(x, HOST_CKPT, a.ckpt_off[(size_t)x.sg] + (size_t)(x.sl->l0 + skip) * pb,
+          buf(x.q, A_U0) + (x.loc0 + skip) * (int64_t)pb, (x.nload - skip) * (int64_t)pb);
+    h2d(x, x.lsrc, (size_t)(x.sl->l0 + skip) * pb, buf(x.q, A_LA) + (x.loc0 + skip) * (int64_t)pb,
+        (x.nload - skip) * (int64_t)pb);
     if (c0f)
-      h2d(x, HOST_AUX, (size_t)x.sl->l0 * pb, buf(x.q, A_C) + x.loc0 * (int64_t)pb, x.nload * (int64_t)pb);
+      h2d(x, HOST_AUX, (size_t)(x.sl->l0 + skip) * pb, buf(x.q, A_C) + (x.loc0 + skip) * (int64_t)pb,
+          (x.nload - skip) * (int64_t)pb);
     h2d(x, HOST_GRAD, (size_t)x.sl->z0 * pb, buf(x.q, A_G) + p.halo * (int64_t)pb, x.nz_int * (int64_t)pb);
     B.rec(S_IN, B.ev.in(x.q));
     B.rec(S_IN, B.ev.h2d(x.t & 1, x.j));
@@ -701,24 +733,44 @@ void build_adjoint_ops(const AdjPlan &a, int lsrc, std::vector<Op> *ops) {
   auto issue_compute = [&](int64_t g) {
     const Geo x = geo(g);
     B.wait(S_COMPUTE, B.ev.in(x.q));
-    if (a.ckpt_coded[(size_t)x.sg]) {
+    if (x.sh > 0) {
+      // region sharing: the decoded state, lambda_{n1} and c0 around the
+      // common face come from the previous slab's buffers (device moves)
+      for (int b : {A_U0, A_LA, A_C}) {
+        if (b == A_C && !c0f) continue;
+        Op o = B.blank(OP_DEC, S_COMPUTE);
+        o.dev_src = buf(x.pq, b) + x.sh_src * (int64_t)pb;
+        o.dev_dst = buf(x.q, b) + x.loc0 * (int64_t)pb;
+        o.bytes = x.sh * (int64_t)pb;
+        o.z_lo = 0;
+        o.z_hi = -1;   // raw move
+        o.slab = x.j;
+        o.sweep = x.t;
+        B.push(o);
+      }
+      B.rec(S_COMPUTE, B.ev.shr(x.pq));
+    }
+    if (a.ckpt_coded[(size_t)x.sg] && x.nload > x.sh) {
       Op o = B.blank(OP_DEC, S_COMPUTE);
-      o.dev_src = (int64_t)a.off_cstage[x.q];
-      o.dev_dst = buf(x.q, A_U0) + x.loc0 * (int64_t)pb;
-      o.z_hi = x.nload / 4;
-      o.planes = x.nload;
+      o.dev_src = (int64_t)(a.off_cstage[x.q] + (size_t)(x.sh / 4) * p.layer_bytes);
+      o.dev_dst = buf(x.q, A_U0) + (x.loc0 + x.sh) * (int64_t)pb;
+      o.z_hi = (x.nload - x.sh) / 4;
+      o.planes = x.nload - x.sh;
       o.slab = x.j;
       o.sweep = x.t;
       B.push(o);
     }
     const int64_t dom_lo = std::max<int64_t>(0, -x.sl->gz0);
     const int64_t dom_hi = std::min<int64_t>(x.sl->planes, p.in.nz - x.sl->gz0);
-    auto step = [&](int64_t src, int64_t dst, int64_t grow, bool tr) {
+    // `lv` steps (fused in one launch when lv > 1); the output range is the
+    // interior grown by `grow` planes per side, clipped to the grid
+    auto step = [&](int64_t src, int64_t dst, int64_t grow, bool tr, int lv) {
       Op o = B.blank(OP_STAR7, S_COMPUTE);
       o.dev_src = src;
       o.dev_dst = dst;
       o.dev_src2 = c0f ? buf(x.q, A_C) : -1;
       o.transpose = tr;
+      o.levels = lv;
       o.z_lo = std::max<int64_t>(p.halo - grow, dom_lo);
       o.z_hi = std::min<int64_t>(p.halo + x.nz_int + grow, dom_hi);
       o.gz0 = x.sl->gz0;
@@ -727,14 +779,20 @@ void build_adjoint_ops(const AdjPlan &a, int lsrc, std::vector<Op> *ops) {
       o.sweep = x.t;
       B.push(o);
     };
+    const int fuse = std::max(1, std::min(p.in.fuse, kMaxFused));
+    // lambda_{n1} stays in La (the next slab may share it); the steps back
+    // alternate between Lb and Lc
     int lcur = A_LA, loth = A_LB;
     for (int64_t i = x.len - 1; i >= 0; i--) {
-      // u_{n0+i}: i forward steps from the checkpoint, the range shrinking to
-      // the interior at the last one
+      // u_{n0+i}: i forward steps from the checkpoint (up to `fuse` per
+      // launch), the range shrinking to the interior at the last one
       int64_t u = buf(x.q, A_U0);
-      for (int64_t tt = 1; tt <= i; tt++) {
-        const int64_t dst = buf(x.q, (tt & 1) ? A_WA : A_WB);
-        step(u, dst, i - tt, false);
+      int nw = 0;
+      for (int64_t tt = 0; tt < i;) {
+        const int lv = (int)std::min<int64_t>(fuse, i - tt);
+        const int64_t dst = buf(x.q, (nw++ & 1) ? A_WB : A_WA);
+        tt += lv;
+        step(u, dst, i - tt, false, lv);
         u = dst;
       }
       Op o = B.blank(OP_AXPY, S_COMPUTE);   // g_c0 += lambda_{n0+i+1} * u_{n0+i}
@@ -745,8 +803,9 @@ void build_adjoint_ops(const AdjPlan &a, int lsrc, std::vector<Op> *ops) {
       o.slab = x.j;
       o.sweep = x.t;
       B.push(o);
-      step(buf(x.q, lcur), buf(x.q, loth), i, true);   // lambda_{n0+i} = A^T lambda_{n0+i+1}
-      std::swap(lcur, loth);
+      step(buf(x.q, lcur), buf(x.q, loth), i, true, 1);   // lambda_{n0+i} = A^T lambda_{n0+i+1}
+      lcur = loth;
+      loth = lcur == A_LB ? A_LC : A_LB;
     }
     B.rec(S_COMPUTE, B.ev.out(x.q));
     return lcur;
@@ -772,8 +831,11 @@ void build_adjoint_ops(const AdjPlan &a, int lsrc, std::vector<Op> *ops) {
     B.rec(S_OUT, B.ev.free(x.q));
     B.rec(S_OUT, B.ev.d2h(x.t & 1, x.j));
   };
-  int64_t next_in = 0, outs_issued = 0;
+  int64_t next_in = 0, outs_issued = 0, computes_issued = 0;
   auto in_ready = [&](int64_t gi) {
+    // a wait can only name an event already recorded: the shared-planes copy
+    // of slab gi - NQ + 1 must have been issued
+    if (gi >= NQ && has_share_copy(gi - NQ + 1) && computes_issued < gi - NQ + 2) return false;
     const int t = (int)(gi / ns);
     if (t == 0) return true;
     const Slab &sl = p.slabs[(size_t)(gi % ns)];
@@ -785,6 +847,8 @@ void build_adjoint_ops(const AdjPlan &a, int lsrc, std::vector<Op> *ops) {
   for (int64_t g = 0; g < total; g++) {
     while (next_in < total && next_in <= g + 1 && in_ready(next_in)) issue_in(next_in++);
     const int lres = issue_compute(g);
+    computes_issued = g + 1;
+    while (next_in < total && next_in <= g + 1 && in_ready(next_in)) issue_in(next_in++);
     issue_out(g, lres);
     outs_issued = g + 1;
   }

@@ -152,8 +152,9 @@ struct AdjPlan {
   int64_t steps = 0;       // T
   int nseg = 0;
   int ckpt_rate = 0;       // 0 = raw checkpoints
-  // arena: per slot: U0, Wa, Wb, La, Lb, C, G (P planes each) + coded stage
-  size_t off_buf[kMaxSlots][7] = {};
+  // arena: per slot U0, La, Lb, Lc, C, G (P planes each) + coded stage; Wa and
+  // Wb (kernel-only scratch of the recomputation) shared by the slots
+  size_t off_buf[kMaxSlots][8] = {};
   size_t off_cstage[kMaxSlots] = {};
   // host checkpoint store: byte offset and coding of each checkpoint
   std::vector<size_t> ckpt_off;
@@ -161,9 +162,13 @@ struct AdjPlan {
   size_t ckpt_bytes = 0;   // whole checkpoint store
   size_t field_bytes = 0;  // one raw field
 };
-enum AdjBuf { A_U0 = 0, A_WA, A_WB, A_LA, A_LB, A_C, A_G };
+enum AdjBuf { A_U0 = 0, A_WA, A_WB, A_LA, A_LB, A_C, A_G, A_LC };
 // in: geometry input (kind STAR7, rate = ckpt rate for alignment, budget,
-// slots, slab_planes); m, T.  Returns a status.
+// slab_planes, share); m, T.  Returns a status.  With sharing, a slab after
+// the first of its sweep takes the 2h planes around its lower face of the
+// checkpoint state, lambda_{n1} and c0 from the previous slab's buffers (they
+// stay intact: the recomputation writes Wa / Wb, lambda steps alternate
+// between Lb and Lc) instead of the host.
 int make_adj_plan(const PlanInput &in, int m, int64_t steps, AdjPlan *out);
 // Reverse op list; lambda_T is read from host level `lsrc` (0/1); the final
 // lambda_0 lands in level (lsrc + nseg) & 1.

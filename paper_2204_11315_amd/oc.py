@@ -242,11 +242,12 @@ def plan_dump(shape, stencil: Stencil, k: int, slab_planes: int, rate: int, swee
 
 
 def check_adjoint_plan(shape, stencil: Stencil, steps: int, ckpt_every: int, ckpt_rate: int,
-                       budget: int = 0, slab_planes: int = 0, mutate: int = 0, i: int = 0) -> int:
+                       budget: int = 0, slab_planes: int = 0, mutate: int = 0, i: int = 0,
+                       share: bool = False) -> int:
     """Race check of the adjoint's reverse-sweep operation list (see oc.h);
     mutate=0, i=-1 returns the number of waits."""
     g = make_grid(shape)
-    cfg = plan_config(1, slab_planes, 0, True, budget)
+    cfg = plan_config(1, slab_planes, 0, True, budget, share=share)
     return int(lib().oc_debug_check_adjoint(_ref(g), _ref(stencil), _ref(cfg), int(steps),
                                             int(ckpt_every), int(ckpt_rate), int(mutate), int(i)))
 
@@ -497,15 +498,17 @@ class Adjoint:
 
     Wraps an uncompressed OutOfCore handle (the forward is exact); checkpoints
     every `ckpt_every` steps are kept on the host as codes at `ckpt_rate`
-    bits/value (0 = raw), u_0 exactly."""
+    bits/value (0 = raw), u_0 exactly.  share = region sharing in the forward
+    and the reverse sweeps; fuse = stencil steps per launch in the forward and
+    in the reverse sweeps' recomputation (0 = 4)."""
 
     def __init__(self, shape, c=C_CONFIG1, steps: int = 64, k: int = 4, ckpt_every: int = 8,
                  ckpt_rate: int = 16, budget: int = 512 << 20, slab_planes: int = 0,
-                 c0_field: bool = True, device=None):
+                 c0_field: bool = True, device=None, share: bool = True, fuse: int = 0):
         torch = _torch()
         self.steps, self.ckpt_every, self.ckpt_rate = int(steps), int(ckpt_every), int(ckpt_rate)
         self.ooc = OutOfCore(shape, c, k=k, rate=0, budget=budget, slab_planes=slab_planes,
-                             c0_field=c0_field, device=device)
+                             c0_field=c0_field, device=device, share=share, fuse=fuse)
         n = int(lib().oc_adjoint_host_bytes(self.ooc.h, self.steps, self.ckpt_every,
                                             self.ckpt_rate))
         if n == 0:

@@ -55,6 +55,38 @@ def test_gradients_vs_oracle(rate, tol):
     assert rel(g_c0, gc_ref) < tol
 
 
+def _run_adjoint(rate, every=EVERY, **kw):
+    u0, c0 = fields()
+    adj = oc.Adjoint(SHAPE, C, steps=STEPS, k=2, ckpt_every=every, ckpt_rate=rate, budget=BUDGET, **kw)
+    try:
+        uT = adj.forward(u0, c0)
+        g_u0, g_c0 = adj.backward(top_grad(uT))
+        return (uT, g_u0, g_c0), adj.ooc.stats()["bytes_h2d"]
+    finally:
+        adj.close()
+
+
+@pytest.mark.parametrize("rate", [0, 16])
+def test_region_sharing_in_reverse_sweeps_is_bitwise_neutral(rate):
+    # the shared planes are the same values the slab would copy in (or
+    # decode), so sharing changes only the traffic
+    a, h2d_a = _run_adjoint(rate, share=True)
+    b, h2d_b = _run_adjoint(rate, share=False)
+    for x, y in zip(a, b):
+        assert np.array_equal(x.view(np.uint32), y.view(np.uint32))
+    assert h2d_a < h2d_b
+
+
+@pytest.mark.parametrize("rate,every", [(0, 5), (16, 4)])
+def test_fused_recomputation_is_bitwise_neutral(rate, every):
+    # the reverse sweeps recompute u from the checkpoint up to four steps per
+    # launch; one step per launch gives the same bits
+    a, _ = _run_adjoint(rate, every=every)
+    b, _ = _run_adjoint(rate, every=every, fuse=1)
+    for x, y in zip(a, b):
+        assert np.array_equal(x.view(np.uint32), y.view(np.uint32))
+
+
 def test_directional_derivatives_vs_central_differences():
     u0, c0 = fields()
     adj = oc.Adjoint(SHAPE, C, steps=STEPS, k=2, ckpt_every=EVERY, ckpt_rate=16, budget=BUDGET)

@@ -224,13 +224,15 @@ def test_wave_memory_model():
 @pytest.mark.parametrize("shape,S,R", [((40, 12, 16), 8, 16), ((40, 12, 16), 8, 0), ((24, 8, 8), 24, 8),
                                        ((36, 8, 8), 12, 0), ((44, 8, 8), 12, 16)])
 @pytest.mark.parametrize("steps,every", [(12, 4), (10, 4), (8, 8)])
-def test_adjoint_operation_list_race_free_and_minimal(shape, S, R, steps, every):
+@pytest.mark.parametrize("share", [False, True])
+def test_adjoint_operation_list_race_free_and_minimal(shape, S, R, steps, every, share):
     st = oc.make_star7(c0_field=True)
-    nw = oc.check_adjoint_plan(shape, st, steps, every, R, slab_planes=S, i=-1)
+    kw = dict(slab_planes=S, share=share)
+    nw = oc.check_adjoint_plan(shape, st, steps, every, R, i=-1, **kw)
     assert nw > 0
-    assert oc.check_adjoint_plan(shape, st, steps, every, R, slab_planes=S) == 0
+    assert oc.check_adjoint_plan(shape, st, steps, every, R, **kw) == 0
     for i in range(nw):
-        assert oc.check_adjoint_plan(shape, st, steps, every, R, slab_planes=S, mutate=1, i=i) > 0
+        assert oc.check_adjoint_plan(shape, st, steps, every, R, mutate=1, i=i, **kw) > 0, i
 
 
 SHARE_CASES = [((40, 12, 16), 4, 8), ((44, 8, 8), 4, 12), ((16, 8, 8), 4, 4), ((36, 8, 12), 3, 8),
