@@ -323,6 +323,13 @@ void build_ops(const Plan &p, int64_t sweeps, int steps_last, int src, int64_t s
     return nin;
   };
   const bool c0_staged = swb && !wave && p.in.c0_field;  // raw c0 rides in a per-slot stage
+  // inputs region sharing covers: the coded fields, the raw 7-point field and
+  // the 7-point c0 field (read-only, so it survives the slab's kernels)
+  auto shared_in = [&](const In &fi, int f) {
+    return fi.coded || (!p.coded && f == 0) || (!wave && fi.buf == 2);
+  };
+  // where a slot keeps its raw c0 slab as loaded
+  auto c0_buf = [&](int q) { return c0_staged ? p.off_ro_stage[q] : B.work(q, 2); };
 
   // ---- copy-in stream: slab g into slot g mod NQ -----------------------------
   auto issue_in = [&](int64_t g) {
@@ -347,9 +354,8 @@ void build_ops(const Plan &p, int64_t sweeps, int steps_last, int src, int64_t s
     for (int f = 0; f < nin; f++) {
       Op o = B.blank(OP_H2D, S_IN);
       o.host_id = (int8_t)fin[f].host_id;
-      // shared inputs (the coded fields, or the raw 7-point field) skip the
-      // planes the overlap copy brings
-      const int64_t skip = (fin[f].coded || (!p.coded && f == 0)) ? x.sh : 0;
+      // shared inputs skip the planes the overlap copy brings
+      const int64_t skip = shared_in(fin[f], f) ? x.sh : 0;
       if (fin[f].coded) {
         // staging slot: layer of local plane z at position z / 4, so the
         // planes shared with the next slab lie past the encoder's output
@@ -359,9 +365,9 @@ void build_ops(const Plan &p, int64_t sweeps, int steps_last, int src, int64_t s
         o.bytes = (int64_t)((size_t)((x.nload - skip) / 4) * p.layer_bytes);
         ncoded++;
       } else if (c0_staged && fin[f].buf == 2) {
-        o.dev_dst = (int64_t)(p.off_ro_stage[x.q] + (size_t)x.loc0 * p.plane_bytes);
-        o.host_off = (int64_t)((size_t)x.sl->l0 * p.plane_bytes);
-        o.bytes = (int64_t)((size_t)x.nload * p.plane_bytes);
+        o.dev_dst = (int64_t)(p.off_ro_stage[x.q] + (size_t)(x.loc0 + skip) * p.plane_bytes);
+        o.host_off = (int64_t)((size_t)(x.sl->l0 + skip) * p.plane_bytes);
+        o.bytes = (int64_t)((size_t)(x.nload - skip) * p.plane_bytes);
       } else {
         o.dev_dst = (int64_t)(B.work(x.q, fin[f].buf) + (size_t)(x.loc0 + skip) * p.plane_bytes);
         o.host_off = (int64_t)(fin[f].host_base + (size_t)(x.sl->l0 + skip) * p.plane_bytes);
@@ -385,20 +391,24 @@ void build_ops(const Plan &p, int64_t sweeps, int steps_last, int src, int64_t s
     if (x.sh > 0) {
       // region sharing: the planes around the common face come from the
       // previous slab's input (device-to-device moves, raw marker z_hi < 0):
-      // each coded field at its stride in the staging slot, or the raw field
+      // each coded field at its stride in the staging slot, the raw field,
+      // the raw c0 slab
       int nsh = 0;
       for (int f = 0; f < nin; f++) {
-        if (!(fin[f].coded || (!p.coded && f == 0))) continue;
+        if (!shared_in(fin[f], f)) continue;
         Op o = B.blank(OP_DEC, S_COMPUTE);
-        if (p.coded) {
+        if (fin[f].coded) {
           o.dev_src = (int64_t)(p.off_stage[x.pq] + (size_t)nsh * (size_t)(x.pv_planes / 4) * p.layer_bytes +
                                 (size_t)(x.sh_src / 4) * p.layer_bytes);
           o.dev_dst = (int64_t)(p.off_stage[x.q] + (size_t)nsh * (size_t)(x.sl->planes / 4) * p.layer_bytes +
                                 (size_t)(x.loc0 / 4) * p.layer_bytes);
           o.bytes = (int64_t)((size_t)(x.sh / 4) * p.layer_bytes);
+          nsh++;
         } else {
-          o.dev_src = (int64_t)(B.work(x.pq, 0) + (size_t)x.sh_src * p.plane_bytes);
-          o.dev_dst = (int64_t)(B.work(x.q, 0) + (size_t)x.loc0 * p.plane_bytes);
+          const size_t src = fin[f].buf == 2 ? c0_buf(x.pq) : B.work(x.pq, 0);
+          const size_t dst = fin[f].buf == 2 ? c0_buf(x.q) : B.work(x.q, 0);
+          o.dev_src = (int64_t)(src + (size_t)x.sh_src * p.plane_bytes);
+          o.dev_dst = (int64_t)(dst + (size_t)x.loc0 * p.plane_bytes);
           o.bytes = (int64_t)((size_t)x.sh * p.plane_bytes);
         }
         o.z_hi = -1;
@@ -406,7 +416,6 @@ void build_ops(const Plan &p, int64_t sweeps, int steps_last, int src, int64_t s
         o.slab = x.j;
         o.sweep = x.t;
         B.push(o);
-        nsh++;
       }
       B.rec(S_COMPUTE, B.ev.shr(x.pq));
     }

@@ -164,13 +164,16 @@ def test_region_sharing_compressed_equals_incore_composition_bitwise(R, swb, k, 
 
 
 def test_region_sharing_with_c0_field_and_split_runs():
+    # the field and the c0 slab both share their planes around slab faces
     u0 = inputs.grf_field(SHAPE, seed=16)
     c0 = inputs.c0_field(SHAPE, seed=17)
-    for R in (0, 8):
-        kw = dict(k=4, rate=R, slab_planes=8, c0_field=True, runs=[5, 8])
-        a, _ = run_ooc(u0, 0, c0, share=True, **kw)
-        b, _ = run_ooc(u0, 0, c0, share=False, **kw)
+    for R, swb in ((0, True), (8, True), (8, False)):
+        kw = dict(k=4, rate=R, slab_planes=8, c0_field=True, runs=[5, 8], single_buffer=swb,
+                  budget=64 << 20)
+        a, sa = run_ooc(u0, 0, c0, share=True, **kw)
+        b, sb = run_ooc(u0, 0, c0, share=False, **kw)
         assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+        assert sa["bytes_h2d"] < sb["bytes_h2d"]
 
 
 @pytest.mark.parametrize("R,k,S,runs", [(0, 4, 8, [10]), (0, 3, 12, [4, 7]), (8, 4, 8, [12]),

@@ -392,3 +392,22 @@ def test_create_in_place_takes_a_single_host_level():
         cfg.host_level_bytes = ctypes.sizeof(lv)
         assert oc.lib().oc_create(oc._ref(g), oc._ref(ST), oc._ref(cfg), oc._ref(h)) == want
         assert not h.value
+
+
+@pytest.mark.parametrize("R,swb", [(0, True), (8, True), (8, False)])
+@pytest.mark.parametrize("shape,S", [((40, 12, 16), 8), ((44, 8, 8), 12), ((16, 8, 8), 4)])
+def test_region_sharing_covers_the_c0_field(R, swb, shape, S):
+    # the raw c0 slab is read-only, so its planes around a common face can be
+    # taken from the previous slab as well
+    st = oc.make_star7(c0_field=True)
+    k = 4
+    kw = dict(single_buffer=swb, share=True)
+    n, nw = oc.plan_ops(shape, st, k, S, R, 2, **kw)
+    assert oc.check_plan(shape, st, k, S, R, 2, **kw) == 0
+    for i in range(nw):
+        assert oc.check_plan(shape, st, k, S, R, 2, mutate=1, i=i, **kw) > 0, i
+    d = oc.plan_dump(shape, st, k, S, R, 2, **kw)
+    c0_bytes = _expected_h2d(shape, k, S, 0, 2, True)      # raw planes, halo k = 4
+    assert _h2d_bytes(d) == _expected_h2d(shape, k, S, R, 2, True) + c0_bytes
+    d0 = oc.plan_dump(shape, st, k, S, R, 2, single_buffer=swb)
+    assert _h2d_bytes(d0) == _expected_h2d(shape, k, S, R, 2, False) + _expected_h2d(shape, k, S, 0, 2, False)
