@@ -359,25 +359,39 @@ bool grid_ok(const oc_grid *g) {
 }
 
 // Encodes a whole host FP32 field into host codes at `rate`, in chunks of
-// `chunk` planes through the device buffers `work` (raw) and `stage` (codes);
-// synchronous on stream 0.
+// `chunk` planes, double-buffered through two device buffer pairs (raw
+// `work[i]`, codes `stage[i]`): the copy-in of a chunk (stream 0) overlaps the
+// encode (stream 1) and copy-back (stream 2) of the one before.  Returns when
+// the codes are on the host.
 int encode_field(oc_handle *h, const float *src, uint8_t *dst, int rate, int64_t chunk,
-                 uint8_t *work, uint8_t *stage) {
+                 uint8_t *const work[2], uint8_t *const stage[2]) {
   const oc::Plan &p = h->plan;
   Exec x{h};
-  hipStream_t s = h->s[0];
   const size_t pb = p.plane_bytes;
   const size_t layer = oc::coded_layer_bytes(p.in.nx, p.in.ny, rate);
-  for (int64_t z = 0; z < p.in.nz; z += chunk) {
-    int64_t n = std::min<int64_t>(chunk, p.in.nz - z);
-    x.ok(hipMemcpyAsync(work, (const uint8_t *)src + (size_t)z * pb, (size_t)n * pb,
-                        hipMemcpyHostToDevice, s));
-    x.ok(oc::launch_encode((const float *)work, p.in.nx, p.in.ny, n / 4, rate, stage, s));
-    x.ok(hipMemcpyAsync(dst + (size_t)(z / 4) * layer, stage, (size_t)(n / 4) * layer,
-                        hipMemcpyDeviceToHost, s));
-    x.ok(hipStreamSynchronize(s));
-    if (x.st) break;
+  hipEvent_t ev[6] = {};   // per buffer pair: copied in, encoded, copied back
+  for (auto &e : ev)
+    if (!x.ok(hipEventCreateWithFlags(&e, hipEventDisableTiming))) break;
+  int64_t c = 0;
+  for (int64_t z = 0; z < p.in.nz && x.st == OC_OK; z += chunk, c++) {
+    const int b = (int)(c & 1);
+    const int64_t n = std::min<int64_t>(chunk, p.in.nz - z);
+    if (c >= 2) x.ok(hipStreamWaitEvent(h->s[0], ev[3 * b + 2], 0));   // pair b copied back
+    x.ok(hipMemcpyAsync(work[b], (const uint8_t *)src + (size_t)z * pb, (size_t)n * pb,
+                        hipMemcpyHostToDevice, h->s[0]));
+    x.ok(hipEventRecord(ev[3 * b], h->s[0]));
+    x.ok(hipStreamWaitEvent(h->s[1], ev[3 * b], 0));
+    x.ok(oc::launch_encode((const float *)work[b], p.in.nx, p.in.ny, n / 4, rate, stage[b], h->s[1]));
+    x.ok(hipEventRecord(ev[3 * b + 1], h->s[1]));
+    x.ok(hipStreamWaitEvent(h->s[2], ev[3 * b + 1], 0));
+    x.ok(hipMemcpyAsync(dst + (size_t)(z / 4) * layer, stage[b], (size_t)(n / 4) * layer,
+                        hipMemcpyDeviceToHost, h->s[2]));
+    x.ok(hipEventRecord(ev[3 * b + 2], h->s[2]));
   }
+  // drain every stream (also after an error: the buffers must be idle)
+  for (int i = 0; i < 3; i++) (void)hipStreamSynchronize(h->s[i]);
+  for (auto &e : ev)
+    if (e) (void)hipEventDestroy(e);
   if (x.st) return x.st;
   return codec_check_and_clear();
 }
@@ -391,8 +405,12 @@ int load_field(oc_handle *h, const float *src, uint8_t *dst, bool coded) {
     std::memcpy(dst, src, p.plane_bytes * (size_t)p.in.nz);
     return OC_OK;
   }
-  return encode_field(h, src, dst, p.in.rate, std::max<int64_t>(4, p.P / 4 * 4),
-                      h->arena + p.off_work[0][0], h->arena + p.off_stage[0]);
+  // two buffer pairs: working buffers a and b of the shared set (or of the
+  // first two slots), staging slots 0 and 1
+  uint8_t *const work[2] = {h->arena + p.off_work[0][0],
+                            h->arena + (p.n_work_sets == 1 ? p.off_work[0][1] : p.off_work[1][0])};
+  uint8_t *const stage[2] = {h->arena + p.off_stage[0], h->arena + p.off_stage[1]};
+  return encode_field(h, src, dst, p.in.rate, std::max<int64_t>(4, p.P / 4 * 4), work, stage);
 }
 
 int store_field(oc_handle *h, const uint8_t *src, float *dst, bool coded) {
@@ -749,9 +767,10 @@ int oc_forward_ckpt(oc_handle *h, int64_t steps, int32_t ckpt_every, int32_t ckp
     uint8_t *dst = work + off[0] + a.ckpt_off[(size_t)sg];
     const float *cur = (const float *)h->host[h->cur];
     if (a.ckpt_coded[(size_t)sg]) {
-      // codes made on the GPU through the adjoint plan's first slot buffers
-      r = encode_field(h, cur, dst, a.ckpt_rate, std::max<int64_t>(4, a.g.P / 4 * 4),
-                       h->arena + a.off_buf[0][oc::A_U0], h->arena + a.off_cstage[0]);
+      // codes made on the GPU through the adjoint plan's two slots' buffers
+      uint8_t *const wbuf[2] = {h->arena + a.off_buf[0][oc::A_U0], h->arena + a.off_buf[1][oc::A_U0]};
+      uint8_t *const sbuf[2] = {h->arena + a.off_cstage[0], h->arena + a.off_cstage[1]};
+      r = encode_field(h, cur, dst, a.ckpt_rate, std::max<int64_t>(4, a.g.P / 4 * 4), wbuf, sbuf);
     } else {
       std::memcpy(dst, cur, a.field_bytes);
     }
