@@ -236,9 +236,17 @@ int oc_debug_fail_after(oc_handle *h, int64_t n);
  * write-back); 3 swap op i with the next op of the same stream; 4 (in_place
  * plans) turn region sharing off, so slabs copy their halos from the level
  * being updated; 5 (two levels, sweeps >= 2) the second sweep copies in from
- * the level the first sweep read. */
+ * the level the first sweep read.  mutate = 0 with i = -1 returns the number
+ * of waits instead. */
 int64_t oc_debug_check_plan(const oc_grid *g, const oc_stencil *st, const oc_config *cfg,
                             int64_t sweeps, int32_t mutate, int64_t i);
+/* As oc_debug_check_plan, for the op list whose last sweep also writes the
+ * new state to the checkpoint store (oc_forward_ckpt's segments): codes at
+ * ckpt_rate_bits (1..32) or raw planes (0).  OC_ERR_UNSUPPORTED unless the
+ * plan is an uncompressed 7-point plan (and, with codes, its slab interiors
+ * are whole 4-plane block layers). */
+int64_t oc_debug_check_plan_ckpt(const oc_grid *g, const oc_stencil *st, const oc_config *cfg,
+                                 int64_t sweeps, int32_t ckpt_rate_bits, int32_t mutate, int64_t i);
 /* Writes a text listing of that operation list (one op per line) into buf
  * (truncated to len-1 bytes, NUL-terminated); returns the bytes the full
  * listing needs, or a negative OC_ERR_*. */

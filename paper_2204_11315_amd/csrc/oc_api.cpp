@@ -214,7 +214,7 @@ int issue(oc_handle *h, const std::vector<oc::Op> &ops, const oc::Plan &p) {
         break;
       case oc::OP_ENC:
         x.ok(oc::launch_encode((const float *)(h->arena + o.dev_src), p.in.nx, p.in.ny, o.z_hi,
-                               p.in.rate, h->arena + o.dev_dst, s, kt));
+                               o.rate > 0 ? o.rate : p.in.rate, h->arena + o.dev_dst, s, kt));
         benc += blocks_per_layer * (uint64_t)o.z_hi;
         break;
       case oc::OP_STAR7: {
@@ -657,17 +657,21 @@ int oc_load(oc_handle *h, const float *u, const float *aux, const float *vel) {
   return OC_OK;
 }
 
-int oc_run(oc_handle *h, int64_t steps) {
-  if (!h || steps < 0) return OC_ERR_ARG;
-  if (h->broken || !h->loaded) return OC_ERR_STATE;
-  if (steps == 0) return OC_OK;
+namespace {
+
+// `steps` time steps through the pipeline; with `ck`, the last sweep also
+// writes the new state to the checkpoint store (that op list is not cached).
+int run_steps(oc_handle *h, int64_t steps, const oc::CkptOut *ck) {
   const oc::Plan &p = h->plan;
   const int64_t k = p.in.k;
   const int64_t sweeps = (steps + k - 1) / k;
   const int steps_last = (int)(steps - (sweeps - 1) * k);
   const int64_t t_key = p.in.kind == oc::KIND_WAVE25 ? h->time_index : 0;
   int64_t key[4] = {sweeps, steps_last, h->cur, t_key};
-  if (std::memcmp(key, h->ops_key, sizeof key) != 0) {
+  if (ck) {
+    oc::build_ops(p, sweeps, steps_last, h->cur, h->time_index, &h->ops, ck);
+    std::memset(h->ops_key, 0xff, sizeof h->ops_key);   // not a valid key
+  } else if (std::memcmp(key, h->ops_key, sizeof key) != 0) {
     oc::build_ops(p, sweeps, steps_last, h->cur, h->time_index, &h->ops);
     std::memcpy(h->ops_key, key, sizeof key);
   }
@@ -685,6 +689,15 @@ int oc_run(oc_handle *h, int64_t steps) {
   h->stats.slab_visits = (uint64_t)(sweeps * (int64_t)p.slabs.size());
   h->stats.n_ops = h->ops.size();
   return cr;
+}
+
+}  // namespace
+
+int oc_run(oc_handle *h, int64_t steps) {
+  if (!h || steps < 0) return OC_ERR_ARG;
+  if (h->broken || !h->loaded) return OC_ERR_STATE;
+  if (steps == 0) return OC_OK;
+  return run_steps(h, steps, nullptr);
 }
 
 int oc_store(oc_handle *h, float *u, float *aux) {
@@ -763,25 +776,43 @@ int oc_forward_ckpt(oc_handle *h, int64_t steps, int32_t ckpt_every, int32_t ckp
   if (adj_work_bytes(a, off) > host_work_bytes) return OC_ERR_BUDGET;
   h->ckpt_valid = false;
   uint8_t *work = (uint8_t *)host_work;
-  for (int sg = 0; sg < a.nseg; sg++) {
-    uint8_t *dst = work + off[0] + a.ckpt_off[(size_t)sg];
-    const float *cur = (const float *)h->host[h->cur];
-    if (a.ckpt_coded[(size_t)sg]) {
-      // codes made on the GPU through the adjoint plan's two slots' buffers
-      uint8_t *const wbuf[2] = {h->arena + a.off_buf[0][oc::A_U0], h->arena + a.off_buf[1][oc::A_U0]};
-      uint8_t *const sbuf[2] = {h->arena + a.off_cstage[0], h->arena + a.off_cstage[1]};
-      r = encode_field(h, cur, dst, a.ckpt_rate, std::max<int64_t>(4, a.g.P / 4 * 4), wbuf, sbuf);
-    } else {
-      std::memcpy(dst, cur, a.field_bytes);
-    }
-    if (r) {
-      h->broken = r == OC_ERR_HIP;
-      return r;
+  // Checkpoint sg + 1 is written by the last sweep of segment sg itself
+  // (codes made from the slab results on the device) where the plan allows;
+  // otherwise, and for u_0, it is made from the host level between segments.
+  const bool in_pipe = oc::ckpt_out_supported(h->plan, a.ckpt_rate);
+  uint8_t *const saved = h->host[oc::HOST_CKPT], *const saved_dev = h->host_dev[oc::HOST_CKPT];
+  h->host[oc::HOST_CKPT] = work + off[0];
+  h->host_dev[oc::HOST_CKPT] = mapped_host(work + off[0]);
+  for (int sg = 0; sg < a.nseg && r == OC_OK; sg++) {
+    if (sg == 0 || !in_pipe) {
+      uint8_t *dst = work + off[0] + a.ckpt_off[(size_t)sg];
+      const float *cur = (const float *)h->host[h->cur];
+      if (a.ckpt_coded[(size_t)sg]) {
+        // codes made on the GPU through the adjoint plan's two slots' buffers
+        uint8_t *const wbuf[2] = {h->arena + a.off_buf[0][oc::A_U0], h->arena + a.off_buf[1][oc::A_U0]};
+        uint8_t *const sbuf[2] = {h->arena + a.off_cstage[0], h->arena + a.off_cstage[1]};
+        r = encode_field(h, cur, dst, a.ckpt_rate, std::max<int64_t>(4, a.g.P / 4 * 4), wbuf, sbuf);
+      } else {
+        std::memcpy(dst, cur, a.field_bytes);
+      }
+      if (r) {
+        h->broken = r == OC_ERR_HIP;
+        break;
+      }
     }
     const int64_t len = std::min<int64_t>(ckpt_every, steps - (int64_t)sg * ckpt_every);
-    r = oc_run(h, len);
-    if (r) return r;
+    oc::CkptOut ck;
+    const bool next = in_pipe && sg + 1 < a.nseg;
+    if (next) {
+      ck.rate = a.ckpt_coded[(size_t)sg + 1] ? a.ckpt_rate : 0;
+      ck.host_off = a.ckpt_off[(size_t)sg + 1];
+    }
+    r = run_steps(h, len, next ? &ck : nullptr);
+    if (!r && next && ck.rate > 0) r = codec_check_and_clear();
   }
+  h->host[oc::HOST_CKPT] = saved;
+  h->host_dev[oc::HOST_CKPT] = saved_dev;
+  if (r) return r;
   h->adj = a;
   h->adj_work = work;
   std::memcpy(h->adj_off, off, sizeof off);
@@ -953,8 +984,11 @@ int64_t oc_debug_plan_dump(const oc_grid *g, const oc_stencil *st, const oc_conf
   return (int64_t)s.size() + 1;
 }
 
-int64_t oc_debug_check_plan(const oc_grid *g, const oc_stencil *st, const oc_config *cfg,
-                            int64_t sweeps, int32_t mutate, int64_t i) {
+namespace {
+
+// ckpt_rate < 0: no checkpoint output
+int64_t check_plan_impl(const oc_grid *g, const oc_stencil *st, const oc_config *cfg,
+                        int64_t sweeps, int32_t ckpt_rate, int32_t mutate, int64_t i) {
   if (!grid_ok(g) || !st || !cfg || sweeps < 1) return OC_ERR_ARG;
   oc::Plan p;
   int r = oc::make_plan(plan_input(g, st, cfg), &p);
@@ -963,8 +997,18 @@ int64_t oc_debug_check_plan(const oc_grid *g, const oc_stencil *st, const oc_con
     if (!p.in_place) return OC_ERR_ARG;
     p.share = false;
   }
+  oc::CkptOut ck;
+  if (ckpt_rate >= 0) {
+    if (ckpt_rate > 32 || !oc::ckpt_out_supported(p, ckpt_rate)) return OC_ERR_UNSUPPORTED;
+    ck.rate = ckpt_rate;
+  }
   std::vector<oc::Op> ops;
-  oc::build_ops(p, sweeps, p.in.k, 0, 0, &ops);
+  oc::build_ops(p, sweeps, p.in.k, 0, 0, &ops, ckpt_rate >= 0 ? &ck : nullptr);
+  if (mutate == 0 && i == -1) {   // the number of waits
+    int64_t n = 0;
+    for (const oc::Op &o : ops) n += o.type == oc::OP_WAIT;
+    return n;
+  }
   if (mutate == 1) {  // drop the i-th wait
     int64_t seen = 0;
     bool dropped = false;
@@ -998,6 +1042,19 @@ int64_t oc_debug_check_plan(const oc_grid *g, const oc_stencil *st, const oc_con
   int64_t bad = oc::check_ops(p, ops, &why);
   if (bad && getenv("OC_CHECK_VERBOSE")) fprintf(stderr, "oc plan check: %s\n", why.c_str());
   return bad;
+}
+
+}  // namespace
+
+int64_t oc_debug_check_plan(const oc_grid *g, const oc_stencil *st, const oc_config *cfg,
+                            int64_t sweeps, int32_t mutate, int64_t i) {
+  return check_plan_impl(g, st, cfg, sweeps, -1, mutate, i);
+}
+
+int64_t oc_debug_check_plan_ckpt(const oc_grid *g, const oc_stencil *st, const oc_config *cfg,
+                                 int64_t sweeps, int32_t ckpt_rate_bits, int32_t mutate, int64_t i) {
+  if (ckpt_rate_bits < 0) return OC_ERR_ARG;
+  return check_plan_impl(g, st, cfg, sweeps, ckpt_rate_bits, mutate, i);
 }
 
 }  // extern "C"

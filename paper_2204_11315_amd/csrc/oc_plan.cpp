@@ -196,6 +196,7 @@ struct Builder {
     o.ev = -1;
     o.dev_src = o.dev_src2 = o.dev_dst = -1;
     o.levels = 1;
+    o.rate = 0;
     return o;
   }
   void push(const Op &o) {
@@ -259,8 +260,15 @@ struct Builder {
 
 }  // namespace
 
+bool ckpt_out_supported(const Plan &p, int rate) {
+  if (p.in.kind != KIND_STAR7 || p.coded) return false;
+  if (rate == 0) return true;
+  return p.in.nx % 4 == 0 && p.in.ny % 4 == 0 && p.in.nz % 4 == 0 && p.S % 4 == 0;
+}
+
 void build_ops(const Plan &p, int64_t sweeps, int steps_last, int src, int64_t step0,
-               std::vector<Op> *ops) {
+               std::vector<Op> *ops, const CkptOut *ck) {
+  if (ck && !ckpt_out_supported(p, ck->rate)) ck = nullptr;
   ops->clear();
   Builder B(p, ops);
   const int ns = (int)p.slabs.size();
@@ -493,6 +501,20 @@ void build_ops(const Plan &p, int64_t sweeps, int steps_last, int src, int64_t s
         B.push(o);
       }
     }
+    if (ck && ck->rate > 0 && x.t == sweeps - 1) {
+      // checkpoint codes of the new state, written into the slot's other
+      // working buffer from its first plane on: they end at or below plane S,
+      // under the planes the next slab may share
+      Op o = B.blank(OP_ENC, S_COMPUTE);
+      o.rate = ck->rate;
+      o.dev_src = (int64_t)(B.work(x.q, res[0]) + (size_t)p.halo * p.plane_bytes);
+      o.dev_dst = (int64_t)B.work(x.q, 1 - res[0]);
+      o.z_hi = x.nz_int / 4;
+      o.planes = x.nz_int;
+      o.slab = x.j;
+      o.sweep = x.t;
+      B.push(o);
+    }
     B.rec(S_COMPUTE, B.ev.out(x.q));
   };
 
@@ -515,6 +537,23 @@ void build_ops(const Plan &p, int64_t sweeps, int steps_last, int src, int64_t s
       } else {
         o.dev_src = (int64_t)(B.work(x.q, res[f]) + (size_t)p.halo * p.plane_bytes);
         o.host_off = (int64_t)((size_t)f * p.host_field_bytes + (size_t)x.sl->z0 * p.plane_bytes);
+        o.bytes = (int64_t)((size_t)x.nz_int * p.plane_bytes);
+      }
+      o.slab = x.j;
+      o.sweep = x.t;
+      B.push(o);
+    }
+    if (ck && x.t == sweeps - 1) {   // the checkpoint copy of the slab's interior
+      Op o = B.blank(OP_D2H, S_OUT);
+      o.host_id = (int8_t)HOST_CKPT;
+      if (ck->rate > 0) {
+        const size_t lb = coded_layer_bytes(p.in.nx, p.in.ny, ck->rate);
+        o.dev_src = (int64_t)B.work(x.q, 1 - res[0]);
+        o.host_off = (int64_t)(ck->host_off + (size_t)(x.sl->z0 / 4) * lb);
+        o.bytes = (int64_t)((size_t)(x.nz_int / 4) * lb);
+      } else {
+        o.dev_src = (int64_t)(B.work(x.q, res[0]) + (size_t)p.halo * p.plane_bytes);
+        o.host_off = (int64_t)(ck->host_off + (size_t)x.sl->z0 * p.plane_bytes);
         o.bytes = (int64_t)((size_t)x.nz_int * p.plane_bytes);
       }
       o.slab = x.j;
@@ -916,10 +955,12 @@ void accesses(const Plan &p, const Op &o, std::vector<Access> *a) {
         dev(o.dev_dst, (int64_t)((size_t)o.z_hi * 4 * p.plane_bytes), true);
       }
       break;
-    case OP_ENC:
+    case OP_ENC: {
+      const size_t lb = o.rate > 0 ? coded_layer_bytes(p.in.nx, p.in.ny, o.rate) : p.layer_bytes;
       dev(o.dev_src, (int64_t)((size_t)o.z_hi * 4 * p.plane_bytes), false);
-      dev(o.dev_dst, (int64_t)((size_t)o.z_hi * p.layer_bytes), true);
+      dev(o.dev_dst, (int64_t)((size_t)o.z_hi * lb), true);
       break;
+    }
     case OP_AXPY:
       dev(o.dev_src, o.bytes, false);
       dev(o.dev_src2, o.bytes, false);
@@ -1065,14 +1106,17 @@ int64_t check_ops(const Plan &p, const std::vector<Op> &ops, std::string *why,
           if (o.type == OP_D2H && o.sweep == t && o.host_id == id)
             rs.push_back({o.host_off, o.host_off + o.bytes});
         if (rs.empty()) continue;
-        any = true;
+        if (id <= HOST_LEVEL1) any = true;
         std::sort(rs.begin(), rs.end());
-        int64_t at = 0;
+        // a level is written whole; another store (a checkpoint) as one
+        // contiguous range
+        const int64_t from = id <= HOST_LEVEL1 ? 0 : rs.front().first;
+        int64_t at = from;
         for (const auto &r : rs) {
           if (r.first != at) break;
           at = r.second;
         }
-        if (at != (int64_t)p.host_level_bytes) {
+        if (id > HOST_LEVEL1 ? at != rs.back().second : at != (int64_t)p.host_level_bytes) {
           bad++;
           if (why && why->empty())
             *why = "sweep " + std::to_string(t) + " does not write back store " +

@@ -46,6 +46,7 @@ struct Op {
   int64_t step;         // WAVE: global time index n of p^n (source term)
   bool transpose;       // STAR7: apply A^T (the -/+ coefficients swapped)
   int32_t levels;       // STAR7: fused time steps in this launch (z_lo..z_hi = output planes)
+  int32_t rate;         // DEC/ENC: bits per value when not the plan's (0 = the plan's)
   int32_t slab, sweep;  // bookkeeping (tests, stats)
 };
 
@@ -136,8 +137,16 @@ struct EventIds {
 // Operation list of `sweeps` consecutive sweeps starting from host level `src`
 // (0 or 1).  steps_last = steps of the final sweep (<= k).  step0 = global
 // time index at the start (WAVE25 source term).
+// A copy of the state the last sweep of an op list writes, for a checkpoint
+// store (HOST_CKPT): raw FP32 planes (rate 0) or codes at `rate`.  Raw
+// 7-point plans whose slab interiors are whole block layers (or rate 0) only.
+struct CkptOut {
+  int rate = 0;
+  size_t host_off = 0;   // byte offset of this checkpoint in the store
+};
+bool ckpt_out_supported(const Plan &p, int rate);
 void build_ops(const Plan &p, int64_t sweeps, int steps_last, int src, int64_t step0,
-               std::vector<Op> *ops);
+               std::vector<Op> *ops, const CkptOut *ck = nullptr);
 
 // ---- adjoint (reverse sweeps over checkpoint segments) ------------------
 // Forward states u_{s*m} (s = 0 .. nseg-1) are kept as checkpoints; segment s

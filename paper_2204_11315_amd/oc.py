@@ -99,6 +99,7 @@ _SIGS = {
     "oc_adjoint": (ctypes.c_int, [_P, _P, _P, _P]),
     "oc_debug_check_adjoint": (_I64, [_P, _P, _P, _I64, _I32, _I32, _I32, _I64]),
     "oc_debug_check_plan": (_I64, [_P, _P, _P, _I64, _I32, _I64]),
+    "oc_debug_check_plan_ckpt": (_I64, [_P, _P, _P, _I64, _I32, _I32, _I64]),
     "oc_debug_plan_ops": (_I64, [_P, _P, _P, _I64, _P]),
     "oc_debug_plan_dump": (_I64, [_P, _P, _P, _I64, ctypes.c_char_p, _SZ]),
     "oc_debug_timeline": (_I64, [_P, _P, _P, _P, _P, _I64]),
@@ -211,6 +212,18 @@ def check_plan(shape, stencil: Stencil, k: int, slab_planes: int, rate: int, swe
                       in_place)
     return int(lib().oc_debug_check_plan(_ref(g), _ref(stencil), _ref(cfg), int(sweeps),
                                          int(mutate), int(i)))
+
+
+def check_plan_ckpt(shape, stencil: Stencil, k: int, slab_planes: int, sweeps: int, ckpt_rate: int,
+                    budget: int = 0, mutate: int = 0, i: int = 0, fuse: int = 0,
+                    share: bool = False) -> int:
+    """check_plan for an uncompressed op list whose last sweep also writes a
+    checkpoint (codes at ckpt_rate, or raw planes for 0); mutate=0, i=-1
+    returns the number of waits."""
+    g = make_grid(shape)
+    cfg = plan_config(k, slab_planes, 0, True, budget, fuse=fuse, share=share)
+    return int(lib().oc_debug_check_plan_ckpt(_ref(g), _ref(stencil), _ref(cfg), int(sweeps),
+                                              int(ckpt_rate), int(mutate), int(i)))
 
 
 def plan_ops(shape, stencil: Stencil, k: int, slab_planes: int, rate: int, sweeps: int,

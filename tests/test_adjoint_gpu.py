@@ -87,6 +87,32 @@ def test_fused_recomputation_is_bitwise_neutral(rate, every):
         assert np.array_equal(x.view(np.uint32), y.view(np.uint32))
 
 
+@pytest.mark.parametrize("rate", [16, 0])
+def test_checkpoints_written_by_the_forward_pipeline(rate):
+    # with block-aligned slabs the last sweep of each forward segment writes
+    # the next checkpoint itself (codes made on the device from the slab
+    # results); 6-plane slabs make them from the host level between segments.
+    # Both give the same checkpoint bytes and the same gradients.
+    u0, c0 = fields()
+    nseg = -(-STEPS // EVERY)
+    field = int(np.prod(SHAPE)) * 4
+    ck_bytes = field + (nseg - 1) * (oc.codec_bytes(SHAPE, rate) if rate else field)
+    out = {}
+    for S in (8, 6):
+        adj = oc.Adjoint(SHAPE, C, steps=STEPS, k=2, ckpt_every=EVERY, ckpt_rate=rate,
+                         budget=1 << 20, slab_planes=S)
+        try:
+            uT = adj.forward(u0, c0)
+            ck = adj.work[:ck_bytes].numpy().copy()
+            g = adj.backward(top_grad(uT))
+            out[S] = (ck, uT) + g
+        finally:
+            adj.close()
+    assert np.array_equal(out[8][0], out[6][0])
+    for a, b in zip(out[8][1:], out[6][1:]):
+        assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+
+
 def test_directional_derivatives_vs_central_differences():
     u0, c0 = fields()
     adj = oc.Adjoint(SHAPE, C, steps=STEPS, k=2, ckpt_every=EVERY, ckpt_rate=16, budget=BUDGET)

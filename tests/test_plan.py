@@ -411,3 +411,31 @@ def test_region_sharing_covers_the_c0_field(R, swb, shape, S):
     assert _h2d_bytes(d) == _expected_h2d(shape, k, S, R, 2, True) + c0_bytes
     d0 = oc.plan_dump(shape, st, k, S, R, 2, single_buffer=swb)
     assert _h2d_bytes(d0) == _expected_h2d(shape, k, S, R, 2, False) + _expected_h2d(shape, k, S, 0, 2, False)
+
+
+@pytest.mark.parametrize("shape,k,S", [((40, 12, 16), 4, 8), ((44, 8, 8), 2, 12), ((48, 8, 8), 4, 4),
+                                       ((40, 12, 16), 4, 40)])
+@pytest.mark.parametrize("ckpt_rate", [0, 16, 8])
+@pytest.mark.parametrize("share", [True, False])
+def test_forward_sweeps_writing_checkpoints_race_free_and_minimal(shape, k, S, ckpt_rate, share):
+    # the last sweep of a forward segment encodes each slab's new interior
+    # into the slot's other working buffer (below the planes the next slab
+    # shares) and copies it to the checkpoint store after the slab's level copy
+    st = oc.make_star7(c0_field=True)
+    kw = dict(share=share)
+    nw = oc.check_plan_ckpt(shape, st, k, S, 2, ckpt_rate, i=-1, **kw)
+    assert nw > 0
+    assert oc.check_plan_ckpt(shape, st, k, S, 2, ckpt_rate, **kw) == 0
+    for i in range(nw):
+        assert oc.check_plan_ckpt(shape, st, k, S, 2, ckpt_rate, mutate=1, i=i, **kw) > 0, i
+    assert oc.check_plan_ckpt(shape, st, k, S, 2, ckpt_rate, mutate=2, **kw) > 0
+
+
+def test_checkpoint_output_needs_block_aligned_raw_slabs():
+    st = oc.make_star7(c0_field=True)
+    assert oc.check_plan_ckpt((40, 12, 16), st, 4, 6, 1, 16) == oc.OC_ERR_UNSUPPORTED   # S % 4
+    assert oc.check_plan_ckpt((40, 12, 16), st, 4, 6, 1, 0) == 0                        # raw copies
+    g = oc.make_grid((40, 12, 16))
+    cfg = oc.plan_config(4, 8, 8)                                                         # coded plan
+    assert oc.lib().oc_debug_check_plan_ckpt(oc._ref(g), oc._ref(st), oc._ref(cfg), 1, 16, 0, 0) \
+        == oc.OC_ERR_UNSUPPORTED
