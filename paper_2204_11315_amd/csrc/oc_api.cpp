@@ -10,6 +10,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/oc.h"
@@ -58,6 +59,30 @@ struct oc_handle {
 };
 
 namespace {
+
+// Large host copies and fills split over a few threads (one thread moves ~10
+// GB/s; whole fields are GiBs).  Small sizes stay on the calling thread.
+void par_bytes(void *dst, const void *src, size_t n) {   // src == nullptr: fill with zeros
+  const size_t kMin = 64u << 20;
+  unsigned t = std::min<unsigned>(8u, std::max(1u, std::thread::hardware_concurrency()));
+  if (n < 2 * kMin || t < 2) {
+    if (src) std::memcpy(dst, src, n);
+    else std::memset(dst, 0, n);
+    return;
+  }
+  t = (unsigned)std::min<size_t>(t, n / kMin);
+  const size_t per = (n / t + 4095) & ~(size_t)4095;
+  std::vector<std::thread> pool;
+  for (unsigned i = 0; i < t; i++) {
+    const size_t lo = std::min(n, (size_t)i * per), hi = std::min(n, lo + per);
+    if (lo >= hi) break;
+    pool.emplace_back([=] {
+      if (src) std::memcpy((uint8_t *)dst + lo, (const uint8_t *)src + lo, hi - lo);
+      else std::memset((uint8_t *)dst + lo, 0, hi - lo);
+    });
+  }
+  for (auto &th : pool) th.join();
+}
 
 thread_local hipError_t g_last_hip = hipSuccess;
 
@@ -402,7 +427,7 @@ int encode_field(oc_handle *h, const float *src, uint8_t *dst, int rate, int64_t
 int load_field(oc_handle *h, const float *src, uint8_t *dst, bool coded) {
   const oc::Plan &p = h->plan;
   if (!coded) {
-    std::memcpy(dst, src, p.plane_bytes * (size_t)p.in.nz);
+    par_bytes(dst, src, p.plane_bytes * (size_t)p.in.nz);
     return OC_OK;
   }
   // two buffer pairs: working buffers a and b of the shared set (or of the
@@ -419,7 +444,7 @@ int store_field(oc_handle *h, const uint8_t *src, float *dst, bool coded) {
   hipStream_t s = h->s[0];
   const size_t pb = p.plane_bytes;
   if (!coded) {
-    std::memcpy(dst, src, pb * (size_t)p.in.nz);
+    par_bytes(dst, src, pb * (size_t)p.in.nz);
     return OC_OK;
   }
   const int64_t chunk = std::max<int64_t>(4, p.P / 4 * 4);
@@ -651,7 +676,7 @@ int oc_load(oc_handle *h, const float *u, const float *aux, const float *vel) {
     h->broken = r == OC_ERR_HIP;
     return r;
   }
-  if (p.in.c0_field) std::memcpy(h->host[2], aux, (size_t)p.host_aux_bytes);
+  if (p.in.c0_field) par_bytes(h->host[2], aux, (size_t)p.host_aux_bytes);
   h->loaded = true;
   h->time_index = 0;
   return OC_OK;
@@ -793,7 +818,7 @@ int oc_forward_ckpt(oc_handle *h, int64_t steps, int32_t ckpt_every, int32_t ckp
         uint8_t *const sbuf[2] = {h->arena + a.off_cstage[0], h->arena + a.off_cstage[1]};
         r = encode_field(h, cur, dst, a.ckpt_rate, std::max<int64_t>(4, a.g.P / 4 * 4), wbuf, sbuf);
       } else {
-        std::memcpy(dst, cur, a.field_bytes);
+        par_bytes(dst, cur, a.field_bytes);
       }
       if (r) {
         h->broken = r == OC_ERR_HIP;
@@ -827,8 +852,8 @@ int oc_adjoint(oc_handle *h, const float *gT, float *g_u0, float *g_c0) {
   const oc::AdjPlan &a = h->adj;
   uint8_t *w = h->adj_work;
   uint8_t *lam0 = w + h->adj_off[1], *lam1 = w + h->adj_off[2], *grad = w + h->adj_off[3];
-  std::memcpy(lam0, gT, a.field_bytes);
-  std::memset(grad, 0, a.field_bytes);
+  par_bytes(lam0, gT, a.field_bytes);
+  par_bytes(grad, nullptr, a.field_bytes);
   // map the host stores of the reverse sweeps, run them, restore the handle's
   uint8_t *saved[oc::kHostStores], *saved_dev[oc::kHostStores];
   std::memcpy(saved, h->host, sizeof saved);
@@ -858,8 +883,8 @@ int oc_adjoint(oc_handle *h, const float *gT, float *g_u0, float *g_c0) {
   }
   h->stats.wall_s = std::chrono::duration<double>(t1 - t0).count();
   h->stats.n_ops = ops.size();
-  std::memcpy(g_u0, (a.nseg & 1) ? lam1 : lam0, a.field_bytes);
-  if (g_c0) std::memcpy(g_c0, grad, a.field_bytes);
+  par_bytes(g_u0, (a.nseg & 1) ? lam1 : lam0, a.field_bytes);
+  if (g_c0) par_bytes(g_c0, grad, a.field_bytes);
   return OC_OK;
 }
 
