@@ -74,6 +74,16 @@ static size_t carve(Plan *p) {
       off += p->work_bytes;
     }
   }
+  // uncompressed 25-point runs with region sharing: a stash per slot for the
+  // shared planes of the two pressure fields
+  p->stash_bytes = 0;
+  if (in.kind == KIND_WAVE25 && !p->coded && in.share) {
+    p->stash_bytes = align256(2u * (size_t)(2 * p->halo) * p->plane_bytes);
+    for (int s = 0; s < p->slots; s++) {
+      p->off_stash[s] = off;
+      off += p->stash_bytes;
+    }
+  }
   (void)in;
   return off;
 }
@@ -157,10 +167,11 @@ int make_plan(const PlanInput &in, Plan *out) {
   // earlier one's input on the device.  The earlier input must survive its own
   // kernels: coded inputs live in the staging slot, past the encoder's output;
   // raw inputs survive only when one stencil launch covers all k steps.
-  // (the 25-point wave updates its raw inputs in place, so it shares only coded)
+  // (the 25-point leapfrog overwrites its raw inputs in place: uncompressed
+  // runs set the shared planes aside in a per-slot stash first)
   p.share = in.share && p.slabs.size() >= 2 &&
             ((in.kind == KIND_STAR7 && (p.coded || in.k <= in.fuse)) ||
-             (in.kind == KIND_WAVE25 && p.coded && p.ro_coded));
+             (in.kind == KIND_WAVE25 && (p.coded ? p.ro_coded : p.stash_bytes > 0)));
   // one host level updated in place (the Ensure clause of Algorithm 1): a
   // slab's copy-back overwrites its interior planes, which the next slab of
   // the sweep still needs as old values around their common face, so every
@@ -334,8 +345,14 @@ void build_ops(const Plan &p, int64_t sweeps, int steps_last, int src, int64_t s
   // inputs region sharing covers: the coded fields, the raw 7-point field and
   // the 7-point c0 field (read-only, so it survives the slab's kernels)
   auto shared_in = [&](const In &fi, int f) {
-    return fi.coded || (!p.coded && f == 0) || (!wave && fi.buf == 2);
+    return fi.coded || (!p.coded && (f == 0 || wave)) || (!wave && fi.buf == 2);
   };
+  // uncompressed 25-point: where slot q's stash keeps the shared planes of a
+  // pressure field (p^n first, then p^{n-1})
+  auto stash_of = [&](int q, int buf) {
+    return p.off_stash[q] + (buf == bpb ? 0u : (size_t)(2 * p.halo) * p.plane_bytes);
+  };
+  const bool stash = wave && !p.coded && p.share;
   // where a slot keeps its raw c0 slab as loaded
   auto c0_buf = [&](int q) { return c0_staged ? p.off_ro_stage[q] : B.work(q, 2); };
 
@@ -412,9 +429,15 @@ void build_ops(const Plan &p, int64_t sweeps, int steps_last, int src, int64_t s
                                 (size_t)(x.loc0 / 4) * p.layer_bytes);
           o.bytes = (int64_t)((size_t)(x.sh / 4) * p.layer_bytes);
           nsh++;
+        } else if (stash && fin[f].buf != bv) {
+          // a pressure field of an uncompressed wave run: from the stash
+          o.dev_src = (int64_t)stash_of(x.pq, fin[f].buf);
+          o.dev_dst = (int64_t)(B.work(x.q, fin[f].buf) + (size_t)x.loc0 * p.plane_bytes);
+          o.bytes = (int64_t)((size_t)x.sh * p.plane_bytes);
         } else {
-          const size_t src = fin[f].buf == 2 ? c0_buf(x.pq) : B.work(x.pq, 0);
-          const size_t dst = fin[f].buf == 2 ? c0_buf(x.q) : B.work(x.q, 0);
+          const bool c0 = !wave && fin[f].buf == 2;
+          const size_t src = c0 ? c0_buf(x.pq) : B.work(x.pq, fin[f].buf);
+          const size_t dst = c0 ? c0_buf(x.q) : B.work(x.q, fin[f].buf);
           o.dev_src = (int64_t)(src + (size_t)x.sh_src * p.plane_bytes);
           o.dev_dst = (int64_t)(dst + (size_t)x.loc0 * p.plane_bytes);
           o.bytes = (int64_t)((size_t)x.sh * p.plane_bytes);
@@ -447,6 +470,23 @@ void build_ops(const Plan &p, int64_t sweeps, int steps_last, int src, int64_t s
         o.z_hi = -1;
         o.planes = x.nload;
         o.bytes = (int64_t)((size_t)x.nload * p.plane_bytes);
+        o.slab = x.j;
+        o.sweep = x.t;
+        B.push(o);
+      }
+    }
+    if (stash && has_share_copy(g + 1)) {
+      // set the planes the next slab shares aside before the leapfrog
+      // overwrites them
+      const Geo nx1 = geo(g + 1);
+      for (int buf : {bpb, bpa}) {
+        if (nx1.sh <= 0) break;
+        Op o = B.blank(OP_DEC, S_COMPUTE);
+        o.dev_src = (int64_t)(B.work(x.q, buf) + (size_t)nx1.sh_src * p.plane_bytes);
+        o.dev_dst = (int64_t)stash_of(x.q, buf);
+        o.bytes = (int64_t)((size_t)nx1.sh * p.plane_bytes);
+        o.z_hi = -1;
+        o.planes = nx1.sh;
         o.slab = x.j;
         o.sweep = x.t;
         B.push(o);

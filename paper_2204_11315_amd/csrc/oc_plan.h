@@ -100,6 +100,10 @@ struct Plan {
   size_t stage_bytes = 0;  // one coded staging buffer
   size_t off_stage[kMaxSlots] = {};
   size_t off_ro_stage[kMaxSlots] = {};  // STAR7 raw c0 slab per ring slot (single working buffer)
+  // WAVE25 raw with region sharing: per slot, the 2h planes of p^n and
+  // p^{n-1} the next slab shares, set aside before the leapfrog overwrites them
+  size_t stash_bytes = 0;
+  size_t off_stash[kMaxSlots] = {};
   size_t arena_bytes = 0;
   std::vector<Slab> slabs;
   // host storage

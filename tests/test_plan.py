@@ -288,10 +288,37 @@ def test_region_sharing_needs_an_intact_input():
     d = oc.plan_dump(shape, ST, k, S, 0, 2, fuse=2, share=True)
     assert "z=[0,-1)" not in d
     assert _h2d_bytes(d) == _expected_h2d(shape, k, S, 0, 2, False)
-    # the uncompressed 25-point wave updates its inputs in place: no sharing
+
+
+
+@pytest.mark.parametrize("shape,k,S", [((32, 8, 8), 2, 8), ((48, 8, 12), 2, 16), ((40, 8, 8), 1, 8),
+                                       ((36, 12, 8), 2, 12), ((24, 8, 8), 2, 24)])
+def test_region_sharing_uncompressed_wave_through_a_stash(shape, k, S):
+    # the leapfrog overwrites p^{n-1} and p^n in place, so each slab first sets
+    # the 2h planes the next slab shares aside (a per-slot stash of two fields)
     wst = oc.make_wave25(10.0, 1e-3, (4, 4, 4), 15.0, 1.0 / 15)
-    d = oc.plan_dump((32, 8, 8), wst, 2, 8, 0, 1, share=True)
-    assert "z=[0,-1)" not in d
+    nslab = len(range(0, shape[0], S))
+    for slots, pre in ((0, 0), (4, 3)):
+        for in_place in (False, True):
+            kw = dict(ring_slots=slots, prefetch=pre, share=True, in_place=in_place)
+            n, nw = oc.plan_ops(shape, wst, k, S, 0, 2, **kw)
+            assert oc.check_plan(shape, wst, k, S, 0, 2, **kw) == 0
+            for i in range(nw):
+                assert oc.check_plan(shape, wst, k, S, 0, 2, mutate=1, i=i, **kw) > 0, (slots, i)
+            if in_place and nslab > 1:
+                assert oc.check_plan(shape, wst, k, S, 0, 2, mutate=4, **kw) > 0
+        d = oc.plan_dump(shape, wst, k, S, 0, 2, ring_slots=slots, prefetch=pre, share=True)
+        moves = sum(" DEC " in line and "z=[0,-1)" in line for line in d.splitlines())
+        # per slab with a successor: two stash copies; per slab after the
+        # first: three overlap copies (p^n, p^{n-1}, velocity)
+        assert moves == 2 * (2 * (nslab - 1) + 3 * (nslab - 1))
+        d0 = oc.plan_dump(shape, wst, k, S, 0, 2, ring_slots=slots, prefetch=pre)
+        if nslab > 1:
+            assert _h2d_bytes(d) < _h2d_bytes(d0)
+    # the arena grows by one stash (2 x 2h planes) per ring slot
+    plane = shape[1] * shape[2] * 4
+    extra = oc.plan_bytes(shape, wst, k, S, 0, share=True) - oc.plan_bytes(shape, wst, k, S, 0)
+    assert extra == 3 * ((2 * 2 * 4 * k * plane + 255) // 256 * 256)
 
 
 @pytest.mark.parametrize("shape,k,S", [((32, 8, 8), 2, 8), ((48, 8, 12), 2, 16), ((40, 8, 8), 1, 8),
@@ -349,7 +376,8 @@ def test_in_place_needs_sharing_or_one_slab():
     shape = (40, 12, 16)
     assert oc.check_plan(shape, ST, 4, 8, 8, 2, in_place=True) == oc.OC_ERR_ARG      # sharing off
     assert oc.check_plan(shape, ST, 4, 8, 0, 2, fuse=2, share=True, in_place=True) == oc.OC_ERR_ARG
-    assert oc.check_plan(shape, WAVE, 2, 8, 0, 2, share=True, in_place=True) == oc.OC_ERR_ARG
+    assert oc.check_plan(shape, WAVE, 2, 8, 0, 2, in_place=True) == oc.OC_ERR_ARG     # sharing off
+    assert oc.check_plan(shape, WAVE, 2, 8, 0, 2, share=True, in_place=True) == 0     # stash
     # one slab: nothing to share, in place is safe
     assert oc.check_plan(shape, ST, 4, 40, 0, 3, in_place=True) == 0
     assert oc.check_plan(shape, ST, 4, 40, 8, 3, in_place=True) == 0

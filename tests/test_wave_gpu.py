@@ -64,10 +64,14 @@ def test_source_only_first_step_matches_oracle():
     assert abs(cur[SRC[2], SRC[1], SRC[0]] - rc[SRC[2], SRC[1], SRC[0]]) <= 1e-6 * abs(rc).max()
 
 
-@pytest.mark.parametrize("k,S,steps", [(2, 8, 6), (2, 8, 5), (1, 12, 3), (3, 40, 6)])
-def test_ooc_uncompressed_equals_incore_bitwise(k, S, steps):
+@pytest.mark.parametrize("k,S,steps", [(2, 8, 6), (2, 8, 5), (1, 12, 3), (3, 40, 6), (3, 4, 7)])
+@pytest.mark.parametrize("share,in_place", [(True, False), (False, False), (True, True)])
+def test_ooc_uncompressed_equals_incore_bitwise(k, S, steps, share, in_place):
+    # with sharing, each slab sets the planes the next one shares aside
+    # before the leapfrog overwrites them; in place needs that sharing
     vel, dt, st, p0, pm1 = setup()
-    o = oc.OutOfCore(SHAPE, k=k, rate=0, slab_planes=S, budget=64 << 20, stencil=st)
+    o = oc.OutOfCore(SHAPE, k=k, rate=0, slab_planes=S, budget=64 << 20, stencil=st, share=share,
+                     in_place=in_place)
     try:
         o.load(p0, pm1, vel)
         o.run(steps)
