@@ -91,9 +91,12 @@ typedef struct {
                               kernel with 4 workgroups; -1 = the runtime's hipMemcpyAsync   */
   int32_t share_overlap;   /* region sharing (Sec. 3.1, Fig. 2): a slab takes the 2h planes
                               around its lower face from the previous slab's input on the
-                              device instead of the host (coded runs of both stencils, and
-                              uncompressed 7-point runs with k <= fuse_steps); 0 or 1 = on
-                              where it applies, -1 = off (every slab loads both halos)     */
+                              device instead of the host (coded runs of both stencils,
+                              uncompressed 7-point runs with k <= fuse_steps, uncompressed
+                              25-point runs through a per-slot stash of 2 x 2h planes that
+                              the arena then holds; read-only c0 / velocity fields too);
+                              0 or 1 = on where it applies, -1 = off (every slab loads both
+                              halos).  Also applies to oc_adjoint's reverse sweeps.        */
   int32_t in_place;        /* 1 = one host level, host_level[0], updated in place by every
                               sweep (Algorithm 1, Ensure); host_level[1] is ignored and may
                               be NULL.  Needs region sharing in effect, or a single slab;
