@@ -265,6 +265,9 @@ int issue(oc_handle *h, const std::vector<oc::Op> &ops, const oc::Plan &p) {
         }
         break;
       }
+      case oc::OP_ZERO:
+        x.ok(hipMemsetAsync(h->arena + o.dev_dst, 0, (size_t)o.bytes, s));
+        break;
       case oc::OP_AXPY:
         x.ok(oc::launch_axpy_prod((float *)(h->arena + o.dev_dst), (const float *)(h->arena + o.dev_src),
                                   (const float *)(h->arena + o.dev_src2), (size_t)o.bytes / 4u, s, kt));
@@ -852,8 +855,9 @@ int oc_adjoint(oc_handle *h, const float *gT, float *g_u0, float *g_c0) {
   const oc::AdjPlan &a = h->adj;
   uint8_t *w = h->adj_work;
   uint8_t *lam0 = w + h->adj_off[1], *lam1 = w + h->adj_off[2], *grad = w + h->adj_off[3];
+  // (the gradient store is not cleared: the first reverse sweep starts each
+  // slab's accumulator at zero on the device and writes the whole store)
   par_bytes(lam0, gT, a.field_bytes);
-  par_bytes(grad, nullptr, a.field_bytes);
   // map the host stores of the reverse sweeps, run them, restore the handle's
   uint8_t *saved[oc::kHostStores], *saved_dev[oc::kHostStores];
   std::memcpy(saved, h->host, sizeof saved);

@@ -814,7 +814,18 @@ void build_adjoint_ops(const AdjPlan &a, int lsrc, std::vector<Op> *ops) {
     if (c0f)
       h2d(x, HOST_AUX, (size_t)(x.sl->l0 + skip) * pb, buf(x.q, A_C) + (x.loc0 + skip) * (int64_t)pb,
           (x.nload - skip) * (int64_t)pb);
-    h2d(x, HOST_GRAD, (size_t)x.sl->z0 * pb, buf(x.q, A_G) + p.halo * (int64_t)pb, x.nz_int * (int64_t)pb);
+    if (x.t == 0) {
+      // the gradient starts at zero: clear the slab's accumulator instead of
+      // copying zeros in (the first reverse sweep writes the whole store)
+      Op o = B.blank(OP_ZERO, S_IN);
+      o.dev_dst = buf(x.q, A_G) + p.halo * (int64_t)pb;
+      o.bytes = x.nz_int * (int64_t)pb;
+      o.slab = x.j;
+      o.sweep = x.t;
+      B.push(o);
+    } else {
+      h2d(x, HOST_GRAD, (size_t)x.sl->z0 * pb, buf(x.q, A_G) + p.halo * (int64_t)pb, x.nz_int * (int64_t)pb);
+    }
     B.rec(S_IN, B.ev.in(x.q));
     B.rec(S_IN, B.ev.h2d(x.t & 1, x.j));
   };
@@ -944,7 +955,8 @@ void build_adjoint_ops(const AdjPlan &a, int lsrc, std::vector<Op> *ops) {
 }
 
 std::string dump_ops(const std::vector<Op> &ops) {
-  static const char *names[] = {"H2D", "D2H", "DEC", "ENC", "STAR7", "WAVE", "AXPY", "REC", "WAIT", "SYNC"};
+  static const char *names[] = {"H2D", "D2H", "DEC", "ENC", "STAR7", "WAVE", "AXPY", "REC", "WAIT", "SYNC",
+                                "ZERO"};
   std::string out;
   char line[256];
   for (size_t i = 0; i < ops.size(); i++) {
@@ -1001,6 +1013,9 @@ void accesses(const Plan &p, const Op &o, std::vector<Access> *a) {
       dev(o.dev_dst, (int64_t)((size_t)o.z_hi * lb), true);
       break;
     }
+    case OP_ZERO:
+      dev(o.dev_dst, o.bytes, true);
+      break;
     case OP_AXPY:
       dev(o.dev_src, o.bytes, false);
       dev(o.dev_src2, o.bytes, false);

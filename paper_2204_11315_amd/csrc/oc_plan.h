@@ -30,7 +30,8 @@ enum OpType : uint8_t {
   OP_AXPY,   // dev_dst[i] += dev_src[i] * dev_src2[i] over `bytes` bytes of FP32
   OP_REC,    // record event ev on stream
   OP_WAIT,   // stream waits for the latest record of ev
-  OP_SYNC    // host waits for every stream (end of a run)
+  OP_SYNC,   // host waits for every stream (end of a run)
+  OP_ZERO    // dev_dst[0, bytes) = 0 on the op's stream
 };
 
 struct Op {
