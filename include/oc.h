@@ -229,6 +229,10 @@ const char *oc_status_str(int status);
 /* Makes the n-th HIP call issued by the executor from now on fail with
  * OC_ERR_HIP (n >= 1); n < 0 disables. */
 int oc_debug_fail_after(oc_handle *h, int64_t n);
+/* on != 0: the executor waits for all three streams after every operation it
+ * issues (a run with no overlap at all, for comparing with the pipelined one);
+ * 0 restores the pipeline. */
+int oc_debug_serialize(oc_handle *h, int32_t on);
 /* Builds the operation list of `sweeps` sweeps (k steps each) for the plan
  * of (g, st, cfg) (plan fields only, as oc_plan_bytes), without a GPU, and runs the happens-before checker
  * over it: returns the number of unordered conflicting accesses, plus

@@ -41,6 +41,7 @@ struct oc_handle {
   int64_t time_index = 0; // time steps applied since load
   oc_stats stats{};
   int64_t fail_after = -1;
+  bool serialize = false;  // test hook: wait for every op before issuing the next
   int64_t hip_calls = 0;
   hipError_t last_hip = hipSuccess;
   // per-op timing (oc_config.timing)
@@ -317,6 +318,8 @@ int issue(oc_handle *h, const std::vector<oc::Op> &ops, const oc::Plan &p) {
       }
       host_s[hc] += std::chrono::duration<double>(std::chrono::steady_clock::now() - th0).count();
     }
+    if (h->serialize && x.st == OC_OK && o.type != oc::OP_SYNC)
+      for (int i = 0; i < 3; i++) x.ok(hipStreamSynchronize(h->s[i]));
     if (x.st != OC_OK) break;
   }
   h->stats.host_ms_kernels = host_s[H_KERNEL] * 1e3;
@@ -977,6 +980,12 @@ int oc_debug_fail_after(oc_handle *h, int64_t n) {
   if (!h) return OC_ERR_ARG;
   h->fail_after = n >= 1 ? n : -1;
   h->hip_calls = 0;
+  return OC_OK;
+}
+
+int oc_debug_serialize(oc_handle *h, int32_t on) {
+  if (!h) return OC_ERR_ARG;
+  h->serialize = on != 0;
   return OC_OK;
 }
 

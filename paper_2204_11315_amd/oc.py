@@ -99,6 +99,7 @@ _SIGS = {
     "oc_adjoint": (ctypes.c_int, [_P, _P, _P, _P]),
     "oc_debug_check_adjoint": (_I64, [_P, _P, _P, _I64, _I32, _I32, _I32, _I64]),
     "oc_debug_check_plan": (_I64, [_P, _P, _P, _I64, _I32, _I64]),
+    "oc_debug_serialize": (_I32, [_P, _I32]),
     "oc_debug_check_plan_ckpt": (_I64, [_P, _P, _P, _I64, _I32, _I32, _I64]),
     "oc_debug_plan_ops": (_I64, [_P, _P, _P, _I64, _P]),
     "oc_debug_plan_dump": (_I64, [_P, _P, _P, _I64, ctypes.c_char_p, _SZ]),
@@ -493,6 +494,10 @@ class OutOfCore:
 
     def fail_after(self, n: int):
         _check(lib().oc_debug_fail_after(self.h, int(n)), "oc_debug_fail_after")
+
+    def serialize(self, on: bool):
+        """Test hook: every operation completes before the next is issued."""
+        _check(lib().oc_debug_serialize(self.h, 1 if on else 0), "oc_debug_serialize")
 
     def close(self):
         if getattr(self, "h", None):

@@ -236,6 +236,25 @@ def test_injected_hip_failure_is_reported_and_handle_destroyable():
     o.close()
 
 
+def test_failed_run_leaves_the_last_complete_level_intact():
+    # two host levels: a run that fails in its first sweep writes only the
+    # level the state is not in
+    u0 = inputs.grf_field(SHAPE, seed=21)
+    for R in (8, 0):
+        o = oc.OutOfCore(SHAPE, k=4, rate=R, slab_planes=8, share=False)
+        try:
+            o.load(u0)
+            o.run(4)                                   # one sweep: the state is in level 1
+            want = o.levels[1].numpy().copy()
+            o.fail_after(9)
+            with pytest.raises(oc.OCError) as e:
+                o.run(8)
+            assert e.value.status == oc.OC_ERR_HIP
+            assert np.array_equal(o.levels[1].numpy(), want)
+        finally:
+            o.close()
+
+
 def test_budget_too_small_is_rejected():
     with pytest.raises(oc.OCError) as e:
         oc.OutOfCore(SHAPE, k=4, rate=0, slab_planes=8, budget=1 << 16)
