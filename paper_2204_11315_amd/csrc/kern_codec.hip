@@ -305,14 +305,13 @@ __global__ __launch_bounds__(256) void k_encode(const float *__restrict__ in, in
       raw[16 * k + 4 * j + 2] = __float_as_uint(v.z);
       raw[16 * k + 4 * j + 3] = __float_as_uint(v.w);
     }
-  uint32_t Eb = 1;
-  bool bad = false;
+  // block exponent: the largest exponent field, taken in place (bits 23..30)
+  // so that no per-value exponent stays live until the quantisation below
+  uint32_t emax = 0;
 #pragma unroll
-  for (int t = 0; t < 64; t++) {
-    uint32_t E = (raw[t] >> 23) & 255u;
-    bad |= (E == 255u);
-    Eb = max(Eb, max(E, 1u));
-  }
+  for (int t = 0; t < 64; t++) emax = max(emax, raw[t] & 0x7F800000u);
+  const bool bad = emax == 0x7F800000u;   // an infinity or NaN in the block
+  const uint32_t Eb = max(emax >> 23, 1u);
   if (bad) atomicOr(&g_oc_codec_err, 1);
   int32_t q[64];
 #pragma unroll
@@ -333,6 +332,14 @@ __global__ __launch_bounds__(256) void k_encode(const float *__restrict__ in, in
   }
   bit_transpose32(lo);
   bit_transpose32(hi);
+  // finish the transposes here: left to itself the compiler sinks their last
+  // stages into the plane loop, which keeps more intermediate words live than
+  // the 64 plane words (155 VGPRs, three waves per SIMD instead of four)
+#pragma unroll
+  for (int p = 0; p < 32; p++) {
+    asm volatile("" : "+v"(lo[p]));
+    asm volatile("" : "+v"(hi[p]));
+  }
 
   BitWriter w;
   w.NW = NW;
