@@ -130,18 +130,18 @@ ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # seeded field under the 7-point stencil), one figure per code rate: VALU
 # wave-instructions per wave of 64 blocks (SQ_INSTS_VALU / SQ_WAVES), averaged
 # over those states.  The count grows as the field smooths (more bit planes
-# fit the budget): decode 4,559 at state 0 to 7,232 at state 60 (R = 8).
-VALU_PER_WAVE = {("decode", 8): 6706.0, ("encode", 8): 6265.0,
-                 ("decode", 9): 6810.0, ("encode", 9): 6358.0,
-                 ("decode", 16): 7399.0, ("encode", 16): 6829.0}
+# fit the budget): decode ~4,500 at state 0 to ~7,200 at state 60 (R = 8).
+VALU_PER_WAVE = {("decode", 8): 6646.0, ("encode", 8): 6287.0,
+                 ("decode", 9): 6749.0, ("encode", 9): 6378.0,
+                 ("decode", 16): 7337.0, ("encode", 16): 6827.0}
 # HBM bytes per launch over the algorithmic bytes, from FETCH_SIZE and
 # WRITE_SIZE of the same probe launches (each scaled by what it reads for a
 # plain 256 MiB device copy: FETCH x 2, WRITE x 1 KiB per unit), read and write
 # weighted by their algorithmic bytes.  Four fused 7-point steps over 72
 # planes: fetch 1.38 (tile halos and z-chunk overlap), write 1.01 -> 1.195.
-# Decode at R = 8: 1.04 of 18 MiB, 1.00 of 72 MiB -> 1.008; encode: 1.01 of
+# Decode at R = 8: 1.05 of 18 MiB, 1.00 of 72 MiB -> 1.010; encode: 1.01 of
 # 64 MiB, 1.00 of 16 MiB -> 1.008.
-TRAFFIC_RATIO = {"stencil": 1.195, "decode": 1.008, "encode": 1.008}
+TRAFFIC_RATIO = {"stencil": 1.195, "decode": 1.010, "encode": 1.008}
 
 
 def kernel_roofline(stats, rate):
