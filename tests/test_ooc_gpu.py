@@ -259,3 +259,24 @@ def test_budget_too_small_is_rejected():
     with pytest.raises(oc.OCError) as e:
         oc.OutOfCore(SHAPE, k=4, rate=0, slab_planes=8, budget=1 << 16)
     assert e.value.status == oc.OC_ERR_BUDGET
+
+
+@pytest.mark.parametrize("shape,kw", [
+    ((1, 3, 5), dict(k=1, rate=0, slab_planes=1)),            # one plane, one slab
+    ((7, 1, 9), dict(k=2, rate=0, slab_planes=2)),            # a line per plane, ragged last slab
+    ((4, 4, 4), dict(k=4, rate=1, slab_planes=4)),            # one block, the lowest rate
+    ((4, 4, 4), dict(k=4, rate=32, slab_planes=4)),           # one block, the highest rate
+    ((12, 4, 8), dict(k=1, rate=8, slab_planes=4, in_place=True)),
+    ((20, 8, 4), dict(k=3, rate=0, slab_planes=3, in_place=True)),
+])
+def test_degenerate_grids_equal_incore(shape, kw):
+    u0 = inputs.grf_field(shape, seed=22) if min(shape) >= 4 else \
+        np.random.default_rng(22).standard_normal(shape).astype(np.float32)
+    steps = 5
+    got, _ = run_ooc(u0, steps, budget=64 << 20, **kw)
+    R = kw["rate"]
+    if R == 0:
+        want = oc.star7_incore(_dev(u0), C, steps).cpu().numpy()
+    else:
+        want = gpu_compressed_incore(u0, R, kw["k"], steps)
+    assert np.array_equal(got.view(np.uint32), want.view(np.uint32))

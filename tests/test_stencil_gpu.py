@@ -74,3 +74,16 @@ def test_fused_steps_equal_single_steps_bitwise(steps):
             u = oc.star7_incore(u, c, 1, c0f=field)
         single = u.cpu().numpy()
         assert np.array_equal(fused.view(np.uint32), single.view(np.uint32))
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 1), (1, 1, 70), (5, 1, 1), (1, 9, 1), (3, 2, 65), (2, 66, 3)])
+@pytest.mark.parametrize("steps", [1, 4, 5])
+def test_degenerate_shapes_vs_fp64(shape, steps):
+    # lines, single planes and single cells: every cell is a boundary cell;
+    # the fused kernel's masked variants and the single step both run here
+    rng = np.random.default_rng(6)
+    u0 = rng.standard_normal(shape).astype(np.float32)
+    c = (0.3, 0.05, 0.15, 0.07, 0.13, 0.11, 0.09)
+    got = oc.star7_incore(_dev(u0), c, steps).cpu().numpy()
+    want = oracle.star7_run(u0, c, steps)
+    assert np.abs(got - want).max() <= 1e-6 * max(1.0, np.abs(want).max())
