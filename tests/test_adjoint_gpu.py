@@ -87,8 +87,8 @@ def test_fused_recomputation_is_bitwise_neutral(rate, every):
         assert np.array_equal(x.view(np.uint32), y.view(np.uint32))
 
 
-@pytest.mark.parametrize("rate", [16, 0])
-def test_checkpoints_written_by_the_forward_pipeline(rate):
+@pytest.mark.parametrize("rate,fuse", [(16, 0), (0, 0), (16, 1)])
+def test_checkpoints_written_by_the_forward_pipeline(rate, fuse):
     # with block-aligned slabs the last sweep of each forward segment writes
     # the next checkpoint itself (codes made on the device from the slab
     # results); 6-plane slabs make them from the host level between segments.
@@ -100,7 +100,7 @@ def test_checkpoints_written_by_the_forward_pipeline(rate):
     out = {}
     for S in (8, 6):
         adj = oc.Adjoint(SHAPE, C, steps=STEPS, k=2, ckpt_every=EVERY, ckpt_rate=rate,
-                         budget=1 << 20, slab_planes=S)
+                         budget=1 << 20, slab_planes=S, fuse=fuse)   # fuse 1: two launches
         try:
             uT = adj.forward(u0, c0)
             ck = adj.work[:ck_bytes].numpy().copy()

@@ -459,6 +459,19 @@ def test_forward_sweeps_writing_checkpoints_race_free_and_minimal(shape, k, S, c
     assert oc.check_plan_ckpt(shape, st, k, S, 2, ckpt_rate, mutate=2, **kw) > 0
 
 
+@pytest.mark.parametrize("ckpt_rate", [0, 16])
+def test_checkpoint_output_with_two_stencil_launches_per_slab(ckpt_rate):
+    # k = 4 in groups of 2: the result is back in the input buffer and the
+    # codes go into the intermediate one (no sharing: the input is overwritten)
+    st = oc.make_star7(c0_field=True)
+    shape, k, S = (40, 12, 16), 4, 8
+    kw = dict(fuse=2, share=True)
+    nw = oc.check_plan_ckpt(shape, st, k, S, 2, ckpt_rate, i=-1, **kw)
+    assert oc.check_plan_ckpt(shape, st, k, S, 2, ckpt_rate, **kw) == 0
+    for i in range(nw):
+        assert oc.check_plan_ckpt(shape, st, k, S, 2, ckpt_rate, mutate=1, i=i, **kw) > 0, i
+
+
 def test_checkpoint_output_needs_block_aligned_raw_slabs():
     st = oc.make_star7(c0_field=True)
     assert oc.check_plan_ckpt((40, 12, 16), st, 4, 6, 1, 16) == oc.OC_ERR_UNSUPPORTED   # S % 4
