@@ -195,7 +195,11 @@ int oc_codec_status(oc_stream stream);
  *   dL/dc0(x) = sum_n lambda_{n+1}(x) u_n(x).
  * oc_forward_ckpt advances the loaded state like oc_run(steps) and keeps the
  * states u_0, u_m, u_2m, ... (m = ckpt_every) in host_work, u_0 exact and the
- * others as codes at ckpt_rate_bits (0 = raw).  oc_adjoint then runs reverse
+ * others as codes at ckpt_rate_bits (0 = raw).  Those after u_0 are written by
+ * the last sweep of each segment itself (encoded on the device from the slab
+ * results) when the slab depth is a multiple of 4 or the checkpoints are raw,
+ * and otherwise made from the host level between segments; the bytes are the
+ * same either way.  oc_adjoint then runs reverse
  * sweeps, one per checkpoint segment, newest first: each slab reloads its
  * checkpoint, recomputes the segment's states in device memory and steps
  * lambda back while accumulating dL/dc0.  It may be called again with another
