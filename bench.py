@@ -361,6 +361,83 @@ def wave_workload(args):
     print(json.dumps(out), flush=True)
 
 
+def incore_workload(args):
+    """In-core 7-point steps on one device field (config 1 and a larger grid
+    for the HBM roofline).  Config 1: 64^3, 8 steps, seeded modes + noise,
+    against the FP64 oracle (rel-L2 <= 1e-5); at 64^3 (1 MiB, L2-resident) a
+    launch is latency-bound.  512^3 (512 MiB, more than the 256 MiB MALL): the
+    single-step kernel and the four-step fused kernel, timed with HIP events
+    over `steps` launches after a warm-up; achieved HBM bandwidth counts the
+    algorithmic bytes (input planes read once, output planes written once per
+    launch).  The oracle runs config 1 only (this module's FP64 reference)."""
+    import torch
+    from paper_2204_11315_amd import inputs, oc
+    import oracle
+    out = {}
+    # config 1
+    u0 = inputs.modes_field((64, 64, 64), seed=1)
+    d = torch.from_numpy(u0).cuda()
+    for _ in range(max(1, args.warmup)):
+        oc.star7_incore(d, C, 8)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    n = 20
+    for _ in range(n):
+        r = oc.star7_incore(d, C, 8)
+    ev[1].record()
+    torch.cuda.synchronize()
+    ms = ev[0].elapsed_time(ev[1]) / n
+    got = r.cpu().numpy()
+    ref = oracle.star7_run(u0, C, 8)
+    out["config1"] = {"gcell_per_s": 64 ** 3 * 8 / (ms * 1e-3) / 1e9, "ms_per_run": ms,
+                      "rel_l2_vs_fp64": float(np.linalg.norm(got - ref) / np.linalg.norm(ref))}
+    log("in-core 64^3 x 8 steps: %.3f ms, %.2f GCell/s, rel-L2 %.2e" % (
+        ms, out["config1"]["gcell_per_s"], out["config1"]["rel_l2_vs_fp64"]))
+    # 512^3: HBM roofline of the single-step and the fused kernel
+    N = 512
+    big = torch.from_numpy(inputs.grf_field((N, N, N), seed=3)).cuda()
+    cells = float(N) ** 3
+    for name, per_launch, reps in (("single step", 1, 32), ("four fused steps", 4, 16)):
+        oc.star7_incore(big, C, per_launch)
+        torch.cuda.synchronize()
+        ev[0].record()
+        for _ in range(reps):
+            oc.star7_incore(big, C, per_launch)
+        ev[1].record()
+        torch.cuda.synchronize()
+        ms = ev[0].elapsed_time(ev[1]) / reps
+        gbs = 8.0 * cells / (ms * 1e-3) / 1e9          # input once + output once per launch
+        out[name] = {"ms_per_launch": ms, "steps_per_launch": per_launch,
+                     "gcell_per_s": cells * per_launch / (ms * 1e-3) / 1e9,
+                     "alg_hbm_gbs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS}
+        log("in-core 512^3 %s: %.3f ms per launch, %.1f GCell/s, %.0f GB/s (%.0f %% of HBM)" % (
+            name, ms, out[name]["gcell_per_s"], gbs, 100 * gbs / HBM_PEAK_GBS))
+    # practical ceiling: a plain device copy of the same bytes (read 512 MiB, write 512 MiB)
+    dst = torch.empty_like(big)
+    dst.copy_(big)
+    torch.cuda.synchronize()
+    ev[0].record()
+    for _ in range(16):
+        dst.copy_(big)
+    ev[1].record()
+    torch.cuda.synchronize()
+    ms = ev[0].elapsed_time(ev[1]) / 16
+    out["device copy"] = {"ms": ms, "gbs": 8.0 * cells / (ms * 1e-3) / 1e9}
+    log("in-core 512^3 plain device copy of the same bytes: %.3f ms, %.0f GB/s" % (ms, out["device copy"]["gbs"]))
+    one = out["single step"]
+    res = {"metric": "in-core 7-point GCell-updates/s (HBM roofline)", "value": one["gcell_per_s"],
+           "unit": "GCell-updates/s", "n_gpus": 1, "steps": 32, "warmup": args.warmup,
+           "ms_per_step": one["ms_per_launch"], "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic (GRF 512^3; modes 64^3)",
+           "config": {"workload": "7-point in-core, 512^3 FP32 single steps (and 64^3 x 8 steps "
+                                  "vs FP64)"},
+           "roofline": {"bound": "hbm", "achieved": one["alg_hbm_gbs"], "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": one["hbm_frac"], "traffic": None},
+           "runs": out}
+    print(json.dumps(res), flush=True)
+
+
 def adjoint_workload(args):
     """Adjoint of the 7-point path (config 5): 512x512x2048, c0(x) in [0.3, 0.5],
     L = 1/2 sum over the top plane of u_T^2 after 64 steps, checkpoints every 8
@@ -447,7 +524,7 @@ def main():
                     help="FP64 oracle reference over the full grid or at 192 sample cells")
     ap.add_argument("--kernels", action="store_true",
                     help="launch each hot kernel at slab shape (for rocprofv3), then exit")
-    ap.add_argument("--workload", choices=["star7", "wave", "adjoint"], default="star7")
+    ap.add_argument("--workload", choices=["star7", "wave", "adjoint", "incore"], default="star7")
     ap.add_argument("--wave-nz", type=int, default=4096)
     ap.add_argument("--wave-rates", default="0,12", help="legs of the wave workload (0 = raw)")
     ap.add_argument("--fd-dirs", type=int, default=32)
@@ -469,6 +546,9 @@ def main():
         return
     if args.workload == "wave":
         wave_workload(args)
+        return
+    if args.workload == "incore":
+        incore_workload(args)
         return
     if args.workload == "adjoint":
         adjoint_workload(args)

@@ -6,7 +6,8 @@
 // blocking, Sec. 3.1), so one launch updates local planes [z_lo, z_hi) of a
 // slab buffer whose local plane 0 is global plane gz0.
 //
-// Layout: a 64x4 workgroup owns a 64x4 column tile and marches a chunk of ZC
+// Layout (rows that are not whole float4s; otherwise k_star7_x4 below, four
+// x per lane): a 64x4 workgroup owns a 64x4 column tile and marches a chunk of ZC
 // planes.  Each lane keeps its (z-1, z, z+1) values in registers, so every
 // input plane is loaded once per lane plus the x/y neighbours, which hit the
 // cache lines of the neighbouring lanes' and rows' own loads.  A wave's 64
@@ -117,6 +118,61 @@ __device__ __forceinline__ float lane_from_left(float v) {    // value of lane -
 }
 __device__ __forceinline__ float lane_from_right(float v) {   // value of lane + 1
   return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x130, 0xf, 0xf, true));
+}
+
+// One 7-point step with four consecutive x per lane, for rows of whole,
+// 16-byte aligned float4s (nx % 4 == 0): a wave covers 256 contiguous x of a
+// row, so the (z+1, y-1, y+1) loads and the store are 1 KiB per instruction,
+// and the x neighbours come from the adjacent lanes by DPP shifts (lane 0's
+// left and lane 63's right neighbour, in the adjacent tiles, by single
+// loads).  Same per-cell operation order as every other 7-point kernel here.
+constexpr int VX = 256;   // x per row of a workgroup (64 lanes x 4)
+
+__device__ __forceinline__ float4 ld4(const float *p) { return *reinterpret_cast<const float4 *>(p); }
+
+template <bool FIELD>
+__global__ __launch_bounds__(64 * TY) void k_star7_x4(const float *__restrict__ in, float *__restrict__ out,
+                                                      const float *__restrict__ c0f, int nx, int ny,
+                                                      int z_lo, int z_hi, int gz0, int nz, int nbx,
+                                                      int nby, int nbz, oc::Star7Coef c) {
+  const int nb = nbx * nby * nbz;
+  const int t = xcd_tile(blockIdx.x, nb);
+  if (t >= nb) return;
+  const int tbx = t % nbx;
+  const int tby = (t / nbx) % nby;
+  const int tbz = t / (nbx * nby);
+  const int lane = (int)threadIdx.x;
+  const int x0 = tbx * VX + 4 * lane;
+  const int y = tby * TY + (int)threadIdx.y;
+  // a wave is one row: y is uniform across it; a lane's four x are all
+  // inside or all outside the grid.  Every lane takes part in the shifts.
+  const bool act = x0 < nx && y < ny;
+  const int zb = z_lo + tbz * ZC;
+  const int ze = min(zb + ZC, z_hi);
+  const ptrdiff_t plane = (ptrdiff_t)nx * (ptrdiff_t)ny;
+  const ptrdiff_t col = (ptrdiff_t)y * nx + x0;
+  const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
+  float4 below = (act && gz0 + zb - 1 >= 0) ? ld4(in + col + (ptrdiff_t)(zb - 1) * plane) : zero;
+  float4 cur = act ? ld4(in + col + (ptrdiff_t)zb * plane) : zero;
+  for (int z = zb; z < ze; z++) {
+    const ptrdiff_t o = col + (ptrdiff_t)z * plane;
+    const float4 above = (act && gz0 + z + 1 < nz) ? ld4(in + o + plane) : zero;
+    const float4 ym = (act && y > 0) ? ld4(in + o - nx) : zero;
+    const float4 yp = (act && y + 1 < ny) ? ld4(in + o + nx) : zero;
+    float l = lane_from_left(cur.w);
+    float r = lane_from_right(cur.x);
+    if (lane == 0) l = (act && x0 > 0) ? in[o - 1] : 0.0f;
+    if (lane == 63 || x0 + 4 >= nx) r = (act && x0 + 4 < nx) ? in[o + 4] : 0.0f;
+    const float4 c0 = FIELD ? (act ? ld4(c0f + o) : zero) : make_float4(c.c0, c.c0, c.c0, c.c0);
+    float4 v;
+    v.x = star7_point(c0.x, cur.x, l, cur.y, ym.x, yp.x, below.x, above.x, c);
+    v.y = star7_point(c0.y, cur.y, cur.x, cur.z, ym.y, yp.y, below.y, above.y, c);
+    v.z = star7_point(c0.z, cur.z, cur.y, cur.w, ym.z, yp.z, below.z, above.z, c);
+    v.w = star7_point(c0.w, cur.w, cur.z, r, ym.w, yp.w, below.w, above.w, c);
+    if (act) *reinterpret_cast<float4 *>(out + o) = v;
+    below = cur;
+    cur = above;
+  }
 }
 
 // State of one thread of the fused kernel.  win[s][slot][r] holds level s of
@@ -340,9 +396,23 @@ hipError_t launch_star7(const float *in, float *out, const float *c0f, int64_t n
                         int64_t z_lo, int64_t z_hi, int64_t gz0, int64_t nz, const Star7Coef &c,
                         hipStream_t s, KernelTimer *kt) {
   if (z_hi <= z_lo) return hipSuccess;
-  const int nbx = (int)((nx + TX - 1) / TX);
   const int nby = (int)((ny + TY - 1) / TY);
   const int nbz = (int)((z_hi - z_lo + ZC - 1) / ZC);
+  const uintptr_t align = (uintptr_t)in | (uintptr_t)out | (uintptr_t)c0f;
+  if (nx % 4 == 0 && align % 16 == 0) {   // rows of whole float4s
+    const int nbx = (int)((nx + VX - 1) / VX);
+    const int64_t nb = (int64_t)nbx * nby * nbz;
+    if (nb > 0x7fffffff) return hipErrorInvalidValue;
+    dim3 grid((unsigned)nb);
+    if (c0f)
+      hipExtLaunchKernelGGL(k_star7_x4<true>, grid, dim3(64, TY), 0, s, kt_start(kt), kt_stop(kt), 0, in, out,
+                            c0f, (int)nx, (int)ny, (int)z_lo, (int)z_hi, (int)gz0, (int)nz, nbx, nby, nbz, c);
+    else
+      hipExtLaunchKernelGGL(k_star7_x4<false>, grid, dim3(64, TY), 0, s, kt_start(kt), kt_stop(kt), 0, in, out,
+                            c0f, (int)nx, (int)ny, (int)z_lo, (int)z_hi, (int)gz0, (int)nz, nbx, nby, nbz, c);
+    return hipGetLastError();
+  }
+  const int nbx = (int)((nx + TX - 1) / TX);
   const int64_t nb = (int64_t)nbx * nby * nbz;
   if (nb > 0x7fffffff) return hipErrorInvalidValue;
   dim3 grid((unsigned)nb);
