@@ -178,7 +178,8 @@ int oc_destroy(oc_handle *h);
 size_t oc_codec_bytes(int64_t nx, int64_t ny, int64_t nz, int32_t rate_bits);
 /* Enqueues compression of d_in [nz][ny][nx] into d_out on `stream`; returns
  * after the enqueue.  Non-finite inputs set the stream's codec error word,
- * read by oc_codec_status. */
+ * read by oc_codec_status.  The FP32 field must be 16-byte aligned and the
+ * codes 4-byte aligned (as device allocations are); else OC_ERR_ARG. */
 int oc_codec_compress(const float *d_in, int64_t nx, int64_t ny, int64_t nz, int32_t rate_bits,
                       void *d_out, size_t out_bytes, oc_stream stream);
 int oc_codec_decompress(const void *d_in, int64_t nx, int64_t ny, int64_t nz, int32_t rate_bits,

@@ -496,6 +496,8 @@ int oc_codec_compress(const float *d_in, int64_t nx, int64_t ny, int64_t nz, int
                       void *d_out, size_t out_bytes, oc_stream stream) {
   if (!d_in || !d_out || nx <= 0 || ny <= 0 || nz <= 0 || rate_bits < 1 || rate_bits > 32)
     return OC_ERR_ARG;
+  // the kernels move the field as float4s and the codes as dwords
+  if (((uintptr_t)d_in & 15) || ((uintptr_t)d_out & 3)) return OC_ERR_ARG;
   if (nx % 4 || ny % 4 || nz % 4) return OC_ERR_SHAPE;
   if (out_bytes < oc_codec_bytes(nx, ny, nz, rate_bits)) return OC_ERR_ARG;
   hipError_t e = oc::launch_encode(d_in, nx, ny, nz / 4, rate_bits, d_out, (hipStream_t)stream);
@@ -510,6 +512,7 @@ int oc_codec_decompress(const void *d_in, int64_t nx, int64_t ny, int64_t nz, in
                         float *d_out, oc_stream stream) {
   if (!d_in || !d_out || nx <= 0 || ny <= 0 || nz <= 0 || rate_bits < 1 || rate_bits > 32)
     return OC_ERR_ARG;
+  if (((uintptr_t)d_in & 3) || ((uintptr_t)d_out & 15)) return OC_ERR_ARG;
   if (nx % 4 || ny % 4 || nz % 4) return OC_ERR_SHAPE;
   hipError_t e = oc::launch_decode(d_in, nx, ny, nz / 4, rate_bits, d_out, (hipStream_t)stream);
   if (e != hipSuccess) {
@@ -532,6 +535,7 @@ int oc_star7_incore(const float *d_in, float *d_out, float *d_tmp, int64_t nx, i
                     int64_t nz, const float *c, const float *d_c0f, int64_t steps,
                     oc_stream stream) {
   if (!d_in || !d_out || !c || nx <= 0 || ny <= 0 || nz <= 0 || steps < 0) return OC_ERR_ARG;
+  if (((uintptr_t)d_in | (uintptr_t)d_out | (uintptr_t)d_tmp | (uintptr_t)d_c0f) & 3) return OC_ERR_ARG;
   if (steps > oc::kMaxFusedSteps && !d_tmp) return OC_ERR_ARG;
   if (nx > (1 << 30) || ny > (1 << 30) || nz > (1 << 30)) return OC_ERR_ARG;
   hipStream_t s = (hipStream_t)stream;
@@ -569,6 +573,7 @@ int oc_wave25_incore(float *d_prev, float *d_cur, const float *d_vel, float *d_t
   if (!d_prev || !d_cur || !d_vel || !st || nx <= 0 || ny <= 0 || nz <= 0 || steps < 0 || n0 < 0)
     return OC_ERR_ARG;
   if (st->kind != OC_WAVE25 || !(st->h > 0.f && st->dt > 0.f)) return OC_ERR_ARG;
+  if (((uintptr_t)d_prev | (uintptr_t)d_cur | (uintptr_t)d_vel | (uintptr_t)d_tmp) & 3) return OC_ERR_ARG;
   if (nx > (1 << 30) || ny > (1 << 30) || nz > (1 << 30)) return OC_ERR_ARG;
   if ((steps & 1) && !d_tmp) return OC_ERR_ARG;
   hipStream_t s = (hipStream_t)stream;

@@ -480,3 +480,18 @@ def test_checkpoint_output_needs_block_aligned_raw_slabs():
     cfg = oc.plan_config(4, 8, 8)                                                         # coded plan
     assert oc.lib().oc_debug_check_plan_ckpt(oc._ref(g), oc._ref(st), oc._ref(cfg), 1, 16, 0, 0) \
         == oc.OC_ERR_UNSUPPORTED
+
+
+def test_device_entry_points_check_pointer_alignment_before_any_launch():
+    # misaligned device pointers come back as OC_ERR_ARG from the host checks
+    # (these fake addresses are never dereferenced)
+    import ctypes
+    lib = oc.lib()
+    P = ctypes.c_void_p
+    ok16, ok4, bad = P(1 << 20), P((1 << 20) + 4), P((1 << 20) + 2)
+    assert lib.oc_codec_compress(ok4, 4, 4, 4, 8, ok16, 64, None) == oc.OC_ERR_ARG   # field not 16-aligned
+    assert lib.oc_codec_compress(ok16, 4, 4, 4, 8, bad, 64, None) == oc.OC_ERR_ARG   # codes not 4-aligned
+    assert lib.oc_codec_decompress(bad, 4, 4, 4, 8, ok16, None) == oc.OC_ERR_ARG
+    assert lib.oc_codec_decompress(ok16, 4, 4, 4, 8, ok4, None) == oc.OC_ERR_ARG
+    c = (ctypes.c_float * 7)(*([0.1] * 7))
+    assert lib.oc_star7_incore(bad, ok16, ok16, 4, 4, 4, c, None, 1, None) == oc.OC_ERR_ARG
