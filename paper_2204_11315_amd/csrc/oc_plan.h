@@ -126,8 +126,9 @@ enum StreamRole { S_IN = 0, S_COMPUTE = 1, S_OUT = 2 };
 
 // Event numbering for a plan with n slabs.  Slot q = g mod slots of the
 // staging ring: "in" = its copy-in landed, "out" = its coded result is ready,
-// "free" = its copy-back finished.  Per slab and sweep parity: copy-in /
-// copy-back of that slab done (cross-sweep host-level hazards).
+// "free" = its copy-back finished (the reverse sweeps of the adjoint; the
+// forward op list uses the per-slab events for those two).  Per slab and sweep
+// parity: copy-in / copy-back of that slab done.
 struct EventIds {
   int n_slabs;
   int in(int q) const { return q; }
