@@ -437,9 +437,29 @@ __global__ __launch_bounds__(256) void k_decode(const uint32_t *__restrict__ in,
             // group bit, run and its closing 1 all lie in the window: one step
             const int run = __builtin_ctz(t);
             if (run >= 64 - n) { m = n + min(64 - n, BITS - (r.pos() + 1)); break; }
-            r.advance(run + 2);
+            const int used = run + 2;
             x |= 1ull << (n + run);
             n += run + 1;
+            // the next token too, when it lies in the same window (fewer trips
+            // for the lanes with the most new coefficients in this plane)
+            if (n < 64 && used < 32 && r.pos() + used < BITS) {
+              const uint32_t w2 = w >> used;
+              if (!(w2 & 1u)) {                    // closing group bit
+                r.advance(used + 1);
+                break;
+              }
+              const uint32_t t2 = (w2 >> 1) & ((1u << (31 - used)) - 1u);
+              if (t2) {
+                const int run2 = __builtin_ctz(t2);
+                if (run2 < 64 - n) {
+                  r.advance(used + run2 + 2);
+                  x |= 1ull << (n + run2);
+                  n += run2 + 1;
+                  continue;
+                }
+              }
+            }
+            r.advance(used);
             continue;
           }
           r.advance(1);
