@@ -360,7 +360,23 @@ __global__ __launch_bounds__(256) void k_encode(const float *__restrict__ in, in
           int tz = __builtin_ctzll(rest);
           // group test 1, then tz zeros and the set bit
           if (tz < 31) {
-            w.put(1u | (2u << tz), tz + 2);
+            uint32_t v = 1u | (2u << tz);
+            int len = tz + 2;
+            n += tz + 1;
+            rest >>= tz + 1;
+            // the next token in the same 32-bit put when it fits (bits past
+            // the budget only ever reach the slot's padding dword)
+            if (rest) {
+              const int tz2 = __builtin_ctzll(rest);
+              if (len + tz2 + 2 <= 32) {
+                v |= (1u | (2u << tz2)) << len;
+                len += tz2 + 2;
+                n += tz2 + 1;
+                rest >>= tz2 + 1;
+              }
+            }
+            w.put(v, len);
+            continue;
           } else if (tz < 62) {
             w.put64(1ull | (2ull << tz), tz + 2);
           } else {
