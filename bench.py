@@ -131,9 +131,9 @@ ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # wave-instructions per wave of 64 blocks (SQ_INSTS_VALU / SQ_WAVES), averaged
 # over those states.  The count grows as the field smooths (more bit planes
 # fit the budget): decode ~4,500 at state 0 to ~7,200 at state 60 (R = 8).
-VALU_PER_WAVE = {("decode", 8): 6713.0, ("encode", 8): 6287.0,
-                 ("decode", 9): 6821.0, ("encode", 9): 6378.0,
-                 ("decode", 16): 7422.0, ("encode", 16): 6827.0}
+VALU_PER_WAVE = {("decode", 8): 6713.0, ("encode", 8): 5801.0,
+                 ("decode", 9): 6821.0, ("encode", 9): 5891.0,
+                 ("decode", 16): 7422.0, ("encode", 16): 6344.0}
 # HBM bytes per launch over the algorithmic bytes, from FETCH_SIZE and
 # WRITE_SIZE of the same probe launches (each scaled by what it reads for a
 # plain 256 MiB device copy: FETCH x 2, WRITE x 1 KiB per unit), read and write
