@@ -108,12 +108,14 @@ def run_leg(oc, torch, u0, rate, steps, warmup, ref=None, timing=True):
             torch.cuda.synchronize()
             times.append(time.perf_counter() - t0)
             stats.append(o.stats())
-        err = None
-        if ref is not None:
-            o.load(u0)
-            o.run(STEPS)
-            err = ref.error(o.store())
-        return times, stats, err
+        # end to end: load (encode on the GPU when coded), the job, store
+        t0 = time.perf_counter()
+        o.load(u0)
+        o.run(STEPS)
+        got = o.store()
+        e2e = time.perf_counter() - t0
+        err = ref.error(got) if ref is not None else None
+        return times, stats, err, e2e
     finally:
         o.close()
 
@@ -237,17 +239,44 @@ def link_roofline(leg, link):
 
 def cpu_baseline(u0, rate):
     """The oracle's compressed path (FP64 stencil + scalar codec) on a bounded
-    sample: the full grid for one residency sweep of k steps."""
+    sample: the full grid for one residency sweep of k steps, on all host
+    threads.  Beside it, on a slab-sized sample of the same field: the oracle's
+    codec on all threads and on one, and its FP64 stencil on one thread."""
     import oracle
-    cores = os.cpu_count() or 1
+    cores = oracle.set_threads(0)   # the OpenMP thread count the oracle runs on
     t0 = time.perf_counter()
     oracle.compressed_sweeps(u0, C, K, K, rate)
     dt = time.perf_counter() - t0
     cells = float(np.prod(SHAPE)) * K
+
+    def codec_rates(f):
+        t0 = time.perf_counter()
+        code = oracle.compress(f, rate)
+        t1 = time.perf_counter()
+        oracle.decompress(code, f.shape, rate)
+        t2 = time.perf_counter()
+        return {"compress_gbs": f.nbytes / (t1 - t0) / 1e9,
+                "decompress_gbs": f.nbytes / (t2 - t1) / 1e9}
+
+    codec = {"all_threads": codec_rates(np.ascontiguousarray(u0[:S])),
+             "sample_all_threads": "512x512x%d FP32 planes of the input at R=%d" % (S, rate)}
+    prev = oracle.set_threads(1)
+    try:
+        one = np.ascontiguousarray(u0[:16])
+        codec["one_thread"] = codec_rates(one)
+        codec["sample_one_thread"] = "512x512x16 FP32 planes of the input at R=%d" % rate
+        t0 = time.perf_counter()
+        oracle.star7_run(one, C, K)
+        st1 = float(one.size) * K / (time.perf_counter() - t0) / 1e9
+    finally:
+        oracle.set_threads(prev)
     return {"value": cells / dt / 1e9, "unit": "GCell-updates/s", "cores": cores,
             "kind": "oracle",
             "sample": "full 512x512x2048 grid, one sweep of k=4 steps at R=%d "
-                      "(load-encode, decode, 4 FP64 steps, encode, decode), %.1f s" % (rate, dt)}
+                      "(load-encode, decode, 4 FP64 steps, encode, decode), %.1f s" % (rate, dt),
+            "codec": codec,
+            "one_thread_fp64_stencil_gcell_per_s": st1,
+            "one_thread_stencil_sample": "512x512x16 planes, k=4 FP64 steps, zero ghosts"}
 
 
 def kernel_probe(rate, reps=20):
@@ -513,7 +542,7 @@ def adjoint_workload(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--rate", type=int, default=0,
                     help="headline rate (bits/value); 0 = smallest candidate meeting --budget")
@@ -571,14 +600,15 @@ def main():
         cands.append(args.rate)
     legs = {}
     for rate in [0] + sorted(cands):
-        times, stats, err = run_leg(oc, torch, u0, rate, args.steps, args.warmup, ref)
+        times, stats, err, e2e = run_leg(oc, torch, u0, rate, args.steps, args.warmup, ref)
         med = float(np.median(times))
         st = stats[-1]
         legs[rate] = {"gcell_per_s": cells / med / 1e9, "ms_per_job": med * 1e3,
                       "rel_l2_vs_fp64": err, "peak_dev_bytes": st["peak_dev_bytes"],
                       "bytes_h2d": st["bytes_h2d"], "bytes_d2h": st["bytes_d2h"],
                       "kernels": kernel_roofline(stats, rate), "times_s": times,
-                      "ms_h2d_sum": st["ms_h2d"], "ms_d2h_sum": st["ms_d2h"]}
+                      "ms_h2d_sum": st["ms_h2d"], "ms_d2h_sum": st["ms_d2h"],
+                      "end_to_end_ms": e2e * 1e3}
         log("rate %2d: %.2f GCell/s, %.1f ms/job, err %s, dev %d MiB" % (
             rate, legs[rate]["gcell_per_s"], med * 1e3, err, st["peak_dev_bytes"] >> 20))
 
@@ -618,6 +648,8 @@ def main():
                    "error_budget": args.budget},
         "uncompressed_gcell_per_s": base_leg["gcell_per_s"],
         "speedup_vs_uncompressed": main_leg["gcell_per_s"] / base_leg["gcell_per_s"],
+        "end_to_end_ms": main_leg["end_to_end_ms"],
+        "uncompressed_end_to_end_ms": base_leg["end_to_end_ms"],
         "rel_l2_vs_fp64": main_leg["rel_l2_vs_fp64"],
         "error_reference": args.error,
         "uncompressed_rel_l2_vs_fp64": base_leg["rel_l2_vs_fp64"],

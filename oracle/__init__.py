@@ -85,6 +85,7 @@ def _load():
             "ocref_unread_mean": (ctypes.c_int32, [ctypes.c_int]),
             "ocref_sequency_order": (None, [P]),
             "ocref_quantize": (ctypes.c_int, [P, P, P]),
+            "ocref_set_threads": (ctypes.c_int, [ctypes.c_int]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(lib, name)
@@ -96,6 +97,12 @@ def _load():
 
 def _ptr(a: np.ndarray):
     return ctypes.c_void_p(a.ctypes.data)
+
+
+def set_threads(n: int) -> int:
+    """Set the host threads of the oracle's OpenMP loops (calling thread);
+    returns the previous count.  For timing the oracle on fewer cores."""
+    return int(_load().ocref_set_threads(int(n)))
 
 
 def _check(st: int, what: str):

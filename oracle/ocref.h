@@ -78,4 +78,8 @@ int32_t ocref_unread_mean(int d);
 void ocref_sequency_order(int *perm);
 int ocref_quantize(const float *v, int32_t *q, int *Eb);
 
+/* Host threads the OpenMP loops use from the calling thread on; n <= 0 leaves
+ * the count as it is.  Returns the previous count.  (Timing only.) */
+int ocref_set_threads(int n);
+
 #endif

@@ -20,8 +20,15 @@
  *   dL/du0 = lambda_0;  dL/dc0(x) = sum_{n=0}^{T-1} lambda_{n+1}[x] u_n[x].
  */
 #include "ocref.h"
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
+
+int ocref_set_threads(int n) {
+  const int prev = omp_get_max_threads();
+  if (n > 0) omp_set_num_threads(n);
+  return prev;
+}
 
 static double at(const double *u, int64_t nx, int64_t ny, int64_t nz, int64_t x, int64_t y,
                  int64_t z) {

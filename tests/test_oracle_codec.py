@@ -358,3 +358,19 @@ def test_field_layout_slot_index():
 def test_shape_must_be_block_aligned():
     with pytest.raises(oracle.OracleError):
         oracle.compress(np.zeros((4, 4, 6), np.float32), 8)
+
+
+def test_thread_count_does_not_change_codes():
+    # blocks are coded independently, so the host thread count the oracle's
+    # loops run on must not change a byte of the stream or of the decode
+    f = RNG.standard_normal((8, 12, 16)).astype(np.float32)
+    ref = oracle.compress(f, 9)
+    prev = oracle.set_threads(1)
+    try:
+        assert oracle.set_threads(0) == 1
+        one = oracle.compress(f, 9)
+        dec1 = oracle.decompress(one, f.shape, 9)
+    finally:
+        oracle.set_threads(prev)
+    assert np.array_equal(one, ref)
+    assert np.array_equal(dec1.view(np.uint32), oracle.decompress(ref, f.shape, 9).view(np.uint32))
