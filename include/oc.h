@@ -15,7 +15,9 @@
  *
  * Conventions shared by every call:
  *  - Return value: OC_OK (0) or a negative OC_ERR_* code; no exception or
- *    signal crosses this boundary.  oc_status_str() names a code.
+ *    signal crosses this boundary (a host allocation failure inside the
+ *    library returns OC_ERR_HOST, or 0 from the size queries).
+ *    oc_status_str() names a code.
  *  - Arrays are FP32, C order [nz][ny][nx] (x fastest) unless stated.
  *  - Ownership: the caller allocates and outlives every large buffer (device
  *    arena, host levels, input/output arrays, streams).  The library owns only
@@ -23,8 +25,8 @@
  *    hipMalloc/hipHostMalloc.
  *  - "device" pointers are HIP device memory of the current device; "host"
  *    pointers are process memory (pinned memory makes copies asynchronous).
- *  - A handle is not thread-safe.  After OC_ERR_HIP the handle may only be
- *    destroyed; with two host levels the one that held the last complete
+ *  - A handle is not thread-safe.  After OC_ERR_HIP (or OC_ERR_HOST from a
+ *    call that queues work) the handle may only be destroyed; with two host levels the one that held the last complete
  *    sweep is intact (with in_place the level may be partly updated).
  *  - Ghost cells outside the grid are zero (zero Dirichlet boundary).
  */
@@ -45,7 +47,8 @@ enum {
   OC_ERR_HIP = -4,       /* a HIP runtime call failed (or an injected failure)            */
   OC_ERR_NONFINITE = -5, /* the codec met an Inf/NaN value                                */
   OC_ERR_STATE = -6,     /* call out of order (e.g. run before load)                      */
-  OC_ERR_UNSUPPORTED = -7
+  OC_ERR_UNSUPPORTED = -7,
+  OC_ERR_HOST = -8       /* host memory or a host thread could not be had (C++ exception) */
 };
 
 typedef struct oc_handle oc_handle;

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <memory>
 #include <new>
 #include <string>
 #include <thread>
@@ -77,10 +78,15 @@ void par_bytes(void *dst, const void *src, size_t n) {   // src == nullptr: fill
   for (unsigned i = 0; i < t; i++) {
     const size_t lo = std::min(n, (size_t)i * per), hi = std::min(n, lo + per);
     if (lo >= hi) break;
-    pool.emplace_back([=] {
+    auto part = [=] {
       if (src) std::memcpy((uint8_t *)dst + lo, (const uint8_t *)src + lo, hi - lo);
       else std::memset((uint8_t *)dst + lo, 0, hi - lo);
-    });
+    };
+    try {
+      pool.emplace_back(part);
+    } catch (...) {   // no thread to be had: this part on the calling thread
+      part();
+    }
   }
   for (auto &th : pool) th.join();
 }
@@ -482,215 +488,260 @@ const char *oc_status_str(int st) {
     case OC_ERR_NONFINITE: return "non-finite value met by the codec";
     case OC_ERR_STATE: return "call out of order";
     case OC_ERR_UNSUPPORTED: return "unsupported combination";
+    case OC_ERR_HOST: return "host allocation or thread creation failed";
     default: return "unknown status";
   }
 }
 
 size_t oc_codec_bytes(int64_t nx, int64_t ny, int64_t nz, int32_t rate_bits) {
-  if (nx <= 0 || ny <= 0 || nz <= 0 || rate_bits < 1 || rate_bits > 32) return 0;
-  if (nx % 4 || ny % 4 || nz % 4) return 0;
-  return (size_t)(nx / 4) * (size_t)(ny / 4) * (size_t)(nz / 4) * 8u * (size_t)rate_bits;
+  try {
+    if (nx <= 0 || ny <= 0 || nz <= 0 || rate_bits < 1 || rate_bits > 32) return 0;
+    if (nx % 4 || ny % 4 || nz % 4) return 0;
+    return (size_t)(nx / 4) * (size_t)(ny / 4) * (size_t)(nz / 4) * 8u * (size_t)rate_bits;
+  } catch (...) {
+    return 0;
+  }
 }
 
 int oc_codec_compress(const float *d_in, int64_t nx, int64_t ny, int64_t nz, int32_t rate_bits,
                       void *d_out, size_t out_bytes, oc_stream stream) {
-  if (!d_in || !d_out || nx <= 0 || ny <= 0 || nz <= 0 || rate_bits < 1 || rate_bits > 32)
-    return OC_ERR_ARG;
-  // the kernels move the field as float4s and the codes as dwords
-  if (((uintptr_t)d_in & 15) || ((uintptr_t)d_out & 3)) return OC_ERR_ARG;
-  if (nx % 4 || ny % 4 || nz % 4) return OC_ERR_SHAPE;
-  if (out_bytes < oc_codec_bytes(nx, ny, nz, rate_bits)) return OC_ERR_ARG;
-  hipError_t e = oc::launch_encode(d_in, nx, ny, nz / 4, rate_bits, d_out, (hipStream_t)stream);
-  if (e != hipSuccess) {
-    g_last_hip = e;
-    return OC_ERR_HIP;
+  try {
+    if (!d_in || !d_out || nx <= 0 || ny <= 0 || nz <= 0 || rate_bits < 1 || rate_bits > 32)
+      return OC_ERR_ARG;
+    // the kernels move the field as float4s and the codes as dwords
+    if (((uintptr_t)d_in & 15) || ((uintptr_t)d_out & 3)) return OC_ERR_ARG;
+    if (nx % 4 || ny % 4 || nz % 4) return OC_ERR_SHAPE;
+    if (out_bytes < oc_codec_bytes(nx, ny, nz, rate_bits)) return OC_ERR_ARG;
+    hipError_t e = oc::launch_encode(d_in, nx, ny, nz / 4, rate_bits, d_out, (hipStream_t)stream);
+    if (e != hipSuccess) {
+      g_last_hip = e;
+      return OC_ERR_HIP;
+    }
+    return OC_OK;
+  } catch (...) {
+    return OC_ERR_HOST;
   }
-  return OC_OK;
 }
 
 int oc_codec_decompress(const void *d_in, int64_t nx, int64_t ny, int64_t nz, int32_t rate_bits,
                         float *d_out, oc_stream stream) {
-  if (!d_in || !d_out || nx <= 0 || ny <= 0 || nz <= 0 || rate_bits < 1 || rate_bits > 32)
-    return OC_ERR_ARG;
-  if (((uintptr_t)d_in & 3) || ((uintptr_t)d_out & 15)) return OC_ERR_ARG;
-  if (nx % 4 || ny % 4 || nz % 4) return OC_ERR_SHAPE;
-  hipError_t e = oc::launch_decode(d_in, nx, ny, nz / 4, rate_bits, d_out, (hipStream_t)stream);
-  if (e != hipSuccess) {
-    g_last_hip = e;
-    return OC_ERR_HIP;
+  try {
+    if (!d_in || !d_out || nx <= 0 || ny <= 0 || nz <= 0 || rate_bits < 1 || rate_bits > 32)
+      return OC_ERR_ARG;
+    if (((uintptr_t)d_in & 3) || ((uintptr_t)d_out & 15)) return OC_ERR_ARG;
+    if (nx % 4 || ny % 4 || nz % 4) return OC_ERR_SHAPE;
+    hipError_t e = oc::launch_decode(d_in, nx, ny, nz / 4, rate_bits, d_out, (hipStream_t)stream);
+    if (e != hipSuccess) {
+      g_last_hip = e;
+      return OC_ERR_HIP;
+    }
+    return OC_OK;
+  } catch (...) {
+    return OC_ERR_HOST;
   }
-  return OC_OK;
 }
 
 int oc_codec_status(oc_stream stream) {
-  hipError_t e = hipStreamSynchronize((hipStream_t)stream);
-  if (e != hipSuccess) {
-    g_last_hip = e;
-    return OC_ERR_HIP;
+  try {
+    hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+    if (e != hipSuccess) {
+      g_last_hip = e;
+      return OC_ERR_HIP;
+    }
+    return codec_check_and_clear();
+  } catch (...) {
+    return OC_ERR_HOST;
   }
-  return codec_check_and_clear();
 }
 
 int oc_star7_incore(const float *d_in, float *d_out, float *d_tmp, int64_t nx, int64_t ny,
                     int64_t nz, const float *c, const float *d_c0f, int64_t steps,
                     oc_stream stream) {
-  if (!d_in || !d_out || !c || nx <= 0 || ny <= 0 || nz <= 0 || steps < 0) return OC_ERR_ARG;
-  if (((uintptr_t)d_in | (uintptr_t)d_out | (uintptr_t)d_tmp | (uintptr_t)d_c0f) & 3) return OC_ERR_ARG;
-  if (steps > oc::kMaxFusedSteps && !d_tmp) return OC_ERR_ARG;
-  if (nx > (1 << 30) || ny > (1 << 30) || nz > (1 << 30)) return OC_ERR_ARG;
-  hipStream_t s = (hipStream_t)stream;
-  oc::Star7Coef cf{c[0], c[1], c[2], c[3], c[4], c[5], c[6]};
-  hipError_t e = hipSuccess;
-  if (steps == 0) {
-    e = hipMemcpyAsync(d_out, d_in, (size_t)(nx * ny * nz) * 4u, hipMemcpyDeviceToDevice, s);
-  } else {
-    // groups of up to kMaxFusedSteps fused steps, ping-ponging so that the
-    // last group writes d_out
-    const int64_t groups = (steps + oc::kMaxFusedSteps - 1) / oc::kMaxFusedSteps;
-    float *X = (groups % 2 == 1) ? d_out : d_tmp;
-    float *Y = (groups % 2 == 1) ? d_tmp : d_out;
-    const float *src = d_in;
-    int64_t done = 0;
-    for (int64_t gi = 1; gi <= groups && e == hipSuccess; gi++) {
-      const int lv = (int)std::min<int64_t>(oc::kMaxFusedSteps, steps - done);
-      float *dst = (gi % 2 == 1) ? X : Y;
-      e = lv > 1 ? oc::launch_star7_multi(src, dst, d_c0f, nx, ny, 0, nz, 0, nz, lv, cf, s)
-                 : oc::launch_star7(src, dst, d_c0f, nx, ny, 0, nz, 0, nz, cf, s);
-      src = dst;
-      done += lv;
+  try {
+    if (!d_in || !d_out || !c || nx <= 0 || ny <= 0 || nz <= 0 || steps < 0) return OC_ERR_ARG;
+    if (((uintptr_t)d_in | (uintptr_t)d_out | (uintptr_t)d_tmp | (uintptr_t)d_c0f) & 3) return OC_ERR_ARG;
+    if (steps > oc::kMaxFusedSteps && !d_tmp) return OC_ERR_ARG;
+    if (nx > (1 << 30) || ny > (1 << 30) || nz > (1 << 30)) return OC_ERR_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    oc::Star7Coef cf{c[0], c[1], c[2], c[3], c[4], c[5], c[6]};
+    hipError_t e = hipSuccess;
+    if (steps == 0) {
+      e = hipMemcpyAsync(d_out, d_in, (size_t)(nx * ny * nz) * 4u, hipMemcpyDeviceToDevice, s);
+    } else {
+      // groups of up to kMaxFusedSteps fused steps, ping-ponging so that the
+      // last group writes d_out
+      const int64_t groups = (steps + oc::kMaxFusedSteps - 1) / oc::kMaxFusedSteps;
+      float *X = (groups % 2 == 1) ? d_out : d_tmp;
+      float *Y = (groups % 2 == 1) ? d_tmp : d_out;
+      const float *src = d_in;
+      int64_t done = 0;
+      for (int64_t gi = 1; gi <= groups && e == hipSuccess; gi++) {
+        const int lv = (int)std::min<int64_t>(oc::kMaxFusedSteps, steps - done);
+        float *dst = (gi % 2 == 1) ? X : Y;
+        e = lv > 1 ? oc::launch_star7_multi(src, dst, d_c0f, nx, ny, 0, nz, 0, nz, lv, cf, s)
+                   : oc::launch_star7(src, dst, d_c0f, nx, ny, 0, nz, 0, nz, cf, s);
+        src = dst;
+        done += lv;
+      }
     }
+    if (e != hipSuccess) {
+      g_last_hip = e;
+      return OC_ERR_HIP;
+    }
+    return OC_OK;
+  } catch (...) {
+    return OC_ERR_HOST;
   }
-  if (e != hipSuccess) {
-    g_last_hip = e;
-    return OC_ERR_HIP;
-  }
-  return OC_OK;
 }
 
 int oc_wave25_incore(float *d_prev, float *d_cur, const float *d_vel, float *d_tmp, int64_t nx,
                      int64_t ny, int64_t nz, const oc_stencil *st, int64_t n0, int64_t steps,
                      oc_stream stream) {
-  if (!d_prev || !d_cur || !d_vel || !st || nx <= 0 || ny <= 0 || nz <= 0 || steps < 0 || n0 < 0)
-    return OC_ERR_ARG;
-  if (st->kind != OC_WAVE25 || !(st->h > 0.f && st->dt > 0.f)) return OC_ERR_ARG;
-  if (((uintptr_t)d_prev | (uintptr_t)d_cur | (uintptr_t)d_vel | (uintptr_t)d_tmp) & 3) return OC_ERR_ARG;
-  if (nx > (1 << 30) || ny > (1 << 30) || nz > (1 << 30)) return OC_ERR_ARG;
-  if ((steps & 1) && !d_tmp) return OC_ERR_ARG;
-  hipStream_t s = (hipStream_t)stream;
-  hipError_t e = hipSuccess;
-  float *a = d_prev, *b = d_cur;   // a holds p^{n-1}, b holds p^n
-  for (int64_t i = 0; i < steps && e == hipSuccess; i++) {
-    const float amp = (float)ricker((double)(n0 + i) * st->dt, st->f_peak, st->t0);
-    e = oc::launch_wave25(b, a, d_vel, nx, ny, 0, nz, 0, nz, st->dt / st->h, st->src, amp, s);
-    std::swap(a, b);
+  try {
+    if (!d_prev || !d_cur || !d_vel || !st || nx <= 0 || ny <= 0 || nz <= 0 || steps < 0 || n0 < 0)
+      return OC_ERR_ARG;
+    if (st->kind != OC_WAVE25 || !(st->h > 0.f && st->dt > 0.f)) return OC_ERR_ARG;
+    if (((uintptr_t)d_prev | (uintptr_t)d_cur | (uintptr_t)d_vel | (uintptr_t)d_tmp) & 3) return OC_ERR_ARG;
+    if (nx > (1 << 30) || ny > (1 << 30) || nz > (1 << 30)) return OC_ERR_ARG;
+    if ((steps & 1) && !d_tmp) return OC_ERR_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipSuccess;
+    float *a = d_prev, *b = d_cur;   // a holds p^{n-1}, b holds p^n
+    for (int64_t i = 0; i < steps && e == hipSuccess; i++) {
+      const float amp = (float)ricker((double)(n0 + i) * st->dt, st->f_peak, st->t0);
+      e = oc::launch_wave25(b, a, d_vel, nx, ny, 0, nz, 0, nz, st->dt / st->h, st->src, amp, s);
+      std::swap(a, b);
+    }
+    if (e == hipSuccess && (steps & 1)) {
+      // the newest level is in d_prev: swap the two buffers' contents
+      const size_t bytes = (size_t)(nx * ny * nz) * 4u;
+      e = hipMemcpyAsync(d_tmp, d_prev, bytes, hipMemcpyDeviceToDevice, s);
+      if (e == hipSuccess) e = hipMemcpyAsync(d_prev, d_cur, bytes, hipMemcpyDeviceToDevice, s);
+      if (e == hipSuccess) e = hipMemcpyAsync(d_cur, d_tmp, bytes, hipMemcpyDeviceToDevice, s);
+    }
+    if (e != hipSuccess) {
+      g_last_hip = e;
+      return OC_ERR_HIP;
+    }
+    return OC_OK;
+  } catch (...) {
+    return OC_ERR_HOST;
   }
-  if (e == hipSuccess && (steps & 1)) {
-    // the newest level is in d_prev: swap the two buffers' contents
-    const size_t bytes = (size_t)(nx * ny * nz) * 4u;
-    e = hipMemcpyAsync(d_tmp, d_prev, bytes, hipMemcpyDeviceToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(d_prev, d_cur, bytes, hipMemcpyDeviceToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(d_cur, d_tmp, bytes, hipMemcpyDeviceToDevice, s);
-  }
-  if (e != hipSuccess) {
-    g_last_hip = e;
-    return OC_ERR_HIP;
-  }
-  return OC_OK;
 }
 
 size_t oc_host_level_bytes(const oc_grid *g, const oc_stencil *st, int32_t rate_bits) {
-  if (!grid_ok(g) || !st) return 0;
-  oc::Plan p;
-  oc_config c = level_query_config(rate_bits);
-  if (oc::make_plan(plan_input(g, st, &c), &p) != oc::ST_OK) return 0;
-  return p.host_level_bytes;
+  try {
+    if (!grid_ok(g) || !st) return 0;
+    oc::Plan p;
+    oc_config c = level_query_config(rate_bits);
+    if (oc::make_plan(plan_input(g, st, &c), &p) != oc::ST_OK) return 0;
+    return p.host_level_bytes;
+  } catch (...) {
+    return 0;
+  }
 }
 
 size_t oc_host_aux_bytes(const oc_grid *g, const oc_stencil *st, int32_t rate_bits) {
-  if (!grid_ok(g) || !st) return 0;
-  oc::Plan p;
-  oc_config c = level_query_config(rate_bits);
-  if (oc::make_plan(plan_input(g, st, &c), &p) != oc::ST_OK) return 0;
-  return p.host_aux_bytes;
+  try {
+    if (!grid_ok(g) || !st) return 0;
+    oc::Plan p;
+    oc_config c = level_query_config(rate_bits);
+    if (oc::make_plan(plan_input(g, st, &c), &p) != oc::ST_OK) return 0;
+    return p.host_aux_bytes;
+  } catch (...) {
+    return 0;
+  }
 }
 
 size_t oc_plan_bytes(const oc_grid *g, const oc_stencil *st, const oc_config *cfg) {
-  if (!grid_ok(g) || !st || !cfg) return 0;
-  oc::Plan p;
-  if (oc::make_plan(plan_input(g, st, cfg), &p) != oc::ST_OK) return 0;
-  return p.arena_bytes;
+  try {
+    if (!grid_ok(g) || !st || !cfg) return 0;
+    oc::Plan p;
+    if (oc::make_plan(plan_input(g, st, cfg), &p) != oc::ST_OK) return 0;
+    return p.arena_bytes;
+  } catch (...) {
+    return 0;
+  }
 }
 
 int oc_create(const oc_grid *g, const oc_stencil *st, const oc_config *cfg, oc_handle **out) {
-  if (!grid_ok(g) || !st || !cfg || !out) return OC_ERR_ARG;
-  *out = nullptr;
-  if (st->kind != OC_STAR7 && st->kind != OC_WAVE25) return OC_ERR_ARG;
-  if (st->kind == OC_WAVE25 && !(st->h > 0.f && st->dt > 0.f)) return OC_ERR_ARG;
-  if (cfg->copy_back < -1 || cfg->copy_back > 1024) return OC_ERR_ARG;
-  oc::Plan p;
-  int r = oc::make_plan(plan_input(g, st, cfg), &p);
-  if (r != oc::ST_OK) return r;
-  if (!cfg->dev_arena || p.arena_bytes > cfg->dev_budget) return OC_ERR_BUDGET;
-  if (!cfg->host_level[0] || (!p.in_place && !cfg->host_level[1]) ||
-      cfg->host_level_bytes < p.host_level_bytes)
-    return OC_ERR_BUDGET;
-  if (p.host_aux_bytes && (!cfg->host_aux || cfg->host_aux_bytes < p.host_aux_bytes))
-    return OC_ERR_BUDGET;
-  for (int i = 0; i < 3; i++)
-    if (!cfg->streams[i]) return OC_ERR_ARG;
-  oc_handle *h = new (std::nothrow) oc_handle();
-  if (!h) return OC_ERR_ARG;
-  h->plan = p;
-  h->g = *g;
-  h->st = *st;
-  h->cfg = *cfg;
-  for (int i = 0; i < 3; i++) h->s[i] = (hipStream_t)cfg->streams[i];
-  h->timing = cfg->timing != 0;
-  h->arena = (uint8_t *)cfg->dev_arena;
-  h->host[0] = (uint8_t *)cfg->host_level[0];
-  h->host[1] = p.in_place ? nullptr : (uint8_t *)cfg->host_level[1];
-  h->host[2] = (uint8_t *)cfg->host_aux;
-  for (int i = 0; i < 3; i++) h->host_dev[i] = mapped_host(h->host[i]);
-  h->ckpt_valid = false;
-  oc::EventIds ids{(int)p.slabs.size()};
-  h->ev.assign((size_t)ids.count(), nullptr);
-  for (auto &e : h->ev) {
-    hipError_t err = hipEventCreateWithFlags(&e, hipEventDisableTiming);
-    if (err != hipSuccess) {
-      g_last_hip = err;
-      for (auto &f : h->ev)
-        if (f) (void)hipEventDestroy(f);
-      delete h;
-      return OC_ERR_HIP;
+  try {
+    if (!grid_ok(g) || !st || !cfg || !out) return OC_ERR_ARG;
+    *out = nullptr;
+    if (st->kind != OC_STAR7 && st->kind != OC_WAVE25) return OC_ERR_ARG;
+    if (st->kind == OC_WAVE25 && !(st->h > 0.f && st->dt > 0.f)) return OC_ERR_ARG;
+    if (cfg->copy_back < -1 || cfg->copy_back > 1024) return OC_ERR_ARG;
+    oc::Plan p;
+    int r = oc::make_plan(plan_input(g, st, cfg), &p);
+    if (r != oc::ST_OK) return r;
+    if (!cfg->dev_arena || p.arena_bytes > cfg->dev_budget) return OC_ERR_BUDGET;
+    if (!cfg->host_level[0] || (!p.in_place && !cfg->host_level[1]) ||
+        cfg->host_level_bytes < p.host_level_bytes)
+      return OC_ERR_BUDGET;
+    if (p.host_aux_bytes && (!cfg->host_aux || cfg->host_aux_bytes < p.host_aux_bytes))
+      return OC_ERR_BUDGET;
+    for (int i = 0; i < 3; i++)
+      if (!cfg->streams[i]) return OC_ERR_ARG;
+    std::unique_ptr<oc_handle> owner(new oc_handle());
+    oc_handle *h = owner.get();
+    h->plan = p;
+    h->g = *g;
+    h->st = *st;
+    h->cfg = *cfg;
+    for (int i = 0; i < 3; i++) h->s[i] = (hipStream_t)cfg->streams[i];
+    h->timing = cfg->timing != 0;
+    h->arena = (uint8_t *)cfg->dev_arena;
+    h->host[0] = (uint8_t *)cfg->host_level[0];
+    h->host[1] = p.in_place ? nullptr : (uint8_t *)cfg->host_level[1];
+    h->host[2] = (uint8_t *)cfg->host_aux;
+    for (int i = 0; i < 3; i++) h->host_dev[i] = mapped_host(h->host[i]);
+    h->ckpt_valid = false;
+    oc::EventIds ids{(int)p.slabs.size()};
+    h->ev.assign((size_t)ids.count(), nullptr);
+    for (auto &e : h->ev) {
+      hipError_t err = hipEventCreateWithFlags(&e, hipEventDisableTiming);
+      if (err != hipSuccess) {
+        g_last_hip = err;
+        for (auto &f : h->ev)
+          if (f) (void)hipEventDestroy(f);
+        return OC_ERR_HIP;
+      }
     }
+    h->stats.peak_dev_bytes = p.arena_bytes;
+    h->stats.slab_planes = p.S;
+    h->stats.halo_planes = p.halo;
+    h->stats.n_slabs = (int64_t)p.slabs.size();
+    *out = owner.release();
+    return OC_OK;
+  } catch (...) {
+    return OC_ERR_HOST;
   }
-  h->stats.peak_dev_bytes = p.arena_bytes;
-  h->stats.slab_planes = p.S;
-  h->stats.halo_planes = p.halo;
-  h->stats.n_slabs = (int64_t)p.slabs.size();
-  *out = h;
-  return OC_OK;
 }
 
 int oc_load(oc_handle *h, const float *u, const float *aux, const float *vel) {
-  if (!h || !u) return OC_ERR_ARG;
-  if (h->broken) return OC_ERR_STATE;
-  const oc::Plan &p = h->plan;
-  const bool wave = p.in.kind == oc::KIND_WAVE25;
-  if (p.in.c0_field && !aux) return OC_ERR_ARG;
-  if (wave && (!aux || !vel)) return OC_ERR_ARG;
-  h->cur = 0;
-  int r = load_field(h, u, h->host[0], p.coded);
-  if (!r && wave) r = load_field(h, aux, h->host[0] + p.host_field_bytes, p.coded);
-  if (!r && wave) r = load_field(h, vel, h->host[2], p.ro_coded);
-  if (r) {
-    h->broken = r == OC_ERR_HIP;
-    return r;
+  try {
+    if (!h || !u) return OC_ERR_ARG;
+    if (h->broken) return OC_ERR_STATE;
+    const oc::Plan &p = h->plan;
+    const bool wave = p.in.kind == oc::KIND_WAVE25;
+    if (p.in.c0_field && !aux) return OC_ERR_ARG;
+    if (wave && (!aux || !vel)) return OC_ERR_ARG;
+    h->cur = 0;
+    int r = load_field(h, u, h->host[0], p.coded);
+    if (!r && wave) r = load_field(h, aux, h->host[0] + p.host_field_bytes, p.coded);
+    if (!r && wave) r = load_field(h, vel, h->host[2], p.ro_coded);
+    if (r) {
+      h->broken = r == OC_ERR_HIP;
+      return r;
+    }
+    if (p.in.c0_field) par_bytes(h->host[2], aux, (size_t)p.host_aux_bytes);
+    h->loaded = true;
+    h->time_index = 0;
+    return OC_OK;
+  } catch (...) {
+    if (h) h->broken = true;
+    return OC_ERR_HOST;
   }
-  if (p.in.c0_field) par_bytes(h->host[2], aux, (size_t)p.host_aux_bytes);
-  h->loaded = true;
-  h->time_index = 0;
-  return OC_OK;
 }
 
 namespace {
@@ -730,21 +781,31 @@ int run_steps(oc_handle *h, int64_t steps, const oc::CkptOut *ck) {
 }  // namespace
 
 int oc_run(oc_handle *h, int64_t steps) {
-  if (!h || steps < 0) return OC_ERR_ARG;
-  if (h->broken || !h->loaded) return OC_ERR_STATE;
-  if (steps == 0) return OC_OK;
-  return run_steps(h, steps, nullptr);
+  try {
+    if (!h || steps < 0) return OC_ERR_ARG;
+    if (h->broken || !h->loaded) return OC_ERR_STATE;
+    if (steps == 0) return OC_OK;
+    return run_steps(h, steps, nullptr);
+  } catch (...) {
+    if (h) h->broken = true;
+    return OC_ERR_HOST;
+  }
 }
 
 int oc_store(oc_handle *h, float *u, float *aux) {
-  if (!h || (!u && !aux)) return OC_ERR_ARG;
-  if (h->broken || !h->loaded) return OC_ERR_STATE;
-  const oc::Plan &p = h->plan;
-  int r = OC_OK;
-  if (u) r = store_field(h, h->host[h->cur], u, p.coded);
-  if (!r && aux && p.in.kind == oc::KIND_WAVE25)
-    r = store_field(h, h->host[h->cur] + p.host_field_bytes, aux, p.coded);
-  return r;
+  try {
+    if (!h || (!u && !aux)) return OC_ERR_ARG;
+    if (h->broken || !h->loaded) return OC_ERR_STATE;
+    const oc::Plan &p = h->plan;
+    int r = OC_OK;
+    if (u) r = store_field(h, h->host[h->cur], u, p.coded);
+    if (!r && aux && p.in.kind == oc::KIND_WAVE25)
+      r = store_field(h, h->host[h->cur] + p.host_field_bytes, aux, p.coded);
+    return r;
+  } catch (...) {
+    if (h) h->broken = true;
+    return OC_ERR_HOST;
+  }
 }
 
 // ---- adjoint ------------------------------------------------------------
@@ -794,237 +855,287 @@ size_t adj_work_bytes(const oc::AdjPlan &a, size_t *off) {
 
 size_t oc_adjoint_host_bytes(const oc_handle *h, int64_t steps, int32_t ckpt_every,
                              int32_t ckpt_rate_bits) {
-  if (!h) return 0;
-  oc::AdjPlan a;
-  if (adj_plan_for(h, steps, ckpt_every, ckpt_rate_bits, &a) != OC_OK) return 0;
-  size_t off[4];
-  return adj_work_bytes(a, off);
+  try {
+    if (!h) return 0;
+    oc::AdjPlan a;
+    if (adj_plan_for(h, steps, ckpt_every, ckpt_rate_bits, &a) != OC_OK) return 0;
+    size_t off[4];
+    return adj_work_bytes(a, off);
+  } catch (...) {
+    return 0;
+  }
 }
 
 int oc_forward_ckpt(oc_handle *h, int64_t steps, int32_t ckpt_every, int32_t ckpt_rate_bits,
                     void *host_work, size_t host_work_bytes) {
-  if (!h || !host_work) return OC_ERR_ARG;
-  if (h->broken || !h->loaded) return OC_ERR_STATE;
-  oc::AdjPlan a;
-  int r = adj_plan_for(h, steps, ckpt_every, ckpt_rate_bits, &a);
-  if (r != OC_OK) return r;
-  size_t off[4];
-  if (adj_work_bytes(a, off) > host_work_bytes) return OC_ERR_BUDGET;
-  h->ckpt_valid = false;
-  uint8_t *work = (uint8_t *)host_work;
-  // Checkpoint sg + 1 is written by the last sweep of segment sg itself
-  // (codes made from the slab results on the device) where the plan allows;
-  // otherwise, and for u_0, it is made from the host level between segments.
-  const bool in_pipe = oc::ckpt_out_supported(h->plan, a.ckpt_rate);
-  uint8_t *const saved = h->host[oc::HOST_CKPT], *const saved_dev = h->host_dev[oc::HOST_CKPT];
-  h->host[oc::HOST_CKPT] = work + off[0];
-  h->host_dev[oc::HOST_CKPT] = mapped_host(work + off[0]);
-  for (int sg = 0; sg < a.nseg && r == OC_OK; sg++) {
-    if (sg == 0 || !in_pipe) {
-      uint8_t *dst = work + off[0] + a.ckpt_off[(size_t)sg];
-      const float *cur = (const float *)h->host[h->cur];
-      if (a.ckpt_coded[(size_t)sg]) {
-        // codes made on the GPU through the adjoint plan's two slots' buffers
-        uint8_t *const wbuf[2] = {h->arena + a.off_buf[0][oc::A_U0], h->arena + a.off_buf[1][oc::A_U0]};
-        uint8_t *const sbuf[2] = {h->arena + a.off_cstage[0], h->arena + a.off_cstage[1]};
-        r = encode_field(h, cur, dst, a.ckpt_rate, std::max<int64_t>(4, a.g.P / 4 * 4), wbuf, sbuf);
-      } else {
-        par_bytes(dst, cur, a.field_bytes);
+  try {
+    if (!h || !host_work) return OC_ERR_ARG;
+    if (h->broken || !h->loaded) return OC_ERR_STATE;
+    oc::AdjPlan a;
+    int r = adj_plan_for(h, steps, ckpt_every, ckpt_rate_bits, &a);
+    if (r != OC_OK) return r;
+    size_t off[4];
+    if (adj_work_bytes(a, off) > host_work_bytes) return OC_ERR_BUDGET;
+    h->ckpt_valid = false;
+    uint8_t *work = (uint8_t *)host_work;
+    // Checkpoint sg + 1 is written by the last sweep of segment sg itself
+    // (codes made from the slab results on the device) where the plan allows;
+    // otherwise, and for u_0, it is made from the host level between segments.
+    const bool in_pipe = oc::ckpt_out_supported(h->plan, a.ckpt_rate);
+    uint8_t *const saved = h->host[oc::HOST_CKPT], *const saved_dev = h->host_dev[oc::HOST_CKPT];
+    h->host[oc::HOST_CKPT] = work + off[0];
+    h->host_dev[oc::HOST_CKPT] = mapped_host(work + off[0]);
+    for (int sg = 0; sg < a.nseg && r == OC_OK; sg++) {
+      if (sg == 0 || !in_pipe) {
+        uint8_t *dst = work + off[0] + a.ckpt_off[(size_t)sg];
+        const float *cur = (const float *)h->host[h->cur];
+        if (a.ckpt_coded[(size_t)sg]) {
+          // codes made on the GPU through the adjoint plan's two slots' buffers
+          uint8_t *const wbuf[2] = {h->arena + a.off_buf[0][oc::A_U0], h->arena + a.off_buf[1][oc::A_U0]};
+          uint8_t *const sbuf[2] = {h->arena + a.off_cstage[0], h->arena + a.off_cstage[1]};
+          r = encode_field(h, cur, dst, a.ckpt_rate, std::max<int64_t>(4, a.g.P / 4 * 4), wbuf, sbuf);
+        } else {
+          par_bytes(dst, cur, a.field_bytes);
+        }
+        if (r) {
+          h->broken = r == OC_ERR_HIP;
+          break;
+        }
       }
-      if (r) {
-        h->broken = r == OC_ERR_HIP;
-        break;
+      const int64_t len = std::min<int64_t>(ckpt_every, steps - (int64_t)sg * ckpt_every);
+      oc::CkptOut ck;
+      const bool next = in_pipe && sg + 1 < a.nseg;
+      if (next) {
+        ck.rate = a.ckpt_coded[(size_t)sg + 1] ? a.ckpt_rate : 0;
+        ck.host_off = a.ckpt_off[(size_t)sg + 1];
       }
+      r = run_steps(h, len, next ? &ck : nullptr);
+      if (!r && next && ck.rate > 0) r = codec_check_and_clear();
     }
-    const int64_t len = std::min<int64_t>(ckpt_every, steps - (int64_t)sg * ckpt_every);
-    oc::CkptOut ck;
-    const bool next = in_pipe && sg + 1 < a.nseg;
-    if (next) {
-      ck.rate = a.ckpt_coded[(size_t)sg + 1] ? a.ckpt_rate : 0;
-      ck.host_off = a.ckpt_off[(size_t)sg + 1];
-    }
-    r = run_steps(h, len, next ? &ck : nullptr);
-    if (!r && next && ck.rate > 0) r = codec_check_and_clear();
+    h->host[oc::HOST_CKPT] = saved;
+    h->host_dev[oc::HOST_CKPT] = saved_dev;
+    if (r) return r;
+    h->adj = a;
+    h->adj_work = work;
+    std::memcpy(h->adj_off, off, sizeof off);
+    h->ckpt_valid = true;
+    return OC_OK;
+  } catch (...) {
+    if (h) h->broken = true;
+    return OC_ERR_HOST;
   }
-  h->host[oc::HOST_CKPT] = saved;
-  h->host_dev[oc::HOST_CKPT] = saved_dev;
-  if (r) return r;
-  h->adj = a;
-  h->adj_work = work;
-  std::memcpy(h->adj_off, off, sizeof off);
-  h->ckpt_valid = true;
-  return OC_OK;
 }
 
 int oc_adjoint(oc_handle *h, const float *gT, float *g_u0, float *g_c0) {
-  if (!h || !gT || !g_u0) return OC_ERR_ARG;
-  if (h->broken) return OC_ERR_STATE;
-  if (!h->ckpt_valid) return OC_ERR_STATE;
-  const oc::AdjPlan &a = h->adj;
-  uint8_t *w = h->adj_work;
-  uint8_t *lam0 = w + h->adj_off[1], *lam1 = w + h->adj_off[2], *grad = w + h->adj_off[3];
-  // (the gradient store is not cleared: the first reverse sweep starts each
-  // slab's accumulator at zero on the device and writes the whole store)
-  par_bytes(lam0, gT, a.field_bytes);
-  // map the host stores of the reverse sweeps, run them, restore the handle's
-  uint8_t *saved[oc::kHostStores], *saved_dev[oc::kHostStores];
-  std::memcpy(saved, h->host, sizeof saved);
-  std::memcpy(saved_dev, h->host_dev, sizeof saved_dev);
-  h->host[0] = lam0;
-  h->host[1] = lam1;
-  h->host[oc::HOST_CKPT] = w + h->adj_off[0];
-  h->host[oc::HOST_GRAD] = grad;
-  for (int i : {0, 1, (int)oc::HOST_CKPT, (int)oc::HOST_GRAD}) h->host_dev[i] = mapped_host(h->host[i]);
-  const int er = ensure_events(h, (size_t)oc::EventIds{(int)a.g.slabs.size()}.count());
-  if (er) {
+  try {
+    if (!h || !gT || !g_u0) return OC_ERR_ARG;
+    if (h->broken) return OC_ERR_STATE;
+    if (!h->ckpt_valid) return OC_ERR_STATE;
+    const oc::AdjPlan &a = h->adj;
+    uint8_t *w = h->adj_work;
+    uint8_t *lam0 = w + h->adj_off[1], *lam1 = w + h->adj_off[2], *grad = w + h->adj_off[3];
+    // (the gradient store is not cleared: the first reverse sweep starts each
+    // slab's accumulator at zero on the device and writes the whole store)
+    par_bytes(lam0, gT, a.field_bytes);
+    // map the host stores of the reverse sweeps, run them, restore the handle's
+    uint8_t *saved[oc::kHostStores], *saved_dev[oc::kHostStores];
+    std::memcpy(saved, h->host, sizeof saved);
+    std::memcpy(saved_dev, h->host_dev, sizeof saved_dev);
+    h->host[0] = lam0;
+    h->host[1] = lam1;
+    h->host[oc::HOST_CKPT] = w + h->adj_off[0];
+    h->host[oc::HOST_GRAD] = grad;
+    for (int i : {0, 1, (int)oc::HOST_CKPT, (int)oc::HOST_GRAD}) h->host_dev[i] = mapped_host(h->host[i]);
+    const int er = ensure_events(h, (size_t)oc::EventIds{(int)a.g.slabs.size()}.count());
+    if (er) {
+      std::memcpy(h->host, saved, sizeof saved);
+      std::memcpy(h->host_dev, saved_dev, sizeof saved_dev);
+      return er;
+    }
+    std::vector<oc::Op> ops;
+    oc::build_adjoint_ops(a, 0, &ops);
+    auto t0 = std::chrono::steady_clock::now();
+    int r = issue(h, ops, a.g);
+    auto t1 = std::chrono::steady_clock::now();
     std::memcpy(h->host, saved, sizeof saved);
     std::memcpy(h->host_dev, saved_dev, sizeof saved_dev);
-    return er;
+    if (r) return r;
+    if (a.ckpt_rate > 0) {
+      int cr = codec_check_and_clear();
+      if (cr) return cr;
+    }
+    h->stats.wall_s = std::chrono::duration<double>(t1 - t0).count();
+    h->stats.n_ops = ops.size();
+    par_bytes(g_u0, (a.nseg & 1) ? lam1 : lam0, a.field_bytes);
+    if (g_c0) par_bytes(g_c0, grad, a.field_bytes);
+    return OC_OK;
+  } catch (...) {
+    if (h) h->broken = true;
+    return OC_ERR_HOST;
   }
-  std::vector<oc::Op> ops;
-  oc::build_adjoint_ops(a, 0, &ops);
-  auto t0 = std::chrono::steady_clock::now();
-  int r = issue(h, ops, a.g);
-  auto t1 = std::chrono::steady_clock::now();
-  std::memcpy(h->host, saved, sizeof saved);
-  std::memcpy(h->host_dev, saved_dev, sizeof saved_dev);
-  if (r) return r;
-  if (a.ckpt_rate > 0) {
-    int cr = codec_check_and_clear();
-    if (cr) return cr;
-  }
-  h->stats.wall_s = std::chrono::duration<double>(t1 - t0).count();
-  h->stats.n_ops = ops.size();
-  par_bytes(g_u0, (a.nseg & 1) ? lam1 : lam0, a.field_bytes);
-  if (g_c0) par_bytes(g_c0, grad, a.field_bytes);
-  return OC_OK;
 }
 
 int64_t oc_debug_check_adjoint(const oc_grid *g, const oc_stencil *st, const oc_config *cfg,
                                int64_t steps, int32_t ckpt_every, int32_t ckpt_rate_bits,
                                int32_t mutate, int64_t i) {
-  if (!grid_ok(g) || !st || !cfg) return OC_ERR_ARG;
-  oc::PlanInput in = plan_input(g, st, cfg);
-  in.rate = ckpt_rate_bits;
-  in.slab_planes = cfg->slab_planes;
-  oc::AdjPlan a;
-  int r = oc::make_adj_plan(in, ckpt_every, steps, &a);
-  if (r != oc::ST_OK) return r;
-  std::vector<oc::Op> ops;
-  oc::build_adjoint_ops(a, 0, &ops);
-  if (mutate == 1) {
-    int64_t seen = 0;
-    bool dropped = false;
-    for (size_t j = 0; j < ops.size(); j++)
-      if (ops[j].type == oc::OP_WAIT && seen++ == i) {
-        ops.erase(ops.begin() + (ptrdiff_t)j);
-        dropped = true;
-        break;
-      }
-    if (!dropped) return OC_ERR_ARG;
-  } else if (mutate != 0) {
-    return OC_ERR_ARG;
+  try {
+    if (!grid_ok(g) || !st || !cfg) return OC_ERR_ARG;
+    oc::PlanInput in = plan_input(g, st, cfg);
+    in.rate = ckpt_rate_bits;
+    in.slab_planes = cfg->slab_planes;
+    oc::AdjPlan a;
+    int r = oc::make_adj_plan(in, ckpt_every, steps, &a);
+    if (r != oc::ST_OK) return r;
+    std::vector<oc::Op> ops;
+    oc::build_adjoint_ops(a, 0, &ops);
+    if (mutate == 1) {
+      int64_t seen = 0;
+      bool dropped = false;
+      for (size_t j = 0; j < ops.size(); j++)
+        if (ops[j].type == oc::OP_WAIT && seen++ == i) {
+          ops.erase(ops.begin() + (ptrdiff_t)j);
+          dropped = true;
+          break;
+        }
+      if (!dropped) return OC_ERR_ARG;
+    } else if (mutate != 0) {
+      return OC_ERR_ARG;
+    }
+    std::string why;
+    int64_t bad = oc::check_ops(a.g, ops, &why);
+    if (bad && getenv("OC_CHECK_VERBOSE")) fprintf(stderr, "oc adjoint check: %s\n", why.c_str());
+    if (mutate == 0 && i == -1) {
+      int64_t w = 0;
+      for (const auto &o : ops) w += o.type == oc::OP_WAIT;
+      return w;   // number of waits (for the mutation sweep)
+    }
+    return bad;
+  } catch (...) {
+    return OC_ERR_HOST;
   }
-  std::string why;
-  int64_t bad = oc::check_ops(a.g, ops, &why);
-  if (bad && getenv("OC_CHECK_VERBOSE")) fprintf(stderr, "oc adjoint check: %s\n", why.c_str());
-  if (mutate == 0 && i == -1) {
-    int64_t w = 0;
-    for (const auto &o : ops) w += o.type == oc::OP_WAIT;
-    return w;   // number of waits (for the mutation sweep)
-  }
-  return bad;
 }
 
 int64_t oc_debug_timeline(const oc_handle *h, int32_t *kind, int64_t *slab, double *start_ms,
                           double *end_ms, int64_t cap) {
-  if (!h) return OC_ERR_ARG;
-  const int64_t n = (int64_t)h->last_timed.size();
-  if (!kind || !slab || !start_ms || !end_ms || cap <= 0) return n;
-  if (h->broken || n == 0) return n == 0 ? 0 : OC_ERR_STATE;
-  const hipEvent_t base = h->tev[h->last_timed[0].ev];
-  const int64_t m = std::min(n, cap);
-  for (int64_t i = 0; i < m; i++) {
-    const auto &t = h->last_timed[(size_t)i];
-    float a = 0.f, b = 0.f;
-    if (hipEventElapsedTime(&a, base, h->tev[t.ev]) != hipSuccess ||
-        hipEventElapsedTime(&b, base, h->tev[t.ev + 1]) != hipSuccess)
-      return OC_ERR_HIP;
-    kind[i] = t.kind;
-    slab[i] = t.slab;
-    start_ms[i] = a;
-    end_ms[i] = b;
+  try {
+    if (!h) return OC_ERR_ARG;
+    const int64_t n = (int64_t)h->last_timed.size();
+    if (!kind || !slab || !start_ms || !end_ms || cap <= 0) return n;
+    if (h->broken || n == 0) return n == 0 ? 0 : OC_ERR_STATE;
+    const hipEvent_t base = h->tev[h->last_timed[0].ev];
+    const int64_t m = std::min(n, cap);
+    for (int64_t i = 0; i < m; i++) {
+      const auto &t = h->last_timed[(size_t)i];
+      float a = 0.f, b = 0.f;
+      if (hipEventElapsedTime(&a, base, h->tev[t.ev]) != hipSuccess ||
+          hipEventElapsedTime(&b, base, h->tev[t.ev + 1]) != hipSuccess)
+        return OC_ERR_HIP;
+      kind[i] = t.kind;
+      slab[i] = t.slab;
+      start_ms[i] = a;
+      end_ms[i] = b;
+    }
+    return m;
+  } catch (...) {
+    return OC_ERR_HOST;
   }
-  return m;
 }
 
 int oc_stats_get(const oc_handle *h, oc_stats *s) {
-  if (!h || !s) return OC_ERR_ARG;
-  *s = h->stats;
-  return OC_OK;
+  try {
+    if (!h || !s) return OC_ERR_ARG;
+    *s = h->stats;
+    return OC_OK;
+  } catch (...) {
+    return OC_ERR_HOST;
+  }
 }
 
 int oc_set_timing(oc_handle *h, int32_t on) {
-  if (!h) return OC_ERR_ARG;
-  h->timing = on != 0;
-  return OC_OK;
+  try {
+    if (!h) return OC_ERR_ARG;
+    h->timing = on != 0;
+    return OC_OK;
+  } catch (...) {
+    return OC_ERR_HOST;
+  }
 }
 
 int oc_destroy(oc_handle *h) {
-  if (!h) return OC_ERR_ARG;
-  drain(h);
-  for (auto &e : h->ev)
-    if (e) (void)hipEventDestroy(e);
-  for (auto &e : h->tev)
-    if (e) (void)hipEventDestroy(e);
-  delete h;
-  return OC_OK;
+  try {
+    if (!h) return OC_ERR_ARG;
+    drain(h);
+    for (auto &e : h->ev)
+      if (e) (void)hipEventDestroy(e);
+    for (auto &e : h->tev)
+      if (e) (void)hipEventDestroy(e);
+    delete h;
+    return OC_OK;
+  } catch (...) {
+    return OC_ERR_HOST;
+  }
 }
 
 int oc_debug_fail_after(oc_handle *h, int64_t n) {
-  if (!h) return OC_ERR_ARG;
-  h->fail_after = n >= 1 ? n : -1;
-  h->hip_calls = 0;
-  return OC_OK;
+  try {
+    if (!h) return OC_ERR_ARG;
+    h->fail_after = n >= 1 ? n : -1;
+    h->hip_calls = 0;
+    return OC_OK;
+  } catch (...) {
+    return OC_ERR_HOST;
+  }
 }
 
 int oc_debug_serialize(oc_handle *h, int32_t on) {
-  if (!h) return OC_ERR_ARG;
-  h->serialize = on != 0;
-  return OC_OK;
+  try {
+    if (!h) return OC_ERR_ARG;
+    h->serialize = on != 0;
+    return OC_OK;
+  } catch (...) {
+    return OC_ERR_HOST;
+  }
 }
 
 int64_t oc_debug_plan_ops(const oc_grid *g, const oc_stencil *st, const oc_config *cfg,
                           int64_t sweeps, int64_t *n_waits) {
-  if (!grid_ok(g) || !st || !cfg || sweeps < 1) return OC_ERR_ARG;
-  oc::Plan p;
-  int r = oc::make_plan(plan_input(g, st, cfg), &p);
-  if (r != oc::ST_OK) return r;
-  std::vector<oc::Op> ops;
-  oc::build_ops(p, sweeps, p.in.k, 0, 0, &ops);
-  if (n_waits) {
-    int64_t w = 0;
-    for (const auto &o : ops) w += o.type == oc::OP_WAIT;
-    *n_waits = w;
+  try {
+    if (!grid_ok(g) || !st || !cfg || sweeps < 1) return OC_ERR_ARG;
+    oc::Plan p;
+    int r = oc::make_plan(plan_input(g, st, cfg), &p);
+    if (r != oc::ST_OK) return r;
+    std::vector<oc::Op> ops;
+    oc::build_ops(p, sweeps, p.in.k, 0, 0, &ops);
+    if (n_waits) {
+      int64_t w = 0;
+      for (const auto &o : ops) w += o.type == oc::OP_WAIT;
+      *n_waits = w;
+    }
+    return (int64_t)ops.size();
+  } catch (...) {
+    return OC_ERR_HOST;
   }
-  return (int64_t)ops.size();
 }
 
 int64_t oc_debug_plan_dump(const oc_grid *g, const oc_stencil *st, const oc_config *cfg,
                            int64_t sweeps, char *buf, size_t len) {
-  if (!grid_ok(g) || !st || !cfg || sweeps < 1) return OC_ERR_ARG;
-  oc::Plan p;
-  int r = oc::make_plan(plan_input(g, st, cfg), &p);
-  if (r != oc::ST_OK) return r;
-  std::vector<oc::Op> ops;
-  oc::build_ops(p, sweeps, p.in.k, 0, 0, &ops);
-  std::string s = oc::dump_ops(ops);
-  if (buf && len) {
-    size_t n = std::min(len - 1, s.size());
-    std::memcpy(buf, s.data(), n);
-    buf[n] = 0;
+  try {
+    if (!grid_ok(g) || !st || !cfg || sweeps < 1) return OC_ERR_ARG;
+    oc::Plan p;
+    int r = oc::make_plan(plan_input(g, st, cfg), &p);
+    if (r != oc::ST_OK) return r;
+    std::vector<oc::Op> ops;
+    oc::build_ops(p, sweeps, p.in.k, 0, 0, &ops);
+    std::string s = oc::dump_ops(ops);
+    if (buf && len) {
+      size_t n = std::min(len - 1, s.size());
+      std::memcpy(buf, s.data(), n);
+      buf[n] = 0;
+    }
+    return (int64_t)s.size() + 1;
+  } catch (...) {
+    return OC_ERR_HOST;
   }
-  return (int64_t)s.size() + 1;
 }
 
 namespace {
@@ -1091,13 +1202,21 @@ int64_t check_plan_impl(const oc_grid *g, const oc_stencil *st, const oc_config 
 
 int64_t oc_debug_check_plan(const oc_grid *g, const oc_stencil *st, const oc_config *cfg,
                             int64_t sweeps, int32_t mutate, int64_t i) {
-  return check_plan_impl(g, st, cfg, sweeps, -1, mutate, i);
+  try {
+    return check_plan_impl(g, st, cfg, sweeps, -1, mutate, i);
+  } catch (...) {
+    return OC_ERR_HOST;
+  }
 }
 
 int64_t oc_debug_check_plan_ckpt(const oc_grid *g, const oc_stencil *st, const oc_config *cfg,
                                  int64_t sweeps, int32_t ckpt_rate_bits, int32_t mutate, int64_t i) {
-  if (ckpt_rate_bits < 0) return OC_ERR_ARG;
-  return check_plan_impl(g, st, cfg, sweeps, ckpt_rate_bits, mutate, i);
+  try {
+    if (ckpt_rate_bits < 0) return OC_ERR_ARG;
+    return check_plan_impl(g, st, cfg, sweeps, ckpt_rate_bits, mutate, i);
+  } catch (...) {
+    return OC_ERR_HOST;
+  }
 }
 
 }  // extern "C"

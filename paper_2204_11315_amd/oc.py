@@ -16,7 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liboc.so")
 
 OC_OK, OC_ERR_ARG, OC_ERR_SHAPE, OC_ERR_BUDGET = 0, -1, -2, -3
-OC_ERR_HIP, OC_ERR_NONFINITE, OC_ERR_STATE, OC_ERR_UNSUPPORTED = -4, -5, -6, -7
+OC_ERR_HIP, OC_ERR_NONFINITE, OC_ERR_STATE, OC_ERR_UNSUPPORTED, OC_ERR_HOST = -4, -5, -6, -7, -8
 OC_STAR7, OC_WAVE25 = 1, 2
 
 C_CONFIG1 = (0.4, 0.1, 0.1, 0.1, 0.1, 0.1, 0.1)
