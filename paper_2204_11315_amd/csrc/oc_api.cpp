@@ -450,27 +450,44 @@ int load_field(oc_handle *h, const float *src, uint8_t *dst, bool coded) {
   return encode_field(h, src, dst, p.in.rate, std::max<int64_t>(4, p.P / 4 * 4), work, stage);
 }
 
+// Host store `src` back to a host FP32 field: a copy, or the codes decoded on
+// the GPU, double-buffered over the three streams like encode_field (codes in,
+// decode, field out) through the plan's first two working and staging buffers.
 int store_field(oc_handle *h, const uint8_t *src, float *dst, bool coded) {
   const oc::Plan &p = h->plan;
-  Exec x{h};
-  hipStream_t s = h->s[0];
   const size_t pb = p.plane_bytes;
   if (!coded) {
     par_bytes(dst, src, pb * (size_t)p.in.nz);
     return OC_OK;
   }
+  Exec x{h};
   const int64_t chunk = std::max<int64_t>(4, p.P / 4 * 4);
-  uint8_t *work = h->arena + p.off_work[0][0];
-  uint8_t *stage = h->arena + p.off_stage[0];
-  for (int64_t z = 0; z < p.in.nz; z += chunk) {
-    int64_t n = std::min<int64_t>(chunk, p.in.nz - z);
-    x.ok(hipMemcpyAsync(stage, src + (size_t)(z / 4) * p.layer_bytes, (size_t)(n / 4) * p.layer_bytes,
-                        hipMemcpyHostToDevice, s));
-    x.ok(oc::launch_decode(stage, p.in.nx, p.in.ny, n / 4, p.in.rate, (float *)work, s));
-    x.ok(hipMemcpyAsync((uint8_t *)dst + (size_t)z * pb, work, (size_t)n * pb, hipMemcpyDeviceToHost, s));
-    x.ok(hipStreamSynchronize(s));
-    if (x.st) break;
+  uint8_t *const work[2] = {h->arena + p.off_work[0][0],
+                            h->arena + (p.n_work_sets == 1 ? p.off_work[0][1] : p.off_work[1][0])};
+  uint8_t *const stage[2] = {h->arena + p.off_stage[0], h->arena + p.off_stage[1]};
+  hipEvent_t ev[6] = {};   // per buffer pair: codes in, decoded, copied out
+  for (auto &e : ev)
+    if (!x.ok(hipEventCreateWithFlags(&e, hipEventDisableTiming))) break;
+  int64_t c = 0;
+  for (int64_t z = 0; z < p.in.nz && x.st == OC_OK; z += chunk, c++) {
+    const int b = (int)(c & 1);
+    const int64_t n = std::min<int64_t>(chunk, p.in.nz - z);
+    if (c >= 2) x.ok(hipStreamWaitEvent(h->s[0], ev[3 * b + 2], 0));   // pair b copied out
+    x.ok(hipMemcpyAsync(stage[b], src + (size_t)(z / 4) * p.layer_bytes, (size_t)(n / 4) * p.layer_bytes,
+                        hipMemcpyHostToDevice, h->s[0]));
+    x.ok(hipEventRecord(ev[3 * b], h->s[0]));
+    x.ok(hipStreamWaitEvent(h->s[1], ev[3 * b], 0));
+    x.ok(oc::launch_decode(stage[b], p.in.nx, p.in.ny, n / 4, p.in.rate, (float *)work[b], h->s[1]));
+    x.ok(hipEventRecord(ev[3 * b + 1], h->s[1]));
+    x.ok(hipStreamWaitEvent(h->s[2], ev[3 * b + 1], 0));
+    x.ok(hipMemcpyAsync((uint8_t *)dst + (size_t)z * pb, work[b], (size_t)n * pb,
+                        hipMemcpyDeviceToHost, h->s[2]));
+    x.ok(hipEventRecord(ev[3 * b + 2], h->s[2]));
   }
+  // drain every stream (also after an error: the buffers must be idle)
+  for (int i = 0; i < 3; i++) (void)hipStreamSynchronize(h->s[i]);
+  for (auto &e : ev)
+    if (e) (void)hipEventDestroy(e);
   return x.st;
 }
 
