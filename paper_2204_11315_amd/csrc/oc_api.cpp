@@ -63,9 +63,10 @@ struct oc_handle {
 namespace {
 
 // Large host copies and fills split over a few threads (one thread moves ~10
-// GB/s; whole fields are GiBs).  Small sizes stay on the calling thread.
+// GB/s; whole fields are GiBs, staged chunks tens of MiB).  Below 16 MiB the
+// calling thread does it alone.
 void par_bytes(void *dst, const void *src, size_t n) {   // src == nullptr: fill with zeros
-  const size_t kMin = 64u << 20;
+  const size_t kMin = 8u << 20;
   unsigned t = std::min<unsigned>(8u, std::max(1u, std::thread::hardware_concurrency()));
   if (n < 2 * kMin || t < 2) {
     if (src) std::memcpy(dst, src, n);
@@ -395,17 +396,30 @@ bool grid_ok(const oc_grid *g) {
          g->nz <= (1 << 30);
 }
 
+// A free pinned host region that can stage a caller's pageable field: the
+// host level that holds no state (none when one level is updated in place),
+// if it fits two chunks of `chunk` planes; else nullptr.
+uint8_t *bounce_region(const oc_handle *h, int free_level, int64_t chunk) {
+  const oc::Plan &p = h->plan;
+  if (p.in_place || !h->host[free_level]) return nullptr;
+  const size_t need = 2u * (size_t)chunk * p.plane_bytes;
+  return h->cfg.host_level_bytes >= need ? h->host[free_level] : nullptr;
+}
+
 // Encodes a whole host FP32 field into host codes at `rate`, in chunks of
 // `chunk` planes, double-buffered through two device buffer pairs (raw
 // `work[i]`, codes `stage[i]`): the copy-in of a chunk (stream 0) overlaps the
-// encode (stream 1) and copy-back (stream 2) of the one before.  Returns when
-// the codes are on the host.
+// encode (stream 1) and copy-back (stream 2) of the one before.  With a pinned
+// `bounce` region (two chunks), each chunk is first copied there by host
+// threads while the previous one crosses the link (pageable sources copy in
+// far slower than pinned ones).  Returns when the codes are on the host.
 int encode_field(oc_handle *h, const float *src, uint8_t *dst, int rate, int64_t chunk,
-                 uint8_t *const work[2], uint8_t *const stage[2]) {
+                 uint8_t *const work[2], uint8_t *const stage[2], uint8_t *bounce = nullptr) {
   const oc::Plan &p = h->plan;
   Exec x{h};
   const size_t pb = p.plane_bytes;
   const size_t layer = oc::coded_layer_bytes(p.in.nx, p.in.ny, rate);
+  const size_t half = (size_t)chunk * pb;
   hipEvent_t ev[6] = {};   // per buffer pair: copied in, encoded, copied back
   for (auto &e : ev)
     if (!x.ok(hipEventCreateWithFlags(&e, hipEventDisableTiming))) break;
@@ -414,8 +428,14 @@ int encode_field(oc_handle *h, const float *src, uint8_t *dst, int rate, int64_t
     const int b = (int)(c & 1);
     const int64_t n = std::min<int64_t>(chunk, p.in.nz - z);
     if (c >= 2) x.ok(hipStreamWaitEvent(h->s[0], ev[3 * b + 2], 0));   // pair b copied back
-    x.ok(hipMemcpyAsync(work[b], (const uint8_t *)src + (size_t)z * pb, (size_t)n * pb,
-                        hipMemcpyHostToDevice, h->s[0]));
+    const uint8_t *from = (const uint8_t *)src + (size_t)z * pb;
+    if (bounce && x.st == OC_OK) {
+      // half b was last read by the copy-in of chunk c - 2
+      if (c >= 2 && !x.ok(hipEventSynchronize(ev[3 * b]))) break;
+      par_bytes(bounce + b * half, from, (size_t)n * pb);
+      from = bounce + b * half;
+    }
+    x.ok(hipMemcpyAsync(work[b], from, (size_t)n * pb, hipMemcpyHostToDevice, h->s[0]));
     x.ok(hipEventRecord(ev[3 * b], h->s[0]));
     x.ok(hipStreamWaitEvent(h->s[1], ev[3 * b], 0));
     x.ok(oc::launch_encode((const float *)work[b], p.in.nx, p.in.ny, n / 4, rate, stage[b], h->s[1]));
@@ -447,12 +467,16 @@ int load_field(oc_handle *h, const float *src, uint8_t *dst, bool coded) {
   uint8_t *const work[2] = {h->arena + p.off_work[0][0],
                             h->arena + (p.n_work_sets == 1 ? p.off_work[0][1] : p.off_work[1][0])};
   uint8_t *const stage[2] = {h->arena + p.off_stage[0], h->arena + p.off_stage[1]};
-  return encode_field(h, src, dst, p.in.rate, std::max<int64_t>(4, p.P / 4 * 4), work, stage);
+  const int64_t chunk = std::max<int64_t>(4, p.P / 4 * 4);
+  // level 0 receives the codes; level 1 holds nothing yet
+  return encode_field(h, src, dst, p.in.rate, chunk, work, stage, bounce_region(h, 1, chunk));
 }
 
 // Host store `src` back to a host FP32 field: a copy, or the codes decoded on
 // the GPU, double-buffered over the three streams like encode_field (codes in,
 // decode, field out) through the plan's first two working and staging buffers.
+// With a free pinned level, each chunk lands there and host threads move it to
+// `dst` while the next one is decoded and copied out.
 int store_field(oc_handle *h, const uint8_t *src, float *dst, bool coded) {
   const oc::Plan &p = h->plan;
   const size_t pb = p.plane_bytes;
@@ -465,10 +489,18 @@ int store_field(oc_handle *h, const uint8_t *src, float *dst, bool coded) {
   uint8_t *const work[2] = {h->arena + p.off_work[0][0],
                             h->arena + (p.n_work_sets == 1 ? p.off_work[0][1] : p.off_work[1][0])};
   uint8_t *const stage[2] = {h->arena + p.off_stage[0], h->arena + p.off_stage[1]};
+  uint8_t *const bounce = bounce_region(h, 1 - h->cur, chunk);
+  const size_t half = (size_t)chunk * pb;
   hipEvent_t ev[6] = {};   // per buffer pair: codes in, decoded, copied out
   for (auto &e : ev)
     if (!x.ok(hipEventCreateWithFlags(&e, hipEventDisableTiming))) break;
-  int64_t c = 0;
+  // moves chunk c (planes [z, z + n)) from its bounce half to dst once copied out
+  auto drain = [&](int64_t c, int64_t z, int64_t n) {
+    const int b = (int)(c & 1);
+    if (x.ok(hipEventSynchronize(ev[3 * b + 2])))
+      par_bytes((uint8_t *)dst + (size_t)z * pb, bounce + b * half, (size_t)n * pb);
+  };
+  int64_t c = 0, zp = 0, np = 0;   // the chunk before c
   for (int64_t z = 0; z < p.in.nz && x.st == OC_OK; z += chunk, c++) {
     const int b = (int)(c & 1);
     const int64_t n = std::min<int64_t>(chunk, p.in.nz - z);
@@ -480,10 +512,16 @@ int store_field(oc_handle *h, const uint8_t *src, float *dst, bool coded) {
     x.ok(oc::launch_decode(stage[b], p.in.nx, p.in.ny, n / 4, p.in.rate, (float *)work[b], h->s[1]));
     x.ok(hipEventRecord(ev[3 * b + 1], h->s[1]));
     x.ok(hipStreamWaitEvent(h->s[2], ev[3 * b + 1], 0));
-    x.ok(hipMemcpyAsync((uint8_t *)dst + (size_t)z * pb, work[b], (size_t)n * pb,
-                        hipMemcpyDeviceToHost, h->s[2]));
+    uint8_t *to = bounce ? bounce + b * half : (uint8_t *)dst + (size_t)z * pb;
+    x.ok(hipMemcpyAsync(to, work[b], (size_t)n * pb, hipMemcpyDeviceToHost, h->s[2]));
     x.ok(hipEventRecord(ev[3 * b + 2], h->s[2]));
+    // the previous chunk's half is written to again only by chunk c + 1,
+    // which is queued after this returns
+    if (bounce && c >= 1 && x.st == OC_OK) drain(c - 1, zp, np);
+    zp = z;
+    np = n;
   }
+  if (bounce && c >= 1 && x.st == OC_OK) drain(c - 1, zp, np);
   // drain every stream (also after an error: the buffers must be idle)
   for (int i = 0; i < 3; i++) (void)hipStreamSynchronize(h->s[i]);
   for (auto &e : ev)

@@ -280,3 +280,27 @@ def test_degenerate_grids_equal_incore(shape, kw):
     else:
         want = gpu_compressed_incore(u0, R, kw["k"], steps)
     assert np.array_equal(got.view(np.uint32), want.view(np.uint32))
+
+
+@pytest.mark.parametrize("in_place", [False, True])
+def test_load_store_stage_through_the_free_level(in_place):
+    # nz = 132 (8 chunks of 16 planes + a ragged 4), S = 8, k = 1, R = 16: a
+    # host level holds two chunks, so load and store stage the caller's
+    # pageable field through the level that holds no state; with in_place
+    # there is none and the copies go direct.  Both must be exact.
+    shape = (132, 32, 32)
+    u0 = inputs.grf_field(shape, seed=12)
+    o = oc.OutOfCore(shape, C, k=1, rate=16, slab_planes=8, budget=64 << 20, in_place=in_place)
+    try:
+        o.load(u0)
+        got0 = o.store()
+        o.run(3)
+        got3 = o.store()
+        got3b = o.store()
+    finally:
+        o.close()
+    want0 = oracle.decompress(oracle.compress(u0, 16), shape, 16)
+    assert np.array_equal(got0.view(np.uint32), want0.view(np.uint32))
+    want3 = gpu_compressed_incore(u0, 16, 1, 3)
+    assert np.array_equal(got3.view(np.uint32), want3.view(np.uint32))
+    assert np.array_equal(got3b.view(np.uint32), want3.view(np.uint32))
