@@ -155,7 +155,9 @@ int oc_create(const oc_grid *g, const oc_stencil *st, const oc_config *cfg, oc_h
  *   STAR7:  u = field, aux = c0 field when c0_is_field (else NULL);
  *   WAVE25: u = p^0, aux = p^{-1}, vel = velocity (m/s).
  * With compression on, the fields are encoded on the GPU (the host keeps only
- * codes).  Synchronous. */
+ * codes); the host level that holds no state (with two levels) then serves as
+ * pinned staging for the caller's arrays and its contents are overwritten.
+ * Synchronous. */
 int oc_load(oc_handle *h, const float *u, const float *aux, const float *vel);
 
 /* Advances the loaded state by `steps` time steps in sweeps of k steps (the
@@ -166,7 +168,9 @@ int oc_load(oc_handle *h, const float *u, const float *aux, const float *vel);
 int oc_run(oc_handle *h, int64_t steps);
 
 /* Copies the current state out (decoding on the GPU when compressed):
- *   STAR7: u; WAVE25: u = p^n, aux = p^{n-1} (either may be NULL). */
+ *   STAR7: u; WAVE25: u = p^n, aux = p^{n-1} (either may be NULL).
+ * With compression on and two host levels, the level not holding the current
+ * state serves as pinned staging (overwritten).  Synchronous. */
 int oc_store(oc_handle *h, float *u, float *aux);
 
 int oc_stats_get(const oc_handle *h, oc_stats *s);
