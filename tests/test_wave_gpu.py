@@ -129,3 +129,28 @@ def test_ooc_split_runs_keep_source_time():
         finally:
             o.close()
     assert np.array_equal(outs[0].view(np.uint32), outs[1].view(np.uint32))
+
+
+def _misaligned(a):
+    # the same values one float past a 16-byte boundary: the launch then takes
+    # the one-x-per-lane kernel even when nx % 4 == 0
+    buf = torch.empty(a.size + 1, dtype=torch.float32, device="cuda")
+    v = buf[1:].view(a.shape)
+    v.copy_(torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)))
+    return v
+
+
+@pytest.mark.parametrize("shape,src", [(SHAPE, SRC), ((12, 6, 264), (260, 3, 6)), ((9, 5, 516), (257, 2, 4))])
+def test_four_x_kernel_equals_one_x_kernel_bitwise(shape, src):
+    vel = inputs.layered_velocity(shape, seed=4)
+    dt = 0.4 * H / float(vel.max())
+    st = oc.make_wave25(H, dt, src, F, T0)
+    p0 = (inputs.modes_field(shape, seed=32, noise=0.0) * 1e-3).astype(np.float32)
+    pm1 = (p0 * 0.999).astype(np.float32)
+    for steps in (1, 6):
+        wp, wc = oc.wave25_incore(_dev(pm1), _dev(p0), _dev(vel), st, 0, steps)
+        mp, mc = oc.wave25_incore(_misaligned(pm1), _misaligned(p0), _misaligned(vel), st, 0, steps)
+        assert np.array_equal(wc.cpu().numpy().view(np.uint32), mc.cpu().numpy().view(np.uint32))
+        assert np.array_equal(wp.cpu().numpy().view(np.uint32), mp.cpu().numpy().view(np.uint32))
+    rp, rc = oracle.wave25_run(pm1, p0, vel, H, dt, src, F, T0, 0, 6)
+    assert rel_l2(wc.cpu().numpy(), rc) < 2e-5
