@@ -392,7 +392,7 @@ def wave_workload(args):
 
 def incore_workload(args):
     """In-core 7-point steps on one device field (config 1 and a larger grid
-    for the HBM roofline).  Config 1: 64^3, 8 steps, seeded modes + noise,
+    for the HBM roofline), and the 25-point wave step on one wave slab.  Config 1: 64^3, 8 steps, seeded modes + noise,
     against the FP64 oracle (rel-L2 <= 1e-5); at 64^3 (1 MiB, L2-resident) a
     launch is latency-bound.  512^3 (512 MiB, more than the 256 MiB MALL): the
     single-step kernel and the four-step fused kernel, timed with HIP events
@@ -454,6 +454,38 @@ def incore_workload(args):
     ms = ev[0].elapsed_time(ev[1]) / 16
     out["device copy"] = {"ms": ms, "gbs": 8.0 * cells / (ms * 1e-3) / 1e9}
     log("in-core 512^3 plain device copy of the same bytes: %.3f ms, %.0f GB/s" % (ms, out["device copy"]["gbs"]))
+    del big, dst
+    # the 25-point wave step on the wave job's slab shape (144 planes of 1024^2):
+    # the four-x-per-lane kernel (float4 rows, 16-byte aligned buffers) and the
+    # one-x kernel (the same buffers one float off alignment); 16 algorithmic
+    # bytes per cell update (p^n, p^(n-1), velocity in; p^(n+1) out)
+    wshape = (144, 1024, 1024)
+    wcells = float(np.prod(wshape))
+    vel = torch.full(wshape, 3000.0, device="cuda")
+    wst = oc.make_wave25(10.0, 0.4 * 10.0 / 4500.0, (512, 512, 72), 15.0, 1.0 / 15.0)
+    p0 = torch.from_numpy(inputs.modes_field(wshape, seed=5) * 1e-3).cuda()
+
+    def offset(t):   # same values, one float past a 16-byte boundary
+        buf = torch.empty(t.numel() + 1, dtype=torch.float32, device="cuda")
+        v = buf[1:].view(t.shape)
+        v.copy_(t)
+        return v
+
+    for name, fields in (("wave25 four x per lane", (p0.clone(), p0.clone(), vel)),
+                         ("wave25 one x per lane", (offset(p0), offset(p0), offset(vel)))):
+        a, b, v = fields
+        oc.wave25_incore(a, b, v, wst, 0, 2)
+        torch.cuda.synchronize()
+        ev[0].record()
+        oc.wave25_incore(a, b, v, wst, 0, 20)
+        ev[1].record()
+        torch.cuda.synchronize()
+        ms = ev[0].elapsed_time(ev[1]) / 20
+        gbs = 16.0 * wcells / (ms * 1e-3) / 1e9
+        out[name] = {"ms_per_step": ms, "shape": list(wshape), "alg_hbm_gbs": gbs,
+                     "hbm_frac": gbs / HBM_PEAK_GBS}
+        log("in-core 1024x1024x144 %s: %.3f ms per step, %.0f GB/s (%.0f %% of HBM)" % (
+            name, ms, gbs, 100 * gbs / HBM_PEAK_GBS))
     one = out["single step"]
     res = {"metric": "in-core 7-point GCell-updates/s (HBM roofline)", "value": one["gcell_per_s"],
            "unit": "GCell-updates/s", "n_gpus": 1, "steps": 32, "warmup": args.warmup,
