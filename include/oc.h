@@ -71,7 +71,8 @@ typedef struct {
   void *dev_arena;         /* device memory the library carves all buffers from             */
   size_t dev_budget;       /* its size in bytes; the plan must fit                          */
   oc_stream streams[3];    /* three caller-owned streams of default priority               */
-  void *host_level[2];     /* two host buffers of >= oc_host_level_bytes() bytes each;
+  void *host_level[2];     /* two disjoint host buffers of >= oc_host_level_bytes() bytes
+                              each (OC_ERR_ARG if they overlap; [1] unused with in_place);
                               pinned (hipHostMalloc / torch pin_memory) for overlap         */
   size_t host_level_bytes; /* size of each host level buffer                               */
   void *host_aux;          /* host buffer of >= oc_host_aux_bytes() bytes for the read-only

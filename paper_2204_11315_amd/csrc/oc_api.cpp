@@ -733,6 +733,11 @@ int oc_create(const oc_grid *g, const oc_stencil *st, const oc_config *cfg, oc_h
     if (!cfg->host_level[0] || (!p.in_place && !cfg->host_level[1]) ||
         cfg->host_level_bytes < p.host_level_bytes)
       return OC_ERR_BUDGET;
+    if (!p.in_place) {   // two levels: each sweep reads one and writes the other
+      const uintptr_t a = (uintptr_t)cfg->host_level[0], b = (uintptr_t)cfg->host_level[1];
+      const uintptr_t n = (uintptr_t)p.host_level_bytes;
+      if (a < b + n && b < a + n) return OC_ERR_ARG;
+    }
     if (p.host_aux_bytes && (!cfg->host_aux || cfg->host_aux_bytes < p.host_aux_bytes))
       return OC_ERR_BUDGET;
     for (int i = 0; i < 3; i++)

@@ -304,3 +304,20 @@ def test_load_store_stage_through_the_free_level(in_place):
     want3 = gpu_compressed_incore(u0, 16, 1, 3)
     assert np.array_equal(got3.view(np.uint32), want3.view(np.uint32))
     assert np.array_equal(got3b.view(np.uint32), want3.view(np.uint32))
+
+
+def test_overlapping_host_levels_are_rejected():
+    # each sweep reads one level and writes the other (and load / store stage
+    # through the stateless one): levels that overlap cannot work
+    import ctypes
+    o = oc.OutOfCore(SHAPE, k=2, rate=16, slab_planes=8, budget=64 << 20)
+    try:
+        cfg = o.cfg
+        h = ctypes.c_void_p()
+        for second in (cfg.host_level[0], cfg.host_level[0] + 64):
+            bad = oc.Config.from_buffer_copy(cfg)
+            bad.host_level[1] = second
+            st = oc.lib().oc_create(oc._ref(o.grid), oc._ref(o.stencil), oc._ref(bad), ctypes.byref(h))
+            assert st == oc.OC_ERR_ARG
+    finally:
+        o.close()
