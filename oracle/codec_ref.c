@@ -207,6 +207,10 @@ static void decode_planes(uint32_t *u, int *low, bitr_t *r) {
         low[n] = p;
         n++;
         if (b) break;
+        /* a run that passes the last coefficient without its closing 1 is
+         * never written by the encoder; such a stream ends here, as if the
+         * budget had cut it */
+        if (n == 64) return;
       }
     }
     for (int q = n; q < 64; q++) low[q] = p;   /* closed by a group bit 0 (or n == 64) */

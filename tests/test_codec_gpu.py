@@ -73,6 +73,19 @@ def test_gpu_decode_matches_cpu_values(shape, R):
         assert np.array_equal(got.view(np.uint32), want.view(np.uint32)), (name, R)
 
 
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("R", [1, 8, 13, 32])
+def test_gpu_decode_of_arbitrary_bytes_matches_cpu(shape, R):
+    # every byte string of the right length decodes: exponents up to 255 (so
+    # infinities), group-test tokens and runs cut anywhere, streams no encoder
+    # writes; the two decoders must still agree on every bit
+    rng = np.random.default_rng(300 + R)
+    codes = rng.integers(0, 256, size=oracle.codec_bytes(shape[2], shape[1], shape[0], R), dtype=np.uint8)
+    want = oracle.decompress(codes, shape, R)
+    got = oc.decompress(_dev(codes), shape, R).cpu().numpy()
+    assert np.array_equal(got.view(np.uint32), want.view(np.uint32)), R
+
+
 def test_round_trip_error_budget_r16():
     f = inputs.grf_field((32, 32, 32), seed=7)
     g = oc.decompress(oc.compress(_dev(f), 16), f.shape, 16).cpu().numpy()

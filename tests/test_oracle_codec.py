@@ -374,3 +374,31 @@ def test_thread_count_does_not_change_codes():
         oracle.set_threads(prev)
     assert np.array_equal(one, ref)
     assert np.array_equal(dec1.view(np.uint32), oracle.decompress(ref, f.shape, 9).view(np.uint32))
+
+
+def test_run_past_the_last_coefficient_ends_the_stream():
+    """A group bit 1 whose run reaches past coefficient 63 without a closing 1
+    is never written by the encoder; the format ends the stream there (as a
+    budget cut would): whatever follows is ignored, and the digits read up to
+    that point decode as usual."""
+    R = 4
+    perm = oracle.sequency_order()
+    rng = np.random.default_rng(77)
+    eb = 150
+    head = [(eb >> b) & 1 for b in range(8)]
+    # (a) plane 31: group bit 1, then 64 zeros: no coefficient is significant
+    # (b) plane 31: group 1, digit 1 (coefficient 0), group 1, then 63 zeros
+    for body, sig in (([1] + [0] * 64, False), ([1, 1, 1] + [0] * 63, True)):
+        outs = []
+        for _ in range(3):
+            bits = np.array(head + body, dtype=np.uint8)
+            tail = rng.integers(0, 2, size=64 * R - bits.size, dtype=np.uint8)
+            slot = np.packbits(np.concatenate([bits, tail]), bitorder="little")
+            outs.append(oracle.block_decode(slot, R))
+        for o in outs[1:]:
+            assert np.array_equal(o.view(np.uint32), outs[0].view(np.uint32))
+        c = np.zeros(64, dtype=np.int32)
+        if sig:
+            c[perm[0]] = oracle.from_negabinary(1 << 31) + oracle.unread_mean(31)
+        want = np.ldexp(oracle.inv_xform(c).astype(np.float32), eb - 153).astype(np.float32)
+        assert np.array_equal(outs[0].view(np.uint32), want.view(np.uint32))
