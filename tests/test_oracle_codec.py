@@ -402,3 +402,23 @@ def test_run_past_the_last_coefficient_ends_the_stream():
             c[perm[0]] = oracle.from_negabinary(1 << 31) + oracle.unread_mean(31)
         want = np.ldexp(oracle.inv_xform(c).astype(np.float32), eb - 153).astype(np.float32)
         assert np.array_equal(outs[0].view(np.uint32), want.view(np.uint32))
+
+
+@pytest.mark.parametrize("R", [1, 3, 8, 17, 32])
+def test_any_byte_string_decodes_deterministically(R):
+    # streams no encoder writes (random bytes) still decode: the same bits on
+    # every call, no NaN (values are integers times a power of two, so at
+    # worst infinite), and equal to a block-by-block decode of the same slots
+    rng = np.random.default_rng(900 + R)
+    shape = (8, 8, 12)
+    codes = rng.integers(0, 256, size=oracle.codec_bytes(12, 8, 8, R), dtype=np.uint8)
+    a = oracle.decompress(codes, shape, R)
+    b = oracle.decompress(codes.copy(), shape, R)
+    assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+    assert not np.isnan(a).any()
+    nbx, nby = 3, 2
+    for blk in range(nbx * nby * 2):
+        bx, by, bz = blk % nbx, (blk // nbx) % nby, blk // (nbx * nby)
+        v = oracle.block_decode(codes[blk * 8 * R:(blk + 1) * 8 * R], R).reshape(4, 4, 4)
+        got = a[4 * bz:4 * bz + 4, 4 * by:4 * by + 4, 4 * bx:4 * bx + 4]
+        assert np.array_equal(got.view(np.uint32), v.view(np.uint32))
