@@ -190,6 +190,11 @@ size_t oc_codec_bytes(int64_t nx, int64_t ny, int64_t nz, int32_t rate_bits);
  * codes 4-byte aligned (as device allocations are); else OC_ERR_ARG. */
 int oc_codec_compress(const float *d_in, int64_t nx, int64_t ny, int64_t nz, int32_t rate_bits,
                       void *d_out, size_t out_bytes, oc_stream stream);
+/* Enqueues decompression of the codes d_in into d_out [nz][ny][nx] FP32 on
+ * `stream` (same alignment rules).  Every byte string of oc_codec_bytes()
+ * bytes decodes, streams no encoder writes included: a block's stream ends at
+ * its budget or where a run passes its last coefficient; large exponents give
+ * infinities, never NaN. */
 int oc_codec_decompress(const void *d_in, int64_t nx, int64_t ny, int64_t nz, int32_t rate_bits,
                         float *d_out, oc_stream stream);
 /* Synchronizes `stream` and returns OC_ERR_NONFINITE if any compression since
