@@ -87,3 +87,33 @@ def test_degenerate_shapes_vs_fp64(shape, steps):
     got = oc.star7_incore(_dev(u0), c, steps).cpu().numpy()
     want = oracle.star7_run(u0, c, steps)
     assert np.abs(got - want).max() <= 1e-6 * max(1.0, np.abs(want).max())
+
+
+def _misaligned(t):
+    # the same values one float past a 16-byte boundary: single steps then
+    # take the one-x-per-lane kernel even when nx % 4 == 0
+    buf = torch.empty(t.numel() + 1, dtype=torch.float32, device="cuda")
+    v = buf[1:].view(t.shape)
+    v.copy_(t)
+    return v
+
+
+@pytest.mark.parametrize("shape", [(21, 37, 260), (6, 9, 516)])
+def test_four_x_single_steps_equal_one_x_and_fused_bitwise(shape):
+    # nx % 4 == 0 and aligned: single steps run four x per lane (DPP neighbours,
+    # 256 x per wave, ragged last wave); the one-x kernel and the fused kernel
+    # must give the same bits
+    rng = np.random.default_rng(6)
+    u0 = rng.standard_normal(shape).astype(np.float32)
+    c = (0.3, 0.05, 0.15, 0.07, 0.13, 0.11, 0.09)
+    c0 = _dev(inputs.c0_field(shape))
+    for field in (None, c0):
+        a, b = _dev(u0), _misaligned(_dev(u0))
+        fb = None if field is None else _misaligned(field)
+        for _ in range(3):
+            a = oc.star7_incore(a, c, 1, c0f=field)
+            b = _misaligned(oc.star7_incore(b, c, 1, c0f=fb))
+        fused = oc.star7_incore(_dev(u0), c, 3, c0f=field).cpu().numpy()
+        a, b = a.cpu().numpy(), b.cpu().numpy()
+        assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+        assert np.array_equal(a.view(np.uint32), fused.view(np.uint32))
