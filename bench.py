@@ -591,8 +591,8 @@ def main():
     ap.add_argument("--fd-dirs", type=int, default=32)
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU; the multi-GPU z-sharding is a design "
-              "note only (--gpus %d requested)" % args.gpus, file=sys.stderr)
+        print("bench.py runs on one GPU: sharding the z-slabs over several GPUs is not "
+              "implemented (--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
     import torch
