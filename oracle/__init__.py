@@ -18,7 +18,8 @@ Out-of-Core GPU Stencil Computation"):
   composition: the data lives compressed on the host, each residency decodes,
   runs k steps and encodes again (Sec. 1, Sec. 4.2, Algorithm 1).  The slab
   decomposition does not enter: blocks are coded independently and halos are
-  whole blocks.
+  whole blocks.  Pinned by the closed form of block-constant fields under a
+  diagonal-only stencil (exact codec, one FP32 rounding per residency).
 """
 from __future__ import annotations
 
