@@ -107,6 +107,20 @@ typedef struct {
                               otherwise oc_create returns OC_ERR_ARG.  A run that fails
                               mid-sweep leaves that level partly updated.  0 = two levels
                               that alternate as source and destination                      */
+  float error_budget;      /* > 0: the codec rate is chosen per error budget (7-point stencil;
+                              else OC_ERR_UNSUPPORTED): oc_load runs the job's own process,
+                              error_steps steps in residencies of k steps, each residency
+                              decoding, stepping and re-encoding, on a z-sample of the loaded
+                              field (whole xy planes, up to 64 planes from the middle of the
+                              grid, zero beyond the sample) at candidate rates on the device,
+                              beside the same steps uncompressed in FP32, and keeps the
+                              smallest rate in 1..rate_bits whose relative L2 error is within
+                              the budget (binary search: the error is taken to fall as the rate
+                              rises).  rate_bits is then the largest rate allowed: host levels
+                              and the arena are sized for it.  If no rate meets the budget,
+                              rate_bits is used.  oc_stats reports the rate and the pilot's
+                              error.  0 = the fixed rate rate_bits (Sec. 5)                  */
+  int32_t error_steps;     /* the job length the budget is for (>= 1 with error_budget > 0)   */
 } oc_config;
 
 typedef struct {
@@ -130,6 +144,11 @@ typedef struct {
    * (including the copy-back kernel), host<->device copy calls, event record /
    * wait calls, and the final stream synchronisation (always measured)     */
   double host_ms_kernels, host_ms_copies, host_ms_events, host_ms_sync;
+  int64_t rate_bits;       /* codec rate in use (0 = uncompressed); with an error budget, the
+                              rate oc_load chose                                           */
+  double pilot_rel_l2;     /* error budget: relative L2 error of the pilot at that rate       */
+  int64_t pilot_planes;    /* error budget: planes of the z-sample the pilot ran on          */
+  int64_t pilot_runs;      /* error budget: rates the last oc_load tried                     */
 } oc_stats;
 
 /* Bytes one host level needs for this grid / stencil / rate (raw FP32 planes,
@@ -201,6 +220,20 @@ int oc_codec_decompress(const void *d_in, int64_t nx, int64_t ny, int64_t nz, in
  * the last call met a non-finite value (and clears the flag), else OC_OK. */
 int oc_codec_status(oc_stream stream);
 
+/* Error of one codec round trip at rate_bits (Sec. 5: the error a fixed rate
+ * costs), measured on the device without writing codes: every 4x4x4 block of
+ * the FP32 field d_in [nz][ny][nx] (16-byte aligned, dims multiples of 4) is
+ * encoded and decoded by one lane, and d_out (device, 3 doubles, 8-byte
+ * aligned) receives sum (dec - in)^2, sum in^2 (FP64) and max |dec - in|.
+ * Sums are taken in a fixed order (the same inputs give the same bits).
+ * d_work: device scratch of >= oc_codec_error_work_bytes() bytes, 8-byte
+ * aligned, owned by the caller.  Enqueued on `stream` (returns after the
+ * enqueue); non-finite inputs set the flag oc_codec_status reports (the sums
+ * are then meaningless). */
+size_t oc_codec_error_work_bytes(int64_t nx, int64_t ny, int64_t nz, int32_t rate_bits);
+int oc_codec_error(const float *d_in, int64_t nx, int64_t ny, int64_t nz, int32_t rate_bits,
+                   void *d_work, size_t work_bytes, double *d_out, oc_stream stream);
+
 /* ---- adjoint (differentiation of the 7-point path, raw handles) ---------- */
 /* For u_T = A(c0)^T u_0 (A = the 7-point update with per-cell c0 when the
  * stencil has a c0 field), the gradients of a loss L(u_T) given dL/du_T:
@@ -223,7 +256,9 @@ size_t oc_adjoint_host_bytes(const oc_handle *h, int64_t steps, int32_t ckpt_eve
                              int32_t ckpt_rate_bits);
 int oc_forward_ckpt(oc_handle *h, int64_t steps, int32_t ckpt_every, int32_t ckpt_rate_bits,
                     void *host_work, size_t host_work_bytes);
-/* gT, g_u0, g_c0: host FP32 [nz][ny][nx]; g_c0 may be NULL. */
+/* gT, g_u0, g_c0: host FP32 [nz][ny][nx]; g_c0 may be NULL.  OC_ERR_STATE
+ * unless oc_forward_ckpt has completed since the last oc_load (a load replaces
+ * the state and the c0 field the checkpoints were taken from). */
 int oc_adjoint(oc_handle *h, const float *gT, float *g_u0, float *g_c0);
 
 /* ---- single-field device kernels (in-core building blocks) -------------- */
@@ -286,6 +321,15 @@ int64_t oc_debug_check_adjoint(const oc_grid *g, const oc_stencil *st, const oc_
 /* Operations in that list; *n_waits receives the number of stream waits. */
 int64_t oc_debug_plan_ops(const oc_grid *g, const oc_stencil *st, const oc_config *cfg,
                           int64_t sweeps, int64_t *n_waits);
+
+/* Enqueues on `stream` the copy-back kernel oc_run uses (copy_back > 0):
+ * `workgroups` workgroups copy `bytes` from device memory at dev_src to byte
+ * host_off of the pinned, mapped host allocation that starts at host_base
+ * (OC_ERR_ARG if host_base is not the start of such memory; the caller keeps
+ * host_off + bytes within it).  Returns after the enqueue.  Tuning aid: the
+ * host-link probe measures this kernel's rate beside host-to-device DMA. */
+int oc_debug_copy_to_host(void *host_base, size_t host_off, const void *dev_src, size_t bytes,
+                          int32_t workgroups, oc_stream stream);
 
 /* GPU timeline of the last oc_run (timing on): for each timed op, its class
  * (0 decode, 1 stencil, 2 encode, 3 host-to-device, 4 device-to-host), its

@@ -23,6 +23,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "oc_kernels.h"
 
 // Sticky per-device error word: bit 0 = a non-finite value was met by the
@@ -277,21 +279,13 @@ __device__ __forceinline__ uint32_t lds_index(uint32_t i, int nw, uint32_t magic
 extern __shared__ uint32_t lds_slots[];
 
 // ---- encoder ------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_encode(const float *__restrict__ in, int64_t nx, int64_t ny,
-                                                int64_t nbx, int64_t nby, int64_t nblocks, int R,
-                                                uint32_t *__restrict__ out) {
+// Codes the block whose first value is at `base` (rows of 4 floats, row pitch
+// nx, plane pitch nx*ny) into the lane's own LDS slot `my` of 2R + 1 zeroed
+// dwords; returns true if the block holds an infinity or NaN.
+__device__ __forceinline__ bool encode_block(const float *__restrict__ base, int64_t nx, int64_t ny,
+                                             int R, uint32_t *my) {
   const int NW = 2 * R;        // dwords per slot
   const int BITS = 64 * R;     // slot bits
-  const int64_t b0 = (int64_t)blockIdx.x * blockDim.x;
-  const int64_t b = b0 + threadIdx.x;
-  const int nslots = (int)min<int64_t>(blockDim.x, nblocks - b0);
-  uint32_t *my = lds_slots + threadIdx.x * (NW + 1);
-  for (int i = 0; i <= NW; i++) my[i] = 0u;   // own slot (+ pad); the writer only ORs in order
-  if (b < nblocks) {
-  const int64_t bx = b % nbx;
-  const int64_t by = (b / nbx) % nby;
-  const int64_t bz = b / (nbx * nby);
-  const float *base = in + ((4 * bz) * ny + 4 * by) * nx + 4 * bx;
 
   // load and take the block apart into sign / exponent / mantissa
   uint32_t raw[64];
@@ -312,7 +306,6 @@ __global__ __launch_bounds__(256) void k_encode(const float *__restrict__ in, in
   for (int t = 0; t < 64; t++) emax = max(emax, raw[t] & 0x7F800000u);
   const bool bad = emax == 0x7F800000u;   // an infinity or NaN in the block
   const uint32_t Eb = max(emax >> 23, 1u);
-  if (bad) atomicOr(&g_oc_codec_err, 1);
   int32_t q[64];
 #pragma unroll
   for (int t = 0; t < 64; t++) {
@@ -391,6 +384,24 @@ __global__ __launch_bounds__(256) void k_encode(const float *__restrict__ in, in
     }
   }
   w.flush();
+  return bad;
+}
+
+__global__ __launch_bounds__(256) void k_encode(const float *__restrict__ in, int64_t nx, int64_t ny,
+                                                int64_t nbx, int64_t nby, int64_t nblocks, int R,
+                                                uint32_t *__restrict__ out) {
+  const int NW = 2 * R;        // dwords per slot
+  const int64_t b0 = (int64_t)blockIdx.x * blockDim.x;
+  const int64_t b = b0 + threadIdx.x;
+  const int nslots = (int)min<int64_t>(blockDim.x, nblocks - b0);
+  uint32_t *my = lds_slots + threadIdx.x * (NW + 1);
+  for (int i = 0; i <= NW; i++) my[i] = 0u;   // own slot (+ pad); the writer only ORs in order
+  if (b < nblocks) {
+    const int64_t bx = b % nbx;
+    const int64_t by = (b / nbx) % nby;
+    const int64_t bz = b / (nbx * nby);
+    if (encode_block(in + ((4 * bz) * ny + 4 * by) * nx + 4 * bx, nx, ny, R, my))
+      atomicOr(&g_oc_codec_err, 1);
   }
   __syncthreads();
   // coalesced copy of the workgroup's slots to global memory
@@ -400,27 +411,123 @@ __global__ __launch_bounds__(256) void k_encode(const float *__restrict__ in, in
   for (uint32_t i = threadIdx.x; i < total; i += blockDim.x) dst[i] = lds_slots[lds_index(i, NW, magic)];
 }
 
+// ---- workgroup sums of error statistics --------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+  return v;
+}
+// Sums se and sr and takes the maximum of mx over the workgroup (at most 1024
+// threads) in a fixed order; thread 0 writes the three results to dst.  Every
+// thread of the workgroup must call it.
+__device__ void block_sums(double se, double sr, double mx, double *dst) {
+  __shared__ double red[3][16];
+  se = wave_sum(se);
+  sr = wave_sum(sr);
+  mx = wave_max(mx);
+  const int w = (int)threadIdx.x >> 6, l = (int)threadIdx.x & 63;
+  if (l == 0) {
+    red[0][w] = se;
+    red[1][w] = sr;
+    red[2][w] = mx;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = 0.0, c = 0.0, m = 0.0;
+    for (int i = 0; i < ((int)blockDim.x + 63) >> 6; i++) {
+      a += red[0][i];
+      c += red[1][i];
+      m = fmax(m, red[2][i]);
+    }
+    dst[0] = a;
+    dst[1] = c;
+    dst[2] = m;
+  }
+}
+
+// Error statistics of x against the reference r over n values: per workgroup
+// (a fixed grid striding over the arrays) the sum of (x - r)^2, the sum of r^2
+// and the largest |x - r|, in FP64.  Needs n % 4 == 0 and 16-byte alignment.
+__global__ __launch_bounds__(256) void k_diff_err(const float4 *__restrict__ r, const float4 *__restrict__ x,
+                                                  int64_t n4, double *__restrict__ parts) {
+  double se = 0.0, sr = 0.0, mx = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += (int64_t)gridDim.x * blockDim.x) {
+    const float4 a = r[i], b = x[i];
+    const float ra[4] = {a.x, a.y, a.z, a.w}, xb[4] = {b.x, b.y, b.z, b.w};
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+      const double d = (double)xb[j] - (double)ra[j];
+      se += d * d;
+      sr += (double)ra[j] * (double)ra[j];
+      mx = fmax(mx, fabs(d));
+    }
+  }
+  block_sums(se, sr, mx, parts + 3 * (int64_t)blockIdx.x);
+}
+
+// One workgroup folds nparts triples (sum, sum, max) into out[3]: thread t
+// takes triples t, t + 256, ... in order, then the fixed-order workgroup sum.
+__global__ __launch_bounds__(256) void k_reduce_parts(const double *__restrict__ parts, int64_t nparts,
+                                                      double *__restrict__ out) {
+  double se = 0.0, sr = 0.0, mx = 0.0;
+  for (int64_t i = threadIdx.x; i < nparts; i += blockDim.x) {
+    se += parts[3 * i];
+    sr += parts[3 * i + 1];
+    mx = fmax(mx, parts[3 * i + 2]);
+  }
+  block_sums(se, sr, mx, out);
+}
+
 // ---- decoder ------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_decode(const uint32_t *__restrict__ in, int64_t nx, int64_t ny,
-                                                int64_t nbx, int64_t nby, int64_t nblocks, int R,
-                                                float *__restrict__ out) {
+// Per-workgroup error sums of a codec round trip: sum of squared errors, sum
+// of squared inputs (FP64) and the largest absolute error, of the blocks one
+// workgroup coded.
+struct ErrSums {
+  double *parts;   // [gridDim.x][3]
+};
+
+// One kernel body for two modes (kept as one function so that the decoder's
+// register allocation is that of a plain kernel):
+//  - decode (ROUNDTRIP = false): the workgroup's code slots are staged from
+//    `in` into LDS, decoded, and the values stored to `out`;
+//  - round trip (ROUNDTRIP = true): each lane encodes its block of the FP32
+//    field `field` into its LDS slot, decodes that slot, and compares the
+//    decoded values with the block's inputs; the workgroup's error sums go to
+//    `err` (no codes and no decoded values are written).
+template <bool ROUNDTRIP>
+__global__ __launch_bounds__(256) void k_decode_t(const uint32_t *__restrict__ in, const float *__restrict__ field,
+                                                  int64_t nx, int64_t ny, int64_t nbx, int64_t nby,
+                                                  int64_t nblocks, int R, float *__restrict__ out,
+                                                  ErrSums err) {
   const int NW = 2 * R;
   const int BITS = 64 * R;
   const int64_t b0 = (int64_t)blockIdx.x * blockDim.x;
   const int64_t b = b0 + threadIdx.x;
-  {
+  if (!ROUNDTRIP) {
     // coalesced copy of the workgroup's slots into LDS
     const int nslots = (int)min<int64_t>(blockDim.x, nblocks - b0);
     const uint32_t magic = div_magic(NW);
     const uint32_t *src = in + b0 * NW;
     const uint32_t total = (uint32_t)(nslots * NW);
     for (uint32_t i = threadIdx.x; i < total; i += blockDim.x) lds_slots[lds_index(i, NW, magic)] = src[i];
+    __syncthreads();
+    if (b >= nblocks) return;
   }
-  __syncthreads();
-  if (b >= nblocks) return;
   const int64_t bx = b % nbx;
   const int64_t by = (b / nbx) % nby;
   const int64_t bz = b / (nbx * nby);
+  if (ROUNDTRIP) {
+    uint32_t *my = lds_slots + threadIdx.x * (NW + 1);
+    for (int i = 0; i <= NW; i++) my[i] = 0u;
+    if (b < nblocks &&
+        encode_block(field + ((4 * bz) * ny + 4 * by) * nx + 4 * bx, nx, ny, R, my))
+      atomicOr(&g_oc_codec_err, 1);
+  }
 
   BitReader r;
   r.init(lds_slots + threadIdx.x * (NW + 1), NW);
@@ -516,19 +623,42 @@ __global__ __launch_bounds__(256) void k_decode(const uint32_t *__restrict__ in,
     q[kSeq.at[p + 32]] = (int32_t)((uint32_t)b + (uint32_t)mb);
   }
   xform_inv(q);
-  float *base = out + ((4 * bz) * ny + 4 * by) * nx + 4 * bx;
   const int e = Eb - 153;
+  if (!ROUNDTRIP) {
+    float *base = out + ((4 * bz) * ny + 4 * by) * nx + 4 * bx;
 #pragma unroll
-  for (int k = 0; k < 4; k++)
+    for (int k = 0; k < 4; k++)
 #pragma unroll
-    for (int j = 0; j < 4; j++) {
-      float4 v;
-      v.x = ldexpf((float)q[16 * k + 4 * j + 0], e);
-      v.y = ldexpf((float)q[16 * k + 4 * j + 1], e);
-      v.z = ldexpf((float)q[16 * k + 4 * j + 2], e);
-      v.w = ldexpf((float)q[16 * k + 4 * j + 3], e);
-      *reinterpret_cast<float4 *>(base + (k * ny + j) * nx) = v;
+      for (int j = 0; j < 4; j++) {
+        float4 v;
+        v.x = ldexpf((float)q[16 * k + 4 * j + 0], e);
+        v.y = ldexpf((float)q[16 * k + 4 * j + 1], e);
+        v.z = ldexpf((float)q[16 * k + 4 * j + 2], e);
+        v.w = ldexpf((float)q[16 * k + 4 * j + 3], e);
+        *reinterpret_cast<float4 *>(base + (k * ny + j) * nx) = v;
+      }
+  } else {
+    double se = 0.0, sr = 0.0, mx = 0.0;
+    if (b < nblocks) {
+      const float *base = field + ((4 * bz) * ny + 4 * by) * nx + 4 * bx;
+#pragma unroll
+      for (int k = 0; k < 4; k++)
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+          const float4 v = *reinterpret_cast<const float4 *>(base + (k * ny + j) * nx);
+          const float x[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+          for (int i = 0; i < 4; i++) {
+            const double r = (double)x[i];
+            const double d = (double)ldexpf((float)q[16 * k + 4 * j + i], e) - r;
+            se += d * d;
+            sr += r * r;
+            mx = fmax(mx, fabs(d));
+          }
+        }
     }
+    block_sums(se, sr, mx, err.parts + 3 * (int64_t)blockIdx.x);
+  }
 }
 
 // 256 lanes per workgroup (128 above 16 bits/value, to keep the slot staging
@@ -560,9 +690,41 @@ hipError_t launch_decode(const void *d_in, int64_t nx, int64_t ny, int64_t nlaye
   if (nb <= 0) return hipSuccess;
   const int threads = codec_threads(rate);
   dim3 grid((unsigned)((nb + threads - 1) / threads));
-  hipExtLaunchKernelGGL(k_decode, grid, dim3(threads), codec_lds_bytes(rate, threads), s, kt_start(kt),
-                        kt_stop(kt), 0,
-                     (const uint32_t *)d_in, nx, ny, nbx, nby, nb, rate, d_out);
+  hipExtLaunchKernelGGL(k_decode_t<false>, grid, dim3(threads), codec_lds_bytes(rate, threads), s,
+                        kt_start(kt), kt_stop(kt), 0, (const uint32_t *)d_in, (const float *)nullptr,
+                        nx, ny, nbx, nby, nb, rate, d_out, ErrSums{nullptr});
+  return hipGetLastError();
+}
+
+int64_t codec_error_parts(int64_t nx, int64_t ny, int64_t nlayers, int rate) {
+  if (rate < 1 || rate > 32) return 0;
+  const int64_t nb = (nx / 4) * (ny / 4) * nlayers;
+  const int threads = codec_threads(rate);
+  return (nb + threads - 1) / threads;
+}
+
+hipError_t launch_codec_error(const float *d_in, int64_t nx, int64_t ny, int64_t nlayers, int rate,
+                              double *parts, double *d_out3, hipStream_t s) {
+  if (rate < 1 || rate > 32) return hipErrorInvalidValue;
+  const int64_t nbx = nx / 4, nby = ny / 4, nb = nbx * nby * nlayers;
+  if (nb <= 0) return hipErrorInvalidValue;
+  const int threads = codec_threads(rate);
+  const int64_t nparts = codec_error_parts(nx, ny, nlayers, rate);
+  hipLaunchKernelGGL(k_decode_t<true>, dim3((unsigned)nparts), dim3(threads),
+                     codec_lds_bytes(rate, threads), s, (const uint32_t *)nullptr, d_in, nx, ny, nbx,
+                     nby, nb, rate, (float *)nullptr, ErrSums{parts});
+  hipLaunchKernelGGL(k_reduce_parts, dim3(1), dim3(256), 0, s, (const double *)parts, nparts, d_out3);
+  return hipGetLastError();
+}
+
+hipError_t launch_diff_error(const float *ref, const float *x, int64_t n, double *parts, double *d_out3,
+                             hipStream_t s) {
+  if (n <= 0 || n % 4 || (((uintptr_t)ref | (uintptr_t)x) & 15)) return hipErrorInvalidValue;
+  const int64_t n4 = n / 4;
+  const int64_t nparts = std::min<int64_t>(kDiffErrParts, (n4 + 255) / 256);
+  hipLaunchKernelGGL(k_diff_err, dim3((unsigned)nparts), dim3(256), 0, s, (const float4 *)ref,
+                     (const float4 *)x, n4, parts);
+  hipLaunchKernelGGL(k_reduce_parts, dim3(1), dim3(256), 0, s, (const double *)parts, nparts, d_out3);
   return hipGetLastError();
 }
 

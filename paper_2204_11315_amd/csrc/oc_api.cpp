@@ -58,6 +58,10 @@ struct oc_handle {
   // cached operation list
   std::vector<oc::Op> ops;
   int64_t ops_key[4] = {-1, -1, -1, -1};
+  // rate per error budget: the plan input at the largest rate (slab depth
+  // pinned), replanned at the rate each oc_load picks
+  bool auto_rate = false;
+  oc::PlanInput in_max;
 };
 
 namespace {
@@ -529,6 +533,139 @@ int store_field(oc_handle *h, const uint8_t *src, float *dst, bool coded) {
   return x.st;
 }
 
+// ---- codec rate per error budget ------------------------------------------
+// The job's own process (error_steps steps in residencies of k: decode, k
+// stencil steps, encode; the field encoded first and decoded last) runs on a
+// z-sample of the loaded field, whole xy planes, beside the same steps
+// uncompressed in FP32; the relative L2 difference at a rate is the pilot's
+// prediction of the job's error at that rate.  The sample is its own grid:
+// zero beyond its first and last plane.
+struct PilotLayout {
+  int64_t planes = 0;
+  size_t u0 = 0, ref = 0, x = 0, y = 0, c0 = 0, codes = 0, parts = 0, out = 0, need = 0;
+};
+
+PilotLayout pilot_layout(const oc::PlanInput &in, int64_t planes) {
+  auto up = [](size_t v) { return (v + 255) & ~(size_t)255; };
+  const size_t fb = up((size_t)planes * (size_t)in.nx * (size_t)in.ny * 4u);
+  PilotLayout L;
+  L.planes = planes;
+  size_t o = 0;
+  L.u0 = o, o += fb;
+  L.ref = o, o += fb;
+  L.x = o, o += fb;
+  L.y = o, o += fb;
+  if (in.c0_field) L.c0 = o, o += fb;
+  L.codes = o, o += up((size_t)(planes / 4) * oc::coded_layer_bytes(in.nx, in.ny, in.rate));
+  L.parts = o, o += up((size_t)oc::kDiffErrParts * 3u * sizeof(double));
+  L.out = o, o += up(3u * sizeof(double));
+  L.need = o;
+  return L;
+}
+
+constexpr int64_t kPilotMaxPlanes = 64;
+
+// Picks the rate for the field u (c0f: the c0 field, or nullptr), replans the
+// handle at that rate and records the choice in its stats.
+int pick_rate(oc_handle *h, const float *u, const float *c0f) {
+  const oc::PlanInput &in = h->in_max;
+  const int rmax = in.rate;
+  const int64_t nx = in.nx, ny = in.ny, nz = in.nz;
+  int64_t planes = std::min<int64_t>(kPilotMaxPlanes, nz / 4 * 4);
+  while (planes >= 4 && pilot_layout(in, planes).need > h->cfg.dev_budget) planes -= 4;
+  if (planes < 4) return OC_ERR_BUDGET;
+  const PilotLayout L = pilot_layout(in, planes);
+  const size_t pb = (size_t)nx * (size_t)ny * 4u;
+  const int64_t z0 = (nz - planes) / 2 / 4 * 4;
+  uint8_t *A = h->arena;
+  float *U0 = (float *)(A + L.u0), *RF = (float *)(A + L.ref), *X = (float *)(A + L.x),
+        *Y = (float *)(A + L.y);
+  const float *C0 = c0f ? (const float *)(A + L.c0) : nullptr;
+  uint8_t *CD = A + L.codes;
+  double *parts = (double *)(A + L.parts), *dout = (double *)(A + L.out);
+  hipStream_t s = h->s[1];
+  Exec x{h};
+  x.ok(hipMemcpyAsync(U0, (const uint8_t *)u + (size_t)z0 * pb, (size_t)planes * pb, hipMemcpyHostToDevice, s));
+  if (c0f)
+    x.ok(hipMemcpyAsync(A + L.c0, (const uint8_t *)c0f + (size_t)z0 * pb, (size_t)planes * pb,
+                        hipMemcpyHostToDevice, s));
+  const oc::Star7Coef c = coef_of(h->st);
+  // n steps from src, alternating between a and b (a != src); the result's buffer
+  auto steps_on = [&](const float *src, int64_t n, float *a, float *b) {
+    const float *cur = src;
+    float *dst = a;
+    while (n > 0 && x.st == OC_OK) {
+      const int lv = (int)std::min<int64_t>(n, oc::kMaxFusedSteps);
+      x.ok(oc::launch_star7_multi(cur, dst, C0, nx, ny, 0, planes, 0, planes, lv, c, s));
+      cur = dst;
+      dst = dst == a ? b : a;
+      n -= lv;
+    }
+    return cur;
+  };
+  const int64_t steps = h->cfg.error_steps, k = in.k;
+  const float *r = steps_on(U0, steps, X, Y);
+  x.ok(hipMemcpyAsync(RF, r, (size_t)planes * pb, hipMemcpyDeviceToDevice, s));
+  const int64_t layers = planes / 4;
+  std::vector<double> err((size_t)rmax + 1, -1.0);
+  int runs = 0;
+  auto run = [&](int R) -> double {
+    if (err[(size_t)R] >= 0.0) return err[(size_t)R];
+    x.ok(oc::launch_encode(U0, nx, ny, layers, R, CD, s));
+    for (int64_t done = 0; done < steps && x.st == OC_OK;) {
+      const int64_t n = std::min<int64_t>(k, steps - done);
+      x.ok(oc::launch_decode(CD, nx, ny, layers, R, X, s));
+      const float *res = steps_on(X, n, Y, X);
+      x.ok(oc::launch_encode(res, nx, ny, layers, R, CD, s));
+      done += n;
+    }
+    x.ok(oc::launch_decode(CD, nx, ny, layers, R, X, s));
+    x.ok(oc::launch_diff_error(RF, X, planes * nx * ny, parts, dout, s));
+    double sums[3] = {0.0, 0.0, 0.0};
+    x.ok(hipMemcpyAsync(sums, dout, sizeof sums, hipMemcpyDeviceToHost, s));
+    x.ok(hipStreamSynchronize(s));
+    runs++;
+    const double e = sums[1] > 0.0 ? std::sqrt(sums[0] / sums[1]) : (sums[0] > 0.0 ? HUGE_VAL : 0.0);
+    err[(size_t)R] = e;
+    return e;
+  };
+  // smallest rate within the budget, by bisection over 1..rmax
+  const double budget = (double)h->cfg.error_budget;
+  int best = -1;
+  for (int lo = 1, hi = rmax; lo <= hi && x.st == OC_OK;) {
+    const int mid = (lo + hi) / 2;
+    if (run(mid) <= budget) {
+      best = mid;
+      hi = mid - 1;
+    } else {
+      lo = mid + 1;
+    }
+  }
+  if (x.st != OC_OK) {
+    drain(h);
+    return x.st;
+  }
+  if (best < 0) best = rmax;
+  const double best_err = run(best);
+  if (x.st != OC_OK) return x.st;
+  const int cr = codec_check_and_clear();
+  if (cr) return cr;
+  oc::PlanInput pin = in;
+  pin.rate = best;
+  oc::Plan np;
+  const int pr = oc::make_plan(pin, &np);
+  if (pr != oc::ST_OK) return pr;
+  if (np.arena_bytes > h->cfg.dev_budget || np.slabs.size() != h->plan.slabs.size()) return OC_ERR_BUDGET;
+  h->plan = np;
+  std::memset(h->ops_key, 0xff, sizeof h->ops_key);   // cached ops belong to the old rate
+  h->stats.peak_dev_bytes = np.arena_bytes;
+  h->stats.rate_bits = best;
+  h->stats.pilot_rel_l2 = best_err;
+  h->stats.pilot_planes = planes;
+  h->stats.pilot_runs = runs;
+  return OC_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -604,6 +741,36 @@ int oc_codec_status(oc_stream stream) {
       return OC_ERR_HIP;
     }
     return codec_check_and_clear();
+  } catch (...) {
+    return OC_ERR_HOST;
+  }
+}
+
+size_t oc_codec_error_work_bytes(int64_t nx, int64_t ny, int64_t nz, int32_t rate_bits) {
+  try {
+    if (nx <= 0 || ny <= 0 || nz <= 0 || rate_bits < 1 || rate_bits > 32) return 0;
+    if (nx % 4 || ny % 4 || nz % 4) return 0;
+    return (size_t)oc::codec_error_parts(nx, ny, nz / 4, rate_bits) * 3u * sizeof(double);
+  } catch (...) {
+    return 0;
+  }
+}
+
+int oc_codec_error(const float *d_in, int64_t nx, int64_t ny, int64_t nz, int32_t rate_bits,
+                   void *d_work, size_t work_bytes, double *d_out, oc_stream stream) {
+  try {
+    if (!d_in || !d_work || !d_out || nx <= 0 || ny <= 0 || nz <= 0 || rate_bits < 1 || rate_bits > 32)
+      return OC_ERR_ARG;
+    if (((uintptr_t)d_in & 15) || ((uintptr_t)d_work & 7) || ((uintptr_t)d_out & 7)) return OC_ERR_ARG;
+    if (nx % 4 || ny % 4 || nz % 4) return OC_ERR_SHAPE;
+    if (work_bytes < oc_codec_error_work_bytes(nx, ny, nz, rate_bits)) return OC_ERR_ARG;
+    hipError_t e = oc::launch_codec_error(d_in, nx, ny, nz / 4, rate_bits, (double *)d_work, d_out,
+                                          (hipStream_t)stream);
+    if (e != hipSuccess) {
+      g_last_hip = e;
+      return OC_ERR_HIP;
+    }
+    return OC_OK;
   } catch (...) {
     return OC_ERR_HOST;
   }
@@ -726,6 +893,15 @@ int oc_create(const oc_grid *g, const oc_stencil *st, const oc_config *cfg, oc_h
     if (st->kind != OC_STAR7 && st->kind != OC_WAVE25) return OC_ERR_ARG;
     if (st->kind == OC_WAVE25 && !(st->h > 0.f && st->dt > 0.f)) return OC_ERR_ARG;
     if (cfg->copy_back < -1 || cfg->copy_back > 1024) return OC_ERR_ARG;
+    const bool auto_rate = cfg->error_budget > 0.f;
+    if (auto_rate) {
+      if (st->kind != OC_STAR7) return OC_ERR_UNSUPPORTED;
+      if (!std::isfinite(cfg->error_budget) || cfg->rate_bits < 1 || cfg->rate_bits > 32 ||
+          cfg->error_steps < 1)
+        return OC_ERR_ARG;
+    } else if (cfg->error_budget < 0.f || std::isnan(cfg->error_budget)) {
+      return OC_ERR_ARG;
+    }
     oc::Plan p;
     int r = oc::make_plan(plan_input(g, st, cfg), &p);
     if (r != oc::ST_OK) return r;
@@ -768,6 +944,10 @@ int oc_create(const oc_grid *g, const oc_stencil *st, const oc_config *cfg, oc_h
       }
     }
     h->stats.peak_dev_bytes = p.arena_bytes;
+    h->stats.rate_bits = p.in.rate;
+    h->auto_rate = auto_rate;
+    h->in_max = p.in;
+    h->in_max.slab_planes = (int)p.S;   // the slabs stay those planned for the largest rate
     h->stats.slab_planes = p.S;
     h->stats.halo_planes = p.halo;
     h->stats.n_slabs = (int64_t)p.slabs.size();
@@ -786,7 +966,18 @@ int oc_load(oc_handle *h, const float *u, const float *aux, const float *vel) {
     const bool wave = p.in.kind == oc::KIND_WAVE25;
     if (p.in.c0_field && !aux) return OC_ERR_ARG;
     if (wave && (!aux || !vel)) return OC_ERR_ARG;
+    // the checkpoints of an earlier oc_forward_ckpt belong to the old state
+    // and c0 field (the reverse sweeps read c0 from the aux store reloaded
+    // here): oc_adjoint needs a new forward
+    h->ckpt_valid = false;
     h->cur = 0;
+    if (h->auto_rate) {
+      const int pr = pick_rate(h, u, p.in.c0_field ? aux : nullptr);
+      if (pr) {
+        h->broken = pr == OC_ERR_HIP;
+        return pr;
+      }
+    }
     int r = load_field(h, u, h->host[0], p.coded);
     if (!r && wave) r = load_field(h, aux, h->host[0] + p.host_field_bytes, p.coded);
     if (!r && wave) r = load_field(h, vel, h->host[2], p.ro_coded);
@@ -1070,6 +1261,24 @@ int64_t oc_debug_check_adjoint(const oc_grid *g, const oc_stencil *st, const oc_
       return w;   // number of waits (for the mutation sweep)
     }
     return bad;
+  } catch (...) {
+    return OC_ERR_HOST;
+  }
+}
+
+int oc_debug_copy_to_host(void *host_base, size_t host_off, const void *dev_src, size_t bytes,
+                          int32_t workgroups, oc_stream stream) {
+  try {
+    if (!host_base || !dev_src || workgroups < 1 || workgroups > 1024) return OC_ERR_ARG;
+    uint8_t *dst = mapped_host(host_base);
+    if (!dst) return OC_ERR_ARG;   // not pinned, mapped host memory
+    hipError_t e = oc::launch_copy_to_host(dst + host_off, dev_src, bytes, workgroups,
+                                           (hipStream_t)stream);
+    if (e != hipSuccess) {
+      g_last_hip = e;
+      return OC_ERR_HIP;
+    }
+    return OC_OK;
   } catch (...) {
     return OC_ERR_HOST;
   }

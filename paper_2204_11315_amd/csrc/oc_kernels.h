@@ -33,6 +33,21 @@ hipError_t launch_decode(const void *d_in, int64_t nx, int64_t ny, int64_t nlaye
 // Device address of the codec's sticky error word.
 hipError_t codec_error_word(int **dev_ptr);
 
+// Round trip of the codec at `rate` over `nlayers` block layers of a device
+// field, without writing codes: every block is encoded and decoded by one
+// lane and compared with its inputs.  d_out3 (device) receives the sum of
+// squared errors, the sum of squared inputs (FP64) and the largest absolute
+// error; `parts` (device) holds codec_error_parts() triples of scratch.
+// Non-finite inputs set the codec's error word.
+int64_t codec_error_parts(int64_t nx, int64_t ny, int64_t nlayers, int rate);
+hipError_t launch_codec_error(const float *d_in, int64_t nx, int64_t ny, int64_t nlayers, int rate,
+                              double *parts, double *d_out3, hipStream_t s);
+// The same three statistics of x against the reference ref over n values
+// (n % 4 == 0, 16-byte aligned arrays); `parts` holds kDiffErrParts triples.
+constexpr int64_t kDiffErrParts = 1024;
+hipError_t launch_diff_error(const float *ref, const float *x, int64_t n, double *parts, double *d_out3,
+                             hipStream_t s);
+
 struct Star7Coef {
   float c0, cmx, cpx, cmy, cpy, cmz, cpz;
 };

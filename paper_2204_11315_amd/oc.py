@@ -47,7 +47,8 @@ class Config(ctypes.Structure):
                 ("single_buffer", ctypes.c_int32), ("timing", ctypes.c_int32),
                 ("ring_slots", ctypes.c_int32), ("prefetch", ctypes.c_int32),
                 ("fuse_steps", ctypes.c_int32), ("copy_back", ctypes.c_int32),
-                ("share_overlap", ctypes.c_int32), ("in_place", ctypes.c_int32)]
+                ("share_overlap", ctypes.c_int32), ("in_place", ctypes.c_int32),
+                ("error_budget", ctypes.c_float), ("error_steps", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -65,7 +66,9 @@ class Stats(ctypes.Structure):
                 ("blocks_decode", ctypes.c_uint64),
                 ("blocks_encode", ctypes.c_uint64),
                 ("host_ms_kernels", ctypes.c_double), ("host_ms_copies", ctypes.c_double),
-                ("host_ms_events", ctypes.c_double), ("host_ms_sync", ctypes.c_double)]
+                ("host_ms_events", ctypes.c_double), ("host_ms_sync", ctypes.c_double),
+                ("rate_bits", ctypes.c_int64), ("pilot_rel_l2", ctypes.c_double),
+                ("pilot_planes", ctypes.c_int64), ("pilot_runs", ctypes.c_int64)]
 
 
 _lock = threading.Lock()
@@ -90,6 +93,8 @@ _SIGS = {
     "oc_codec_compress": (ctypes.c_int, [_P, _I64, _I64, _I64, _I32, _P, _SZ, _P]),
     "oc_codec_decompress": (ctypes.c_int, [_P, _I64, _I64, _I64, _I32, _P, _P]),
     "oc_codec_status": (ctypes.c_int, [_P]),
+    "oc_codec_error_work_bytes": (_SZ, [_I64, _I64, _I64, _I32]),
+    "oc_codec_error": (ctypes.c_int, [_P, _I64, _I64, _I64, _I32, _P, _SZ, _P, _P]),
     "oc_star7_incore": (ctypes.c_int, [_P, _P, _P, _I64, _I64, _I64, _P, _P, _I64, _P]),
     "oc_wave25_incore": (ctypes.c_int, [_P, _P, _P, _P, _I64, _I64, _I64, _P, _I64, _I64, _P]),
     "oc_debug_fail_after": (ctypes.c_int, [_P, _I64]),
@@ -104,6 +109,7 @@ _SIGS = {
     "oc_debug_plan_ops": (_I64, [_P, _P, _P, _I64, _P]),
     "oc_debug_plan_dump": (_I64, [_P, _P, _P, _I64, ctypes.c_char_p, _SZ]),
     "oc_debug_timeline": (_I64, [_P, _P, _P, _P, _P, _I64]),
+    "oc_debug_copy_to_host": (ctypes.c_int, [_P, _SZ, _P, _SZ, _I32, _P]),
 }
 EXPORTED = tuple(_SIGS)
 
@@ -339,6 +345,39 @@ def decompress(d_codes, shape, rate: int, out=None, stream=None):
     return out
 
 
+def codec_error(d_in, rate: int, stream=None):
+    """Codec round trip at `rate` of a [nz][ny][nx] float32 CUDA tensor, on the
+    device: (sum of squared errors, sum of squared inputs, max abs error)."""
+    torch = _torch()
+    nz, ny, nx = d_in.shape
+    nw = int(lib().oc_codec_error_work_bytes(nx, ny, nz, int(rate)))
+    if nw == 0:
+        raise OCError(OC_ERR_SHAPE, "codec_error", "dims must be multiples of 4, rate 1..32")
+    work = torch.empty(nw, dtype=torch.uint8, device=d_in.device)
+    out = torch.empty(3, dtype=torch.float64, device=d_in.device)
+    _check(lib().oc_codec_error(_dev(d_in, torch.float32, "d_in"), nx, ny, nz, int(rate),
+                                ctypes.c_void_p(work.data_ptr()), nw, ctypes.c_void_p(out.data_ptr()),
+                                _stream_handle(stream)), "oc_codec_error")
+    torch.cuda.synchronize(d_in.device)
+    return tuple(float(v) for v in out.cpu())
+
+
+def copy_to_host(host_dst, host_off: int, dev_src, nbytes: int, workgroups: int = 4, stream=None):
+    """Enqueues the pipeline's copy-back kernel: `nbytes` from the start of a
+    CUDA tensor to byte `host_off` of a pinned CPU tensor (tuning aid for the
+    host-link probe)."""
+    torch = _torch()
+    if not (isinstance(host_dst, torch.Tensor) and host_dst.is_pinned()):
+        raise ValueError("host_dst must be a pinned CPU tensor")
+    if host_off < 0 or host_off + nbytes > host_dst.numel() * host_dst.element_size() or \
+            nbytes > dev_src.numel() * dev_src.element_size():
+        raise ValueError("copy range outside the tensors")
+    _check(lib().oc_debug_copy_to_host(ctypes.c_void_p(host_dst.data_ptr()), int(host_off),
+                                       ctypes.c_void_p(dev_src.data_ptr()), int(nbytes),
+                                       int(workgroups), _stream_handle(stream)),
+           "oc_debug_copy_to_host")
+
+
 def codec_status(stream=None) -> int:
     return int(lib().oc_codec_status(_stream_handle(stream)))
 
@@ -376,20 +415,27 @@ class OutOfCore:
 
     shape = (nz, ny, nx).  stencil = a Stencil (make_star7 / make_wave25); when
     None, the 7-point star with coefficients `c` (and a c0 field if c0_field).
-    budget = bytes of device memory the library may use (one torch allocation).
+    budget = bytes of device memory the library may use; one torch allocation of
+    exactly the bytes the plan needs (of the whole budget with full_arena: the
+    adjoint's reverse sweeps plan their own slabs within it).
     rate = 0 keeps raw FP32 on the host; 1..32 keeps fixed-rate codes.  k =
     steps per residency; slab_planes = S (0 = largest that fits the budget).
     fuse = 7-point steps per stencil launch (0 = 4); copy_back = workgroups of
     the copy-back kernel (0 = 4, -1 = runtime copies); share = region sharing
     (the overlap of consecutive slabs stays on the device); in_place = one host
-    level updated in place (needs sharing, or one slab).
+    level updated in place (needs sharing, or one slab).  error_budget > 0
+    (7-point only): `rate` is the largest rate allowed, and load() picks the
+    smallest rate whose relative L2 error after error_steps steps stays within
+    the budget, from a pilot run of the job's process on a z-sample of the
+    field; stats() reports the rate ("rate_bits") and the pilot's error.
     """
 
     def __init__(self, shape, c=C_CONFIG1, k: int = 4, rate: int = 0, budget: int = 512 << 20,
                  slab_planes: int = 0, single_buffer: bool = True, c0_field: bool = False,
                  timing: bool = False, ring_slots: int = 0, prefetch: int = 0, device=None,
                  stencil: Stencil = None, fuse: int = 0, copy_back: int = 0, share: bool = True,
-                 in_place: bool = False):
+                 in_place: bool = False, full_arena: bool = False, error_budget: float = 0.0,
+                 error_steps: int = 0):
         torch = _torch()
         self.shape = tuple(int(v) for v in shape)
         self.rate = int(rate)
@@ -402,7 +448,10 @@ class OutOfCore:
                           ring_slots, prefetch, fuse, share)
         if need == 0:
             raise OCError(OC_ERR_BUDGET, "plan", "no slab depth fits the budget")
-        self.arena = torch.empty(int(budget), dtype=torch.uint8, device=self.device)
+        # the plan's bytes fit `budget`; planning again with exactly those bytes
+        # as the budget picks the same slab depth (plan bytes grow with it)
+        arena_bytes = int(budget) if full_arena else int(need)
+        self.arena = torch.empty(arena_bytes, dtype=torch.uint8, device=self.device)
         self.streams = pipeline_streams(self.device)
         lb = host_level_bytes(self.shape, self.stencil, rate)
         self.levels = [torch.empty(lb, dtype=torch.uint8, pin_memory=True)
@@ -411,7 +460,7 @@ class OutOfCore:
         self.aux = torch.empty(ab, dtype=torch.uint8, pin_memory=True) if ab else None
         cfg = Config()
         cfg.dev_arena = self.arena.data_ptr()
-        cfg.dev_budget = int(budget)
+        cfg.dev_budget = arena_bytes
         for i, s in enumerate(self.streams):
             cfg.streams[i] = s.cuda_stream
         cfg.host_level[0] = self.levels[0].data_ptr()
@@ -430,6 +479,8 @@ class OutOfCore:
         cfg.copy_back = int(copy_back)
         cfg.share_overlap = 1 if share else -1
         cfg.in_place = 1 if in_place else 0
+        cfg.error_budget = float(error_budget)
+        cfg.error_steps = int(error_steps)
         self.cfg = cfg
         h = ctypes.c_void_p()
         torch.cuda.synchronize(self.device)
@@ -526,15 +577,20 @@ class Adjoint:
         torch = _torch()
         self.steps, self.ckpt_every, self.ckpt_rate = int(steps), int(ckpt_every), int(ckpt_rate)
         self.ooc = OutOfCore(shape, c, k=k, rate=0, budget=budget, slab_planes=slab_planes,
-                             c0_field=c0_field, device=device, share=share, fuse=fuse)
+                             c0_field=c0_field, device=device, share=share, fuse=fuse,
+                             full_arena=True)
         n = int(lib().oc_adjoint_host_bytes(self.ooc.h, self.steps, self.ckpt_every,
                                             self.ckpt_rate))
         if n == 0:
             raise OCError(OC_ERR_BUDGET, "oc_adjoint_host_bytes", "no adjoint plan fits")
         self.work = torch.empty(n, dtype=torch.uint8, pin_memory=True)
         self.shape = self.ooc.shape
+        # forwards started on this runner; the checkpoints backward() uses are
+        # those of forward number `generation`
+        self.generation = 0
 
     def forward(self, u0, c0=None) -> np.ndarray:
+        self.generation += 1
         self.ooc.load(u0, c0)
         _check(lib().oc_forward_ckpt(self.ooc.h, self.steps, self.ckpt_every, self.ckpt_rate,
                                      ctypes.c_void_p(self.work.data_ptr()), self.work.numel()),
@@ -564,10 +620,17 @@ def stencil_function():
         def forward(ctx, u0, c0, runner):
             uT = runner.forward(u0.detach().cpu().numpy(), c0.detach().cpu().numpy())
             ctx.runner = runner
+            ctx.generation = runner.generation
             return torch.from_numpy(uT)
 
         @staticmethod
         def backward(ctx, gT):
+            # the runner keeps the checkpoints of its latest forward only
+            if ctx.runner.generation != ctx.generation:
+                raise RuntimeError(
+                    "OCStencilFn.backward: the runner ran another forward (number %d) after "
+                    "this one (number %d) and no longer holds its checkpoints; use one runner "
+                    "per pending backward" % (ctx.runner.generation, ctx.generation))
             g_u0, g_c0 = ctx.runner.backward(gT.detach().to(torch.float32).cpu().numpy())
             return torch.from_numpy(g_u0), torch.from_numpy(g_c0), None
 

@@ -183,3 +183,22 @@ def test_adjoint_needs_checkpoints_and_raw_handle():
         assert e.value.status == oc.OC_ERR_STATE
     finally:
         adj.close()
+
+
+def test_load_after_forward_invalidates_the_checkpoints():
+    """oc_load replaces the state and the c0 field the checkpoints came from:
+    oc_adjoint then refuses (OC_ERR_STATE) until a new forward has run."""
+    u0, c0 = fields()
+    adj = oc.Adjoint(SHAPE, C, steps=STEPS, k=2, ckpt_every=EVERY, ckpt_rate=16, budget=BUDGET)
+    try:
+        uT = adj.forward(u0, c0)
+        adj.ooc.load(u0, 0.9 * c0)
+        with pytest.raises(oc.OCError) as e:
+            adj.backward(top_grad(uT))
+        assert e.value.status == oc.OC_ERR_STATE
+        uT = adj.forward(u0, c0)            # a new forward makes it valid again
+        g_u0, _ = adj.backward(top_grad(uT))
+    finally:
+        adj.close()
+    _, _, gu_ref, _ = oracle.star7_grad(u0, C, STEPS, c0)
+    assert rel(g_u0, gu_ref) < 1e-3

@@ -1,0 +1,140 @@
+"""Codec error on the device, and the codec rate chosen per error budget
+(Sec. 5: the user fixes a rate; here the library picks the smallest rate that
+keeps the job's error within a stated budget).
+
+* oc_codec_error (one round trip, no codes written) against the oracle's
+  compress / decompress, summed in FP64 on the host;
+* oc_load with an error budget: the pilot's pick, the job's actual error
+  against the FP64 oracle at the picked rate and one rate below, and the
+  result of the auto-rate handle against a fixed-rate handle at the picked
+  rate (bitwise: same plan, same kernels).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2204_11315_amd import inputs, oc
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+C = (0.4, 0.1, 0.1, 0.1, 0.1, 0.1, 0.1)
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("shape", [(8, 12, 16), (36, 20, 264), (4, 4, 4)])
+@pytest.mark.parametrize("R", [1, 5, 8, 16, 17, 32])
+def test_codec_error_matches_oracle_round_trip(shape, R):
+    f = inputs.grf_field(shape, seed=60 + R)
+    f[0, 0, :4] = [1e-40, -3e-42, 0.0, 7.5]      # subnormals in one block
+    se, sr, mx = oc.codec_error(_dev(f), R)
+    g = oracle.decompress(oracle.compress(f, R), shape, R).astype(np.float64)
+    d = g - f.astype(np.float64)
+    assert mx == float(np.abs(d).max())
+    assert se == pytest.approx(float(np.sum(d * d)), rel=1e-12, abs=1e-300)
+    assert sr == pytest.approx(float(np.sum(f.astype(np.float64) ** 2)), rel=1e-12)
+    assert oc.codec_status() == oc.OC_OK
+
+
+def test_codec_error_is_deterministic_and_rejects_bad_shapes():
+    f = _dev(inputs.grf_field((32, 64, 64), seed=3))
+    a = oc.codec_error(f, 9)
+    b = oc.codec_error(f, 9)
+    assert a == b
+    assert oc.lib().oc_codec_error_work_bytes(6, 8, 8, 8) == 0
+    assert oc.lib().oc_codec_error_work_bytes(8, 8, 8, 0) == 0
+
+
+def test_codec_error_flags_non_finite_input():
+    f = inputs.grf_field((8, 8, 8), seed=4)
+    f[3, 3, 3] = np.inf
+    oc.codec_error(_dev(f), 8)
+    assert oc.codec_status() == oc.OC_ERR_NONFINITE
+    assert oc.codec_status() == oc.OC_OK          # the flag clears
+
+
+SHAPE = (128, 64, 64)     # the pilot's sample is 64 of the 128 planes
+STEPS, K = 16, 4
+
+
+def run_job(u0, rate, **kw):
+    o = oc.OutOfCore(SHAPE, C, k=K, rate=rate, slab_planes=16, budget=64 << 20, **kw)
+    try:
+        o.load(u0)
+        o.run(STEPS)
+        return o.store(), o.stats()
+    finally:
+        o.close()
+
+
+@pytest.fixture(scope="module")
+def field():
+    u0 = inputs.grf_field(SHAPE, seed=2)
+    return u0, oracle.star7_run(u0, C, STEPS)
+
+
+@pytest.mark.parametrize("budget", [1e-3, 1e-4])
+def test_picked_rate_meets_the_budget_and_one_below_does_not(field, budget):
+    u0, ref = field
+    got, st = run_job(u0, 16, error_budget=budget, error_steps=STEPS)
+    R = st["rate_bits"]
+    assert 1 <= R <= 16
+    assert st["pilot_planes"] == 64 and st["pilot_runs"] >= 1
+    assert st["pilot_rel_l2"] <= budget
+    e = rel_l2(got, ref)
+    # the pilot predicts the job's error (same process, a z-sample of the
+    # field): within a factor 1.5 either way, and the pick meets the budget
+    assert e <= budget
+    assert st["pilot_rel_l2"] / 1.5 <= e <= 1.5 * st["pilot_rel_l2"]
+    if R > 1:
+        below, _ = run_job(u0, R - 1)
+        assert rel_l2(below, ref) > budget
+    # the auto-rate handle runs exactly the fixed-rate plan of its pick
+    fixed, st2 = run_job(u0, R)
+    assert np.array_equal(got.view(np.uint32), fixed.view(np.uint32))
+    assert st["peak_dev_bytes"] == st2["peak_dev_bytes"]
+
+
+def test_budget_no_rate_can_meet_uses_the_largest(field):
+    u0, _ = field
+    _, st = run_job(u0, 6, error_budget=1e-9, error_steps=STEPS)
+    assert st["rate_bits"] == 6 and st["pilot_rel_l2"] > 1e-9
+
+
+def test_budget_with_c0_field_and_a_reload():
+    shape = (96, 32, 48)
+    u0 = inputs.grf_field(shape, seed=5)
+    c0 = inputs.c0_field(shape, seed=6)
+    o = oc.OutOfCore(shape, C, k=3, rate=12, slab_planes=8, budget=32 << 20, c0_field=True,
+                     error_budget=5e-4, error_steps=7)
+    try:
+        o.load(u0, c0)
+        r1 = o.stats()["rate_bits"]
+        o.run(7)
+        got = o.store()
+        o.load(0.5 * u0, c0)                # the pilot runs again on the new field
+        assert o.stats()["rate_bits"] == r1     # scale-invariant codec: same pick
+    finally:
+        o.close()
+    ref = oracle.star7_run(u0, C, 7, c0)
+    assert rel_l2(got, ref) <= 5e-4 * 1.5
+
+
+def test_budget_needs_the_7_point_stencil_and_steps():
+    st = oc.make_wave25(10.0, 1e-3, (4, 4, 4), 15.0, 0.1)
+    with pytest.raises(oc.OCError) as e:
+        oc.OutOfCore((16, 16, 16), rate=12, k=2, stencil=st, budget=32 << 20, error_budget=1e-3,
+                     error_steps=4)
+    assert e.value.status == oc.OC_ERR_UNSUPPORTED
+    with pytest.raises(oc.OCError) as e:
+        oc.OutOfCore((16, 16, 16), rate=12, k=2, budget=32 << 20, error_budget=1e-3, error_steps=0)
+    assert e.value.status == oc.OC_ERR_ARG
