@@ -143,6 +143,32 @@ def run_leg(oc, torch, u0, rate, steps, warmup, ref=None, timing=True):
         o.close()
 
 
+def library_rate_pick(oc, torch, u0, rmax, budget, legs):
+    """The library's own choice of rate per error budget (oc_config.error_budget:
+    a pilot of the job's process on a 64-plane z-sample during oc_load), next
+    to the full-grid FP64 errors the bench measured for each candidate rate."""
+    torch.cuda.synchronize()
+    o = oc.OutOfCore(SHAPE, C, k=K, rate=rmax, budget=BUDGET, slab_planes=S,
+                     error_budget=budget, error_steps=STEPS)
+    try:
+        t0 = time.perf_counter()
+        o.load(u0)
+        torch.cuda.synchronize()
+        t_load = time.perf_counter() - t0
+        st = o.stats()
+    finally:
+        o.close()
+    pick = int(st["rate_bits"])
+    full = {str(r): leg["error_vs_fp64"]["rel_l2"] for r, leg in legs.items()
+            if r and leg["error_vs_fp64"] is not None}
+    res = {"rate_bits": pick, "pilot_rel_l2": st["pilot_rel_l2"], "pilot_planes": st["pilot_planes"],
+           "pilot_runs": st["pilot_runs"], "load_ms_with_pilot": t_load * 1e3,
+           "peak_dev_bytes": st["peak_dev_bytes"], "full_grid_rel_l2_by_rate": full}
+    log("library pick at budget %g: R=%d (pilot rel-L2 %.3g on %d planes, %d runs, load %.0f ms)" % (
+        budget, pick, st["pilot_rel_l2"], st["pilot_planes"], st["pilot_runs"], t_load * 1e3))
+    return res
+
+
 # Peaks of one MI355X: HBM3E 8 TB/s; 32-bit vector ALU = 256 CUs x 4 SIMDs x
 # 16 lanes x 2.4 GHz = 39.3 T lane-ops/s (one wave64 VALU instruction per CU
 # per cycle; the FP32 rate of 157.3 TFLOP/s counts packed FMA as 4 flops).
@@ -722,6 +748,7 @@ def main():
                    args.budget, args.error))
     main_leg = legs[head]
     base_leg = legs[0]
+    auto = library_rate_pick(oc, torch, u0, max(cands), args.budget, legs)
     roof = roofline_of(main_leg["kernels"], head)
     cpu = None
     if not args.no_cpu_baseline:
@@ -769,6 +796,7 @@ def main():
         "link_roofline": main_leg["link_roofline"],
         "uncompressed_link_roofline": base_leg["link_roofline"],
         "link_probe_gbs": link,
+        "library_rate_pick": auto,
         "cpu_baseline": cpu,
         "legs": {str(r): {k: v for k, v in leg.items() if k != "times_s"} for r, leg in legs.items()},
     }

@@ -565,14 +565,31 @@ PilotLayout pilot_layout(const oc::PlanInput &in, int64_t planes) {
 
 constexpr int64_t kPilotMaxPlanes = 64;
 
+// Planes of the pilot's z-sample that fit `bytes` of device memory (up to
+// kPilotMaxPlanes, a multiple of 4; 0 if not even 4 fit).
+int64_t pilot_planes_within(const oc::PlanInput &in, size_t bytes) {
+  int64_t planes = std::min<int64_t>(kPilotMaxPlanes, in.nz / 4 * 4);
+  while (planes >= 4 && pilot_layout(in, planes).need > bytes) planes -= 4;
+  return planes >= 4 ? planes : 0;
+}
+
+// Device bytes a handle needs: the plan's arena, and with an error budget at
+// least the pilot's largest sample within `budget` (the pilot runs in the
+// arena during oc_load, before the job uses it).
+size_t arena_bytes_for(const oc::Plan &p, const oc_config *cfg) {
+  if (!(cfg->error_budget > 0.f)) return p.arena_bytes;
+  const int64_t planes = pilot_planes_within(p.in, cfg->dev_budget);
+  if (planes == 0) return p.arena_bytes;
+  return std::max(p.arena_bytes, pilot_layout(p.in, planes).need);
+}
+
 // Picks the rate for the field u (c0f: the c0 field, or nullptr), replans the
 // handle at that rate and records the choice in its stats.
 int pick_rate(oc_handle *h, const float *u, const float *c0f) {
   const oc::PlanInput &in = h->in_max;
   const int rmax = in.rate;
   const int64_t nx = in.nx, ny = in.ny, nz = in.nz;
-  int64_t planes = std::min<int64_t>(kPilotMaxPlanes, nz / 4 * 4);
-  while (planes >= 4 && pilot_layout(in, planes).need > h->cfg.dev_budget) planes -= 4;
+  const int64_t planes = pilot_planes_within(in, h->cfg.dev_budget);
   if (planes < 4) return OC_ERR_BUDGET;
   const PilotLayout L = pilot_layout(in, planes);
   const size_t pb = (size_t)nx * (size_t)ny * 4u;
@@ -658,7 +675,7 @@ int pick_rate(oc_handle *h, const float *u, const float *c0f) {
   if (np.arena_bytes > h->cfg.dev_budget || np.slabs.size() != h->plan.slabs.size()) return OC_ERR_BUDGET;
   h->plan = np;
   std::memset(h->ops_key, 0xff, sizeof h->ops_key);   // cached ops belong to the old rate
-  h->stats.peak_dev_bytes = np.arena_bytes;
+  h->stats.peak_dev_bytes = std::max(np.arena_bytes, L.need);   // the pilot ran in the arena too
   h->stats.rate_bits = best;
   h->stats.pilot_rel_l2 = best_err;
   h->stats.pilot_planes = planes;
@@ -880,7 +897,7 @@ size_t oc_plan_bytes(const oc_grid *g, const oc_stencil *st, const oc_config *cf
     if (!grid_ok(g) || !st || !cfg) return 0;
     oc::Plan p;
     if (oc::make_plan(plan_input(g, st, cfg), &p) != oc::ST_OK) return 0;
-    return p.arena_bytes;
+    return arena_bytes_for(p, cfg);
   } catch (...) {
     return 0;
   }

@@ -186,7 +186,8 @@ def host_aux_bytes(shape, stencil: Stencil, rate: int) -> int:
 
 def plan_config(k: int, slab_planes: int, rate: int, single_buffer: bool = True,
                 budget: int = 0, ring_slots: int = 0, prefetch: int = 0, fuse: int = 0,
-                share: bool = False, in_place: bool = False) -> Config:
+                share: bool = False, in_place: bool = False, error_budget: float = 0.0,
+                error_steps: int = 0) -> Config:
     """A Config carrying only the plan fields."""
     cfg = Config()
     cfg.k = int(k)
@@ -199,14 +200,20 @@ def plan_config(k: int, slab_planes: int, rate: int, single_buffer: bool = True,
     cfg.fuse_steps = int(fuse)
     cfg.share_overlap = 1 if share else -1
     cfg.in_place = 1 if in_place else 0
+    cfg.error_budget = float(error_budget)
+    cfg.error_steps = int(error_steps)
     return cfg
 
 
 def plan_bytes(shape, stencil: Stencil, k: int, slab_planes: int, rate: int,
                single_buffer: bool = True, budget: int = 0, ring_slots: int = 0,
-               prefetch: int = 0, fuse: int = 0, share: bool = False) -> int:
+               prefetch: int = 0, fuse: int = 0, share: bool = False,
+               error_budget: float = 0.0, error_steps: int = 0) -> int:
+    """Device bytes of the plan (with an error budget: at least the pilot's
+    sample within `budget`)."""
     g = make_grid(shape)
-    cfg = plan_config(k, slab_planes, rate, single_buffer, budget, ring_slots, prefetch, fuse, share)
+    cfg = plan_config(k, slab_planes, rate, single_buffer, budget, ring_slots, prefetch, fuse, share,
+                      error_budget=error_budget, error_steps=error_steps)
     return int(lib().oc_plan_bytes(_ref(g), _ref(stencil), _ref(cfg)))
 
 
@@ -445,7 +452,8 @@ class OutOfCore:
         self.grid = make_grid(self.shape)
         self.device = torch.device(device if device is not None else "cuda")
         need = plan_bytes(self.shape, self.stencil, k, slab_planes, rate, single_buffer, budget,
-                          ring_slots, prefetch, fuse, share)
+                          ring_slots, prefetch, fuse, share, error_budget=error_budget,
+                          error_steps=error_steps)
         if need == 0:
             raise OCError(OC_ERR_BUDGET, "plan", "no slab depth fits the budget")
         # the plan's bytes fit `budget`; planning again with exactly those bytes

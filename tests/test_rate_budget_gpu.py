@@ -101,7 +101,8 @@ def test_picked_rate_meets_the_budget_and_one_below_does_not(field, budget):
     # the auto-rate handle runs exactly the fixed-rate plan of its pick
     fixed, st2 = run_job(u0, R)
     assert np.array_equal(got.view(np.uint32), fixed.view(np.uint32))
-    assert st["peak_dev_bytes"] == st2["peak_dev_bytes"]
+    # the arena holds the plan of the pick and, during oc_load, the pilot
+    assert st["peak_dev_bytes"] >= st2["peak_dev_bytes"]
 
 
 def test_budget_no_rate_can_meet_uses_the_largest(field):
