@@ -48,7 +48,8 @@ enum {
   OC_ERR_NONFINITE = -5, /* the codec met an Inf/NaN value                                */
   OC_ERR_STATE = -6,     /* call out of order (e.g. run before load)                      */
   OC_ERR_UNSUPPORTED = -7,
-  OC_ERR_HOST = -8       /* host memory or a host thread could not be had (C++ exception) */
+  OC_ERR_HOST = -8,      /* host memory or a host thread could not be had (C++ exception) */
+  OC_ERR_TOO_LARGE = -9  /* input beyond the fixed scratch of an allocation-free entry point */
 };
 
 typedef struct oc_handle oc_handle;
@@ -233,6 +234,22 @@ int oc_codec_status(oc_stream stream);
 size_t oc_codec_error_work_bytes(int64_t nx, int64_t ny, int64_t nz, int32_t rate_bits);
 int oc_codec_error(const float *d_in, int64_t nx, int64_t ny, int64_t nz, int32_t rate_bits,
                    void *d_work, size_t work_bytes, double *d_out, oc_stream stream);
+
+/* oc_codec_error without a workspace, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, results and error behaviour as
+ * oc_codec_error; the partial sums go to a static device array of just under
+ * 2 MiB that each device holds until the process ends.  The call allocates
+ * nothing (no hipMalloc, no allocating library routine).  Limit: at most
+ * 87381 workgroups of the round-trip kernel, i.e. (nx/4)*(ny/4)*(nz/4) <=
+ * 22,369,536 blocks for rate_bits <= 16 and <= 11,184,768 blocks above
+ * (OC_ERR_TOO_LARGE beyond, checked on the host before anything is
+ * enqueued).  The current device must own d_in, d_out and `stream`.  Every
+ * call on a device shares that device's array (each call overwrites the sums
+ * it reads, nothing needs clearing): calls that overlap on one device, e.g.
+ * on two streams without ordering, race and give wrong sums. */
+int oc_codec_error_noalloc(const float *d_in, int64_t nx, int64_t ny, int64_t nz, int32_t rate_bits,
+                           double *d_out, oc_stream stream);
 
 /* ---- adjoint (differentiation of the 7-point path, raw handles) ---------- */
 /* For u_T = A(c0)^T u_0 (A = the 7-point update with per-cell c0 when the

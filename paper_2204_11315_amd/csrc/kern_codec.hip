@@ -24,6 +24,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "oc_kernels.h"
 
@@ -730,6 +731,41 @@ hipError_t launch_diff_error(const float *ref, const float *x, int64_t n, double
 
 hipError_t codec_error_word(int **dev_ptr) {
   return hipGetSymbolAddress((void **)dev_ptr, HIP_SYMBOL(g_oc_codec_err));
+}
+
+}  // namespace oc
+
+// ---- allocation-free round trip ----------------------------------------------
+// The per-workgroup partial sums of the codec round trip live in this
+// file-scope array when the caller brings no workspace: one copy per device,
+// held until the process ends.  On the host the array's name only stands for
+// the symbol; kernels get the device address that hipGetSymbolAddress returns
+// for the current device, looked up once per device and kept.
+static __device__ __align__(256) double scratch[3 * oc::kCodecErrStaticParts];
+
+namespace oc {
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_addr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t codec_error_scratch(double **dev_ptr) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_addr[dev] = (double *)p;
+  }
+  *dev_ptr = g_scratch_addr[dev];
+  return hipSuccess;
 }
 
 }  // namespace oc

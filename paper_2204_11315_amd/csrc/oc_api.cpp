@@ -698,6 +698,7 @@ const char *oc_status_str(int st) {
     case OC_ERR_STATE: return "call out of order";
     case OC_ERR_UNSUPPORTED: return "unsupported combination";
     case OC_ERR_HOST: return "host allocation or thread creation failed";
+    case OC_ERR_TOO_LARGE: return "input larger than the allocation-free entry point's fixed scratch";
     default: return "unknown status";
   }
 }
@@ -783,6 +784,29 @@ int oc_codec_error(const float *d_in, int64_t nx, int64_t ny, int64_t nz, int32_
     if (work_bytes < oc_codec_error_work_bytes(nx, ny, nz, rate_bits)) return OC_ERR_ARG;
     hipError_t e = oc::launch_codec_error(d_in, nx, ny, nz / 4, rate_bits, (double *)d_work, d_out,
                                           (hipStream_t)stream);
+    if (e != hipSuccess) {
+      g_last_hip = e;
+      return OC_ERR_HIP;
+    }
+    return OC_OK;
+  } catch (...) {
+    return OC_ERR_HOST;
+  }
+}
+
+int oc_codec_error_noalloc(const float *d_in, int64_t nx, int64_t ny, int64_t nz, int32_t rate_bits,
+                           double *d_out, oc_stream stream) {
+  try {
+    if (!d_in || !d_out || nx <= 0 || ny <= 0 || nz <= 0 || rate_bits < 1 || rate_bits > 32)
+      return OC_ERR_ARG;
+    if (((uintptr_t)d_in & 15) || ((uintptr_t)d_out & 7)) return OC_ERR_ARG;
+    if (nx % 4 || ny % 4 || nz % 4) return OC_ERR_SHAPE;
+    if (oc::codec_error_parts(nx, ny, nz / 4, rate_bits) > oc::kCodecErrStaticParts)
+      return OC_ERR_TOO_LARGE;
+    double *parts = nullptr;
+    hipError_t e = oc::codec_error_scratch(&parts);
+    if (e == hipSuccess)
+      e = oc::launch_codec_error(d_in, nx, ny, nz / 4, rate_bits, parts, d_out, (hipStream_t)stream);
     if (e != hipSuccess) {
       g_last_hip = e;
       return OC_ERR_HIP;

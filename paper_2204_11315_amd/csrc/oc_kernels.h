@@ -45,6 +45,11 @@ hipError_t launch_codec_error(const float *d_in, int64_t nx, int64_t ny, int64_t
 // The same three statistics of x against the reference ref over n values
 // (n % 4 == 0, 16-byte aligned arrays); `parts` holds kDiffErrParts triples.
 constexpr int64_t kDiffErrParts = 1024;
+// Partial-sum triples the allocation-free round trip can hold (a static
+// device array of 3 * kCodecErrStaticParts doubles, just under 2 MiB), and
+// that array's address on the current device (looked up once per device).
+constexpr int64_t kCodecErrStaticParts = 87381;
+hipError_t codec_error_scratch(double **dev_ptr);
 hipError_t launch_diff_error(const float *ref, const float *x, int64_t n, double *parts, double *d_out3,
                              hipStream_t s);
 

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_HERE, "liboc.so")
 
 OC_OK, OC_ERR_ARG, OC_ERR_SHAPE, OC_ERR_BUDGET = 0, -1, -2, -3
 OC_ERR_HIP, OC_ERR_NONFINITE, OC_ERR_STATE, OC_ERR_UNSUPPORTED, OC_ERR_HOST = -4, -5, -6, -7, -8
+OC_ERR_TOO_LARGE = -9
 OC_STAR7, OC_WAVE25 = 1, 2
 
 C_CONFIG1 = (0.4, 0.1, 0.1, 0.1, 0.1, 0.1, 0.1)
@@ -95,6 +96,7 @@ _SIGS = {
     "oc_codec_status": (ctypes.c_int, [_P]),
     "oc_codec_error_work_bytes": (_SZ, [_I64, _I64, _I64, _I32]),
     "oc_codec_error": (ctypes.c_int, [_P, _I64, _I64, _I64, _I32, _P, _SZ, _P, _P]),
+    "oc_codec_error_noalloc": (ctypes.c_int, [_P, _I64, _I64, _I64, _I32, _P, _P]),
     "oc_star7_incore": (ctypes.c_int, [_P, _P, _P, _I64, _I64, _I64, _P, _P, _I64, _P]),
     "oc_wave25_incore": (ctypes.c_int, [_P, _P, _P, _P, _I64, _I64, _I64, _P, _I64, _I64, _P]),
     "oc_debug_fail_after": (ctypes.c_int, [_P, _I64]),
@@ -365,6 +367,21 @@ def codec_error(d_in, rate: int, stream=None):
     _check(lib().oc_codec_error(_dev(d_in, torch.float32, "d_in"), nx, ny, nz, int(rate),
                                 ctypes.c_void_p(work.data_ptr()), nw, ctypes.c_void_p(out.data_ptr()),
                                 _stream_handle(stream)), "oc_codec_error")
+    torch.cuda.synchronize(d_in.device)
+    return tuple(float(v) for v in out.cpu())
+
+
+def codec_error_noalloc(d_in, rate: int, out=None, stream=None):
+    """codec_error through the allocation-free entry point: no workspace; the
+    three FP64 results go to `out` (a CUDA float64 tensor of 3, allocated here
+    if None) and are returned as a tuple after a synchronisation."""
+    torch = _torch()
+    nz, ny, nx = d_in.shape
+    if out is None:
+        out = torch.empty(3, dtype=torch.float64, device=d_in.device)
+    _check(lib().oc_codec_error_noalloc(_dev(d_in, torch.float32, "d_in"), nx, ny, nz, int(rate),
+                                        _dev(out, torch.float64, "out"), _stream_handle(stream)),
+           "oc_codec_error_noalloc")
     torch.cuda.synchronize(d_in.device)
     return tuple(float(v) for v in out.cpu())
 

@@ -38,11 +38,11 @@ def test_library_exports_every_declared_function():
 
 
 def test_status_strings():
-    codes = (0, -1, -2, -3, -5, -6, -7, -8)
+    codes = (0, -1, -2, -3, -5, -6, -7, -8, -9)
     names = [oc.status_str(st) for st in codes]
     assert all(names) and "unknown status" not in names
     assert len(set(names)) == len(codes)
-    assert oc.status_str(-9) == "unknown status"
+    assert oc.status_str(-10) == "unknown status"
 
 
 ST = oc.make_star7()
