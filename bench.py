@@ -105,17 +105,19 @@ class Reference:
         return {"rel_l2": float(np.linalg.norm(have - self.vals) / np.linalg.norm(self.vals))}
 
 
-def run_leg(oc, torch, u0, rate, steps, warmup, ref=None, timing=True):
+def run_leg(oc, torch, u0, rate, steps, warmup, ref=None, timing=True, fused=False, keep=False):
     """Times `steps` jobs after `warmup`; then one end-to-end load + job +
-    store whose output is checked against `ref`.  Device memory of the leg:
-    the plan's carve-out (oc_stats), torch's peak allocation while the handle
-    lives (the arena is the only allocation) and the drop of the device's free
-    memory (hipMemGetInfo) across the handle's creation."""
+    store whose output is checked against `ref` (and returned with keep).
+    Device memory of the leg: the plan's carve-out (oc_stats), torch's peak
+    allocation while the handle lives (the arena is the only allocation) and
+    the drop of the device's free memory (hipMemGetInfo) across the handle's
+    creation.  fused: one fused codec kernel per slab instead of three."""
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
     torch.cuda.reset_peak_memory_stats()
     free0 = torch.cuda.mem_get_info()[0]
-    o = oc.OutOfCore(SHAPE, C, k=K, rate=rate, budget=BUDGET, slab_planes=S, timing=timing)
+    o = oc.OutOfCore(SHAPE, C, k=K, rate=rate, budget=BUDGET, slab_planes=S, timing=timing,
+                     fused_codec=fused)
     try:
         mem = {"torch_peak_allocated_bytes": None,
                "meminfo_drop_bytes": int(free0 - torch.cuda.mem_get_info()[0])}
@@ -138,9 +140,41 @@ def run_leg(oc, torch, u0, rate, steps, warmup, ref=None, timing=True):
         e2e = time.perf_counter() - t0
         mem["torch_peak_allocated_bytes"] = int(torch.cuda.max_memory_allocated())
         err = ref.error(got) if ref is not None else None
-        return times, stats, err, e2e, mem
+        return times, stats, err, e2e, mem, (got if keep else None)
     finally:
         o.close()
+
+
+def digest(a):
+    """Digest of an array's bytes (equal outputs of two legs)."""
+    try:
+        import xxhash
+        return xxhash.xxh3_128_hexdigest(np.ascontiguousarray(a).view(np.uint8))
+    except ImportError:
+        import hashlib
+        return hashlib.blake2b(np.ascontiguousarray(a).view(np.uint8), digest_size=16).hexdigest()
+
+
+def fused_leg(oc, torch, u0, rate, args, ref, cells, digest_three):
+    """The headline rate with the fused codec kernel (one launch per slab:
+    decode, k steps, encode; no FP32 working buffer in device memory): timed
+    like the other legs; its end-to-end output must equal the three-kernel
+    leg's bit for bit."""
+    times, stats, err, e2e, mem, got = run_leg(oc, torch, u0, rate, args.steps, args.warmup, ref,
+                                               fused=True, keep=True)
+    same = digest(got) == digest_three
+    del got
+    med = float(np.median(times))
+    st = stats[-1]
+    leg = {"rate_bits": rate, "gcell_per_s": cells / med / 1e9, "ms_per_job": med * 1e3,
+           "error_vs_fp64": err, "peak_dev_bytes": st["peak_dev_bytes"], "device_memory": mem,
+           "bytes_h2d": st["bytes_h2d"], "bytes_d2h": st["bytes_d2h"],
+           "kernels": kernel_roofline(stats, rate), "end_to_end_ms": e2e * 1e3,
+           "same_output_as_three_kernels": bool(same)}
+    log("fused codec kernel, rate %d: %.2f GCell/s, %.1f ms/job, device memory %d MiB, "
+        "same output as three kernels: %s" % (rate, leg["gcell_per_s"], med * 1e3,
+                                               mem["torch_peak_allocated_bytes"] >> 20, same))
+    return leg
 
 
 def library_rate_pick(oc, torch, u0, rmax, budget, legs):
@@ -195,11 +229,13 @@ def kernel_roofline(stats, rate):
     """Per-kernel averages over the timed runs, from the library's own launch
     events.  Algorithmic bytes per launch: decode reads 8R B and writes 256 B
     per 4x4x4 block, encode the reverse; a stencil launch reads its input plane
-    range once and writes its output range once (as counted by the library)."""
-    tot = {"decode": 0.0, "encode": 0.0, "stencil": 0.0}
-    cnt = {"decode": 0, "encode": 0, "stencil": 0}
-    byt = {"decode": 0.0, "encode": 0.0, "stencil": 0.0}
-    blk = {"decode": 0, "encode": 0, "stencil": 0}
+    range once and writes its output range once (as counted by the library);
+    the fused codec kernel reads the slab's codes and writes the interior's
+    (8R B per block each way: its FP32 planes never leave LDS)."""
+    tot = {"decode": 0.0, "encode": 0.0, "stencil": 0.0, "fused": 0.0}
+    cnt = {"decode": 0, "encode": 0, "stencil": 0, "fused": 0}
+    byt = {"decode": 0.0, "encode": 0.0, "stencil": 0.0, "fused": 0.0}
+    blk = {"decode": 0, "encode": 0, "stencil": 0, "fused": 0}
     for s in stats:
         for k in tot:
             tot[k] += s["ms_" + k]
@@ -207,6 +243,7 @@ def kernel_roofline(stats, rate):
         byt["decode"] += s["blocks_decode"] * (8 * rate + 256)
         byt["encode"] += s["blocks_encode"] * (256 + 8 * rate)
         byt["stencil"] += s["bytes_stencil"]
+        byt["fused"] += (s["blocks_decode"] + s["blocks_encode"]) * 8 * rate
         blk["decode"] += s["blocks_decode"]
         blk["encode"] += s["blocks_encode"]
     per = {}
@@ -216,7 +253,7 @@ def kernel_roofline(stats, rate):
             per_launch = byt[k] / cnt[k]
             d = {"avg_ms": avg_ms, "launches": cnt[k], "bytes_per_launch": per_launch,
                  "gbs": per_launch / (avg_ms * 1e-3) / 1e9, "total_ms": tot[k]}
-            if k != "stencil":
+            if k in ("decode", "encode"):
                 d["blocks_per_launch"] = blk[k] / cnt[k]
             ctr = KERNEL_COUNTERS.get((k, None if k == "stencil" else rate))
             if ctr and "valu_per_wave" in ctr:
@@ -672,6 +709,8 @@ def main():
     ap.add_argument("--wave-rates", default="12,14,16",
                     help="coded legs of the wave workload (an uncompressed leg always runs)")
     ap.add_argument("--fd-dirs", type=int, default=32)
+    ap.add_argument("--no-fused", action="store_true",
+                    help="skip the fused codec kernel leg at the headline rate")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU: sharding the z-slabs over several GPUs is not "
@@ -713,9 +752,12 @@ def main():
     cands = [int(r) for r in args.rates.split(",") if r]
     if args.rate and args.rate not in cands:
         cands.append(args.rate)
-    legs = {}
+    legs, digests = {}, {}
     for rate in [0] + sorted(cands):
-        times, stats, err, e2e, mem = run_leg(oc, torch, u0, rate, args.steps, args.warmup, ref)
+        times, stats, err, e2e, mem, got = run_leg(oc, torch, u0, rate, args.steps, args.warmup, ref,
+                                                   keep=True)
+        digests[rate] = digest(got)
+        del got
         med = float(np.median(times))
         st = stats[-1]
         legs[rate] = {"gcell_per_s": cells / med / 1e9, "ms_per_job": med * 1e3,
@@ -748,6 +790,9 @@ def main():
                    args.budget, args.error))
     main_leg = legs[head]
     base_leg = legs[0]
+    fused = None
+    if not args.no_fused and head <= 16:
+        fused = fused_leg(oc, torch, u0, head, args, ref, cells, digests[head])
     auto = library_rate_pick(oc, torch, u0, max(cands), args.budget, legs)
     roof = roofline_of(main_leg["kernels"], head)
     cpu = None
@@ -797,6 +842,7 @@ def main():
         "uncompressed_link_roofline": base_leg["link_roofline"],
         "link_probe_gbs": link,
         "library_rate_pick": auto,
+        "fused_codec_leg": fused,
         "cpu_baseline": cpu,
         "legs": {str(r): {k: v for k, v in leg.items() if k != "times_s"} for r, leg in legs.items()},
     }

@@ -122,6 +122,12 @@ typedef struct {
                               rate_bits is used.  oc_stats reports the rate and the pilot's
                               error.  0 = the fixed rate rate_bits (Sec. 5)                  */
   int32_t error_steps;     /* the job length the budget is for (>= 1 with error_budget > 0)   */
+  int32_t fused_codec;     /* 1 = each coded residency runs as one kernel (decode, k steps,
+                              encode; no FP32 working buffer in device memory, the device
+                              holds only the ring of coded slots): 7-point with constant c0,
+                              k <= 4, rate_bits 1..16, else OC_ERR_UNSUPPORTED.  The codes
+                              are those of the three-kernel path, bit for bit.  0 = decode,
+                              stencil and encode kernels over a full-size working buffer   */
 } oc_config;
 
 typedef struct {
@@ -150,6 +156,8 @@ typedef struct {
   double pilot_rel_l2;     /* error budget: relative L2 error of the pilot at that rate       */
   int64_t pilot_planes;    /* error budget: planes of the z-sample the pilot ran on          */
   int64_t pilot_runs;      /* error budget: rates the last oc_load tried                     */
+  double ms_fused;         /* timing on: summed durations of the fused codec launches        */
+  uint64_t n_fused;        /* and their count                                                 */
 } oc_stats;
 
 /* Bytes one host level needs for this grid / stencil / rate (raw FP32 planes,

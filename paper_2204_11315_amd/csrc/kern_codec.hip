@@ -32,361 +32,12 @@
 // encoder.  Read and cleared by the host through its symbol address.
 __device__ int g_oc_codec_err;
 
+#include "codec_dev.h"
+#include "stencil_dev.h"
+
 namespace {
 
-// ---- coefficient order: ascending (i+j+k, i^2+j^2+k^2, t) ------------------
-struct SeqOrder {
-  int at[64];
-};
-constexpr SeqOrder make_seq_order() {
-  SeqOrder o{};
-  int key1[64] = {}, key2[64] = {};
-  for (int t = 0; t < 64; t++) {
-    int i = t & 3, j = (t >> 2) & 3, k = t >> 4;
-    key1[t] = i + j + k;
-    key2[t] = i * i + j * j + k * k;
-    o.at[t] = t;
-  }
-  // selection sort, compile time
-  for (int a = 0; a < 64; a++) {
-    int best = a;
-    for (int b = a + 1; b < 64; b++) {
-      int x = o.at[b], y = o.at[best];
-      bool less = key1[x] != key1[y] ? key1[x] < key1[y]
-                  : key2[x] != key2[y] ? key2[x] < key2[y] : x < y;
-      if (less) best = b;
-    }
-    int tmp = o.at[a];
-    o.at[a] = o.at[best];
-    o.at[best] = tmp;
-  }
-  return o;
-}
-constexpr SeqOrder kSeq = make_seq_order();
-
-// ---- integer lifting (wrapping, floor shifts) -----------------------------
-__device__ __forceinline__ void lift_fwd(int32_t &a, int32_t &b, int32_t &c, int32_t &d) {
-  uint32_t d0 = (uint32_t)b - (uint32_t)a;
-  uint32_t s0 = (uint32_t)a + (uint32_t)((int32_t)d0 >> 1);
-  uint32_t d1 = (uint32_t)d - (uint32_t)c;
-  uint32_t s1 = (uint32_t)c + (uint32_t)((int32_t)d1 >> 1);
-  uint32_t D = s1 - s0;
-  uint32_t S = s0 + (uint32_t)((int32_t)D >> 1);
-  a = (int32_t)S;
-  b = (int32_t)D;
-  c = (int32_t)d0;
-  d = (int32_t)d1;
-}
-__device__ __forceinline__ void lift_inv(int32_t &a, int32_t &b, int32_t &c, int32_t &d) {
-  uint32_t S = (uint32_t)a, D = (uint32_t)b, d0 = (uint32_t)c, d1 = (uint32_t)d;
-  uint32_t s0 = S - (uint32_t)((int32_t)D >> 1);
-  uint32_t s1 = D + s0;
-  uint32_t x2 = s1 - (uint32_t)((int32_t)d1 >> 1);
-  uint32_t x3 = d1 + x2;
-  uint32_t x0 = s0 - (uint32_t)((int32_t)d0 >> 1);
-  uint32_t x1 = d0 + x0;
-  a = (int32_t)x0;
-  b = (int32_t)x1;
-  c = (int32_t)x2;
-  d = (int32_t)x3;
-}
-
-__device__ __forceinline__ void xform_fwd(int32_t *q) {
-#pragma unroll
-  for (int k = 0; k < 4; k++)
-#pragma unroll
-    for (int j = 0; j < 4; j++) lift_fwd(q[16 * k + 4 * j], q[16 * k + 4 * j + 1], q[16 * k + 4 * j + 2], q[16 * k + 4 * j + 3]);
-#pragma unroll
-  for (int k = 0; k < 4; k++)
-#pragma unroll
-    for (int i = 0; i < 4; i++) lift_fwd(q[16 * k + i], q[16 * k + 4 + i], q[16 * k + 8 + i], q[16 * k + 12 + i]);
-#pragma unroll
-  for (int j = 0; j < 4; j++)
-#pragma unroll
-    for (int i = 0; i < 4; i++) lift_fwd(q[4 * j + i], q[16 + 4 * j + i], q[32 + 4 * j + i], q[48 + 4 * j + i]);
-}
-__device__ __forceinline__ void xform_inv(int32_t *q) {
-#pragma unroll
-  for (int j = 0; j < 4; j++)
-#pragma unroll
-    for (int i = 0; i < 4; i++) lift_inv(q[4 * j + i], q[16 + 4 * j + i], q[32 + 4 * j + i], q[48 + 4 * j + i]);
-#pragma unroll
-  for (int k = 0; k < 4; k++)
-#pragma unroll
-    for (int i = 0; i < 4; i++) lift_inv(q[16 * k + i], q[16 * k + 4 + i], q[16 * k + 8 + i], q[16 * k + 12 + i]);
-#pragma unroll
-  for (int k = 0; k < 4; k++)
-#pragma unroll
-    for (int j = 0; j < 4; j++) lift_inv(q[16 * k + 4 * j], q[16 * k + 4 * j + 1], q[16 * k + 4 * j + 2], q[16 * k + 4 * j + 3]);
-}
-
-// ---- 32x32 bit-matrix transpose, in place: bit c of A[r] <-> bit r of A[c] --
-__device__ __forceinline__ void bit_transpose32(uint32_t *A) {
-#pragma unroll
-  for (int r = 0; r < 16; r++) {
-    // halves: bytes {A.b0, A.b1, B.b0, B.b1} and {A.b2, A.b3, B.b2, B.b3}
-    uint32_t a = A[r], b = A[r + 16];
-    A[r] = __builtin_amdgcn_perm(b, a, 0x05040100u);
-    A[r + 16] = __builtin_amdgcn_perm(b, a, 0x07060302u);
-  }
-#pragma unroll
-  for (int r = 0; r < 32; r++) {
-    if (r & 8) continue;
-    uint32_t a = A[r], b = A[r + 8];
-    A[r] = __builtin_amdgcn_perm(b, a, 0x06020400u);
-    A[r + 8] = __builtin_amdgcn_perm(b, a, 0x07030501u);
-  }
-#pragma unroll
-  for (int r = 0; r < 32; r++) {
-    if (r & 4) continue;
-    uint32_t t = ((A[r] >> 4) ^ A[r + 4]) & 0x0F0F0F0Fu;
-    A[r] ^= t << 4;
-    A[r + 4] ^= t;
-  }
-#pragma unroll
-  for (int r = 0; r < 32; r++) {
-    if (r & 2) continue;
-    uint32_t t = ((A[r] >> 2) ^ A[r + 2]) & 0x33333333u;
-    A[r] ^= t << 2;
-    A[r + 2] ^= t;
-  }
-#pragma unroll
-  for (int r = 0; r < 32; r++) {
-    if (r & 1) continue;
-    uint32_t t = ((A[r] >> 1) ^ A[r + 1]) & 0x55555555u;
-    A[r] ^= t << 1;
-    A[r + 1] ^= t;
-  }
-}
-
-// floor((1 - (-2)^d) / 6): the mean of d unread negabinary digits, rounded
-// down.  d = 0 (nothing unread) and d = 32 (nothing read, so no 1 read either)
-// add nothing.
-__device__ __forceinline__ int32_t unread_mean(int d) {
-  if (d <= 0 || d >= 32) return 0;
-  const int64_t pw = (int64_t)1 << d;
-  const int64_t num = 1 - ((d & 1) ? -pw : pw);
-  return (int32_t)(num >= 0 ? num / 6 : -((-num + 5) / 6));
-}
-
-__device__ __forceinline__ uint64_t lowmask64(int n) {
-  return n >= 64 ? ~0ull : ((1ull << n) - 1ull);
-}
-
-// ---- bit writer over one slot of NW dwords ----------------------------------
-// Branch-free: every put stores the current (possibly partial) dword, so a
-// later put simply overwrites it; once the budget is spent the index is
-// clamped onto the slot's padding dword (index NW), which is never copied out.
-// The slot must start zeroed, and flush() ends the stream.
-struct BitWriter {
-  uint32_t *slot;
-  int NW;    // dwords in the slot
-  uint64_t acc;
-  int nacc;  // valid bits in acc (< 32 between calls)
-  int widx;  // dwords completed
-  __device__ __forceinline__ int pos() const { return 32 * widx + nacc; }
-  __device__ __forceinline__ void put(uint32_t v, int len) {  // len <= 32, v < 2^len
-    acc |= (uint64_t)v << nacc;
-    nacc += len;
-    slot[min(widx, NW)] = (uint32_t)acc;
-    const bool full = nacc >= 32;
-    widx += full ? 1 : 0;
-    acc = full ? (acc >> 32) : acc;
-    nacc -= full ? 32 : 0;
-  }
-  __device__ __forceinline__ void put64(uint64_t v, int len) {  // len <= 64
-    const int lo = min(len, 32);
-    put((uint32_t)v & (lo >= 32 ? 0xFFFFFFFFu : ((1u << lo) - 1u)), lo);
-    put((uint32_t)(v >> 32), len - lo);
-  }
-  // Stores the bits still held in acc (a put that completes a dword leaves the
-  // carry in acc until the next put).
-  __device__ __forceinline__ void flush() { slot[min(widx, NW)] = (uint32_t)acc; }
-};
-
-// ---- bit reader over one slot of NW dwords ----------------------------------
-struct BitReader {
-  const uint32_t *slot;
-  int NW;
-  uint64_t win;  // dwords wi, wi+1
-  int wi, off;   // bit position = 32*wi + off, 0 <= off < 32
-  __device__ __forceinline__ uint32_t fetch(int i) const {   // 0 past the slot, branch-free
-    const uint32_t v = slot[min(i, NW - 1)];
-    return i < NW ? v : 0u;
-  }
-  __device__ __forceinline__ void init(const uint32_t *s, int nw) {
-    slot = s;
-    NW = nw;
-    wi = 0;
-    off = 0;
-    win = (uint64_t)fetch(0) | ((uint64_t)fetch(1) << 32);
-  }
-  __device__ __forceinline__ int pos() const { return 32 * wi + off; }
-  // the next 32 bits of the stream (lowest = next bit)
-  __device__ __forceinline__ uint32_t peek() const { return (uint32_t)(win >> off); }
-  __device__ __forceinline__ void advance(int len) {  // off + len < 64
-    off += len;
-    const bool f = off >= 32;
-    const uint32_t nxt = fetch(wi + 2);
-    off -= f ? 32 : 0;
-    wi += f ? 1 : 0;
-    win = f ? ((win >> 32) | ((uint64_t)nxt << 32)) : win;
-  }
-  __device__ __forceinline__ uint32_t get(int len) {  // 1 <= len <= 32
-    uint32_t v = (uint32_t)(win >> off) & (uint32_t)(len >= 32 ? 0xFFFFFFFFu : ((1u << len) - 1u));
-    advance(len);
-    return v;
-  }
-  __device__ __forceinline__ uint64_t get64(int len) {  // 0 <= len <= 64
-    if (len == 0) return 0;
-    if (len > 32) {
-      uint64_t lo = get(32);
-      return lo | ((uint64_t)get(len - 32) << 32);
-    }
-    return get(len);
-  }
-  // Consumes a run of zeros and the 1 ending it; returns the run length, or
-  // -1 if no 1 appears within `limit` bits (the stream was cut by the budget).
-  __device__ __forceinline__ int zero_run(int limit) {
-    int run = 0;
-    for (;;) {
-      uint32_t w = (uint32_t)(win >> off);
-      if (w) {
-        int c = __builtin_ctz(w);
-        if (run + c >= limit) return -1;
-        advance(c + 1);
-        return run + c;
-      }
-      run += 32;
-      advance(32);
-      if (run >= limit) return -1;
-    }
-  }
-};
-
-// ---- slot staging through LDS ----------------------------------------------------
-// A workgroup's slots are one contiguous range of global memory; they move
-// between global memory and LDS with coalesced dword accesses, and each lane
-// reads / writes its own slot in LDS at a padded stride of NW + 1 dwords so
-// that the per-lane sequential accesses spread over the LDS banks.
-__device__ __forceinline__ uint32_t div_magic(int nw) {  // floor(2^32 / nw) + 1
-  return (uint32_t)(0xFFFFFFFFu / (uint32_t)nw) + 1u;
-}
-__device__ __forceinline__ uint32_t lds_index(uint32_t i, int nw, uint32_t magic) {
-  const uint32_t slot = __umulhi(i, magic);   // exact floor(i / nw) for i * nw < 2^32
-  return i + slot;                            // slot * (nw + 1) + (i - slot * nw)
-}
-
 extern __shared__ uint32_t lds_slots[];
-
-// ---- encoder ------------------------------------------------------------------
-// Codes the block whose first value is at `base` (rows of 4 floats, row pitch
-// nx, plane pitch nx*ny) into the lane's own LDS slot `my` of 2R + 1 zeroed
-// dwords; returns true if the block holds an infinity or NaN.
-__device__ __forceinline__ bool encode_block(const float *__restrict__ base, int64_t nx, int64_t ny,
-                                             int R, uint32_t *my) {
-  const int NW = 2 * R;        // dwords per slot
-  const int BITS = 64 * R;     // slot bits
-
-  // load and take the block apart into sign / exponent / mantissa
-  uint32_t raw[64];
-#pragma unroll
-  for (int k = 0; k < 4; k++)
-#pragma unroll
-    for (int j = 0; j < 4; j++) {
-      float4 v = *reinterpret_cast<const float4 *>(base + (k * ny + j) * nx);
-      raw[16 * k + 4 * j + 0] = __float_as_uint(v.x);
-      raw[16 * k + 4 * j + 1] = __float_as_uint(v.y);
-      raw[16 * k + 4 * j + 2] = __float_as_uint(v.z);
-      raw[16 * k + 4 * j + 3] = __float_as_uint(v.w);
-    }
-  // block exponent: the largest exponent field, taken in place (bits 23..30)
-  // so that no per-value exponent stays live until the quantisation below
-  uint32_t emax = 0;
-#pragma unroll
-  for (int t = 0; t < 64; t++) emax = max(emax, raw[t] & 0x7F800000u);
-  const bool bad = emax == 0x7F800000u;   // an infinity or NaN in the block
-  const uint32_t Eb = max(emax >> 23, 1u);
-  int32_t q[64];
-#pragma unroll
-  for (int t = 0; t < 64; t++) {
-    uint32_t E = (raw[t] >> 23) & 255u;
-    uint32_t M = E ? ((raw[t] & 0x7FFFFFu) | 0x800000u) : (raw[t] & 0x7FFFFFu);
-    uint32_t sh = Eb - max(E, 1u);
-    uint32_t mag = sh >= 27u ? 0u : ((M << 3) >> sh);
-    q[t] = (raw[t] >> 31) ? -(int32_t)mag : (int32_t)mag;
-  }
-  xform_fwd(q);
-  // reorder + negabinary, split in halves for the plane transpose
-  uint32_t lo[32], hi[32];
-#pragma unroll
-  for (int p = 0; p < 32; p++) {
-    lo[p] = ((uint32_t)q[kSeq.at[p]] + 0xAAAAAAAAu) ^ 0xAAAAAAAAu;
-    hi[p] = ((uint32_t)q[kSeq.at[p + 32]] + 0xAAAAAAAAu) ^ 0xAAAAAAAAu;
-  }
-  bit_transpose32(lo);
-  bit_transpose32(hi);
-  // finish the transposes here: left to itself the compiler sinks their last
-  // stages into the plane loop, which keeps more intermediate words live than
-  // the 64 plane words (155 VGPRs, three waves per SIMD instead of four)
-#pragma unroll
-  for (int p = 0; p < 32; p++) {
-    asm volatile("" : "+v"(lo[p]));
-    asm volatile("" : "+v"(hi[p]));
-  }
-
-  BitWriter w;
-  w.NW = NW;
-  w.slot = my;
-  w.acc = 0;
-  w.nacc = 0;
-  w.widx = 0;
-  w.put(Eb, 8);
-  int n = 0;
-#pragma unroll
-  for (int p = 31; p >= 0; p--) {
-    if (w.pos() < BITS) {
-      const uint64_t x = (uint64_t)lo[p] | ((uint64_t)hi[p] << 32);
-      w.put64(x & lowmask64(n), n);
-      if (n < 64) {
-        uint64_t rest = x >> n;
-        while (rest && w.pos() < BITS) {
-          int tz = __builtin_ctzll(rest);
-          // group test 1, then tz zeros and the set bit
-          if (tz < 31) {
-            uint32_t v = 1u | (2u << tz);
-            int len = tz + 2;
-            n += tz + 1;
-            rest >>= tz + 1;
-            // the next token in the same 32-bit put when it fits (bits past
-            // the budget only ever reach the slot's padding dword)
-            if (rest) {
-              const int tz2 = __builtin_ctzll(rest);
-              if (len + tz2 + 2 <= 32) {
-                v |= (1u | (2u << tz2)) << len;
-                len += tz2 + 2;
-                n += tz2 + 1;
-                rest >>= tz2 + 1;
-              }
-            }
-            w.put(v, len);
-            continue;
-          } else if (tz < 62) {
-            w.put64(1ull | (2ull << tz), tz + 2);
-          } else {
-            w.put(1u, 1);
-            w.put64(1ull << tz, tz + 1);
-          }
-          n += tz + 1;
-          rest = (tz + 1 < 64) ? (rest >> (tz + 1)) : 0ull;
-        }
-        if (n < 64) w.put(0u, 1);            // group test: nothing left
-      }
-    }
-  }
-  w.flush();
-  return bad;
-}
 
 __global__ __launch_bounds__(256) void k_encode(const float *__restrict__ in, int64_t nx, int64_t ny,
                                                 int64_t nbx, int64_t nby, int64_t nblocks, int R,
@@ -493,7 +144,11 @@ struct ErrSums {
 };
 
 // One kernel body for two modes (kept as one function so that the decoder's
-// register allocation is that of a plain kernel):
+// register allocation is that of a plain kernel; for the same reason the
+// block decoder is written out here rather than called as decode_block(),
+// which compiles to 97 VGPRs in this kernel against 91, one wave per SIMD
+// fewer, and ran 37 % slower in the bench job; the fused kernel calls decode_block(), and
+// its tests require the two to give the same codes' values bit for bit):
 //  - decode (ROUNDTRIP = false): the workgroup's code slots are staged from
 //    `in` into LDS, decoded, and the values stored to `out`;
 //  - round trip (ROUNDTRIP = true): each lane encodes its block of the FP32
@@ -667,6 +322,253 @@ __global__ __launch_bounds__(256) void k_decode_t(const uint32_t *__restrict__ i
 int codec_threads(int rate) { return rate > 16 ? 128 : 256; }
 size_t codec_lds_bytes(int rate, int threads) { return (size_t)threads * (size_t)(2 * rate + 1) * 4u; }
 
+// ---- fused decode -> K 7-point steps -> encode, one launch per slab --------
+// The three kernels of a coded residency (decode after the copy-in, k stencil
+// steps, encode before the copy-back; Sec. 1, Sec. 3.1, Sec. 4.2) in one
+// kernel with no full-size working buffer: a workgroup owns an xy tile of the
+// slab and marches its block layers in z, holding decoded planes and finished
+// output planes only in LDS.  Its eight waves take fixed roles for the whole
+// launch, one step per block layer, one workgroup barrier per step:
+//   waves 0-1  decode block layer t of the input tile (16 x 8 blocks, one lane
+//              per block) into a two-layer LDS ring of FP32 planes;
+//   waves 4-7  run the K-level wavefront over layer t-1's four planes: level s
+//              makes plane z - s from level s-1's planes z-s-1 .. z-s+1, kept
+//              in a three-plane register window per level; x neighbours by DPP
+//              lane shifts, and each wave carries K extra rows on either side
+//              of its 6 output rows so that no row crosses between waves
+//              within a step; level K goes to a three-layer LDS output ring;
+//   waves 2-3  encode the output layer the stencil finished in an earlier step
+//              (14 x 6 blocks: the tile minus its one-block halo).
+// Codes move between global memory and LDS with per-wave coalesced copies.
+// The output tile is block aligned, so its codes are bit-identical to those of
+// the decode / stencil / encode kernels on the same slab: same decoder and
+// encoder, same per-cell operation order (star7_point), zero outside the grid.
+constexpr int FZ_IBX = 16, FZ_IBY = 8;                    // input tile, blocks
+constexpr int FZ_OBX = FZ_IBX - 2, FZ_OBY = FZ_IBY - 2;   // output tile, blocks
+constexpr int FZ_ICX = 4 * FZ_IBX, FZ_ICY = 4 * FZ_IBY;   // 64 x 32 cells
+constexpr int FZ_OCX = 4 * FZ_OBX, FZ_OCY = 4 * FZ_OBY;   // 56 x 24 cells
+constexpr int FZ_DEC = 2, FZ_ENC = 2, FZ_ST = 4, FZ_WAVES = FZ_DEC + FZ_ENC + FZ_ST;
+constexpr int FZ_SROWS = FZ_OCY / FZ_ST;                   // output rows per stencil wave
+constexpr int FZ_EROWS = FZ_OBY / FZ_ENC;                  // output block rows per encode wave
+constexpr int FZ_RING = 3;                                 // output layers held in LDS
+constexpr int FZ_L0 = 2 * 4 * FZ_ICY * FZ_ICX;             // floats: two decoded layers
+constexpr int FZ_OUT = FZ_RING * 4 * FZ_OCY * FZ_OCX;      // floats: the output ring
+constexpr int FZ_DSLOTS = FZ_DEC * 64;
+constexpr int FZ_ESLOTS = FZ_OBX * FZ_OBY;
+static_assert(FZ_DEC * 64 == FZ_IBX * FZ_IBY, "one decode lane per input block");
+static_assert(FZ_EROWS * FZ_OBX <= 64, "one encode lane per output block");
+
+size_t fused_lds_bytes(int R) {
+  return 4u * (size_t)(FZ_L0 + FZ_OUT) + 4u * (size_t)(FZ_DSLOTS + FZ_ESLOTS) * (size_t)(2 * R + 1);
+}
+
+struct FusedArgs {
+  const uint32_t *in;   // slot codes: local block layer l at in + l * lw
+  uint32_t *out;        // output codes: layer m at out + m * lw
+  int64_t lw;           // dwords per coded layer (nbx * nby * 2R)
+  int nx, ny, nbx, nby, R;
+  int lay_lo, lay_hi;   // slot layers holding codes; the others lie outside the grid (zero)
+  int nl;               // slot layers (S + 2h) / 4
+  int out_l0, out_nl;   // local layer of output layer 0 (h / 4); output layers (S / 4)
+  int gz0, nz;          // global z of local plane 0; grid depth
+  int ntx, nty;         // tiles
+  oc::Star7Coef c;
+};
+
+// LDS accesses of one wave take effect in issue order; this only keeps the
+// compiler from moving the wave's later LDS reads above its earlier writes
+// (another lane's slot data written by the same wave).
+__device__ __forceinline__ void wave_lds_order() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ void fz_decode_role(const FusedArgs &a, int tx, int ty, int w, int lane, int T,
+                                               float *L0, uint32_t *DSL) {
+  const int NW = 2 * a.R;
+  const uint32_t magic = div_magic(NW);
+  const int bx0 = tx * FZ_OBX - 1, by0 = ty * FZ_OBY - 1;   // the tile's first input block
+  const int bxl = lane & 15, byl = 4 * w + (lane >> 4);
+  const int bx = bx0 + bxl, by = by0 + byl;
+  const bool xy_in = bx >= 0 && bx < a.nbx && by >= 0 && by < a.nby;
+  const int cx_lo = max(bx0, 0), cx_hi = min(bx0 + FZ_IBX, a.nbx);
+  uint32_t *my = DSL + (64 * w + lane) * (NW + 1);
+  for (int t = 0; t < T; t++) {
+    if (t < a.nl) {
+      const bool lay_in = t >= a.lay_lo && t < a.lay_hi;
+      if (lay_in) {
+        // this wave's four block rows of the layer: a contiguous run of slots
+        // per row, copied coalesced into the lanes' LDS slots
+        for (int r = 0; r < 4; r++) {
+          const int gby = by0 + 4 * w + r;
+          if (gby < 0 || gby >= a.nby || cx_hi <= cx_lo) continue;
+          const uint32_t *src = a.in + (int64_t)t * a.lw + ((int64_t)gby * a.nbx + cx_lo) * NW;
+          const int n = (cx_hi - cx_lo) * NW;
+          const int s0 = 64 * w + 16 * r + (cx_lo - bx0);
+          for (int i = lane; i < n; i += 64) {
+            const int sl = (int)__umulhi((uint32_t)i, magic);   // i / NW
+            DSL[(s0 + sl) * (NW + 1) + (i - sl * NW)] = src[i];
+          }
+        }
+        wave_lds_order();
+      }
+      float *dst = L0 + (t & 1) * (4 * FZ_ICY * FZ_ICX) + (4 * byl) * FZ_ICX + 4 * bxl;
+      if (lay_in && xy_in) {
+        int32_t q[64];
+        const int e = decode_block(my, a.R, q) - 153;
+#pragma unroll
+        for (int k = 0; k < 4; k++)
+#pragma unroll
+          for (int j = 0; j < 4; j++) {
+            float4 v;
+            v.x = ldexpf((float)q[16 * k + 4 * j + 0], e);
+            v.y = ldexpf((float)q[16 * k + 4 * j + 1], e);
+            v.z = ldexpf((float)q[16 * k + 4 * j + 2], e);
+            v.w = ldexpf((float)q[16 * k + 4 * j + 3], e);
+            *reinterpret_cast<float4 *>(dst + (k * FZ_ICY + j) * FZ_ICX) = v;
+          }
+      } else {
+        const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+        for (int k = 0; k < 4; k++)
+#pragma unroll
+          for (int j = 0; j < 4; j++) *reinterpret_cast<float4 *>(dst + (k * FZ_ICY + j) * FZ_ICX) = z4;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+__device__ __forceinline__ void fz_encode_role(const FusedArgs &a, int tx, int ty, int ew, int lane, int T,
+                                               const float *OUT, uint32_t *ESL) {
+  const int NW = 2 * a.R;
+  const uint32_t magic = div_magic(NW);
+  const bool act = lane < FZ_EROWS * FZ_OBX;
+  const int la = act ? lane : 0;
+  const int oxl = la % FZ_OBX, oyl = FZ_EROWS * ew + la / FZ_OBX;
+  const int bx = tx * FZ_OBX + oxl, by = ty * FZ_OBY + oyl;
+  const bool mine = act && bx < a.nbx && by < a.nby;
+  uint32_t *my = ESL + (FZ_EROWS * FZ_OBX * ew + la) * (NW + 1);
+  const int ncols = min(FZ_OBX, a.nbx - tx * FZ_OBX);
+  for (int t = 0; t < T; t++) {
+    const int m = t - (a.out_l0 + 3);   // the output layer the stencil finished a step ago
+    if (m >= 0 && m < a.out_nl) {
+      if (mine) {
+        for (int i = 0; i <= NW; i++) my[i] = 0u;
+        const float *base = OUT + (m % FZ_RING) * (4 * FZ_OCY * FZ_OCX) + (4 * oyl) * FZ_OCX + 4 * oxl;
+        if (encode_block(base, FZ_OCX, FZ_OCY, a.R, my)) atomicOr(&g_oc_codec_err, 1);
+      }
+      wave_lds_order();
+      for (int r = 0; r < FZ_EROWS; r++) {
+        const int gby = ty * FZ_OBY + FZ_EROWS * ew + r;
+        if (gby >= a.nby) continue;
+        uint32_t *dst = a.out + (int64_t)m * a.lw + ((int64_t)gby * a.nbx + tx * FZ_OBX) * NW;
+        const int n = ncols * NW;
+        const int s0 = FZ_EROWS * FZ_OBX * ew + FZ_OBX * r;
+        for (int i = lane; i < n; i += 64) {
+          const int sl = (int)__umulhi((uint32_t)i, magic);
+          dst[i] = ESL[(s0 + sl) * (NW + 1) + (i - sl * NW)];
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <int K>
+__device__ __forceinline__ void fz_stencil_role(const FusedArgs &a, int tx, int ty, int sw, int lane, int T,
+                                                const float *L0, float *OUT) {
+  constexpr int NR0 = FZ_SROWS + 2 * K;   // rows of level 0; level s has NR0 - 2s
+  const int X = lane;
+  const int gx = tx * FZ_OCX - 4 + X;
+  const bool x_in = gx >= 0 && gx < a.nx;
+  const bool x_out = X >= 4 && X < 4 + FZ_OCX;
+  const int y0 = 4 + FZ_SROWS * sw;            // first output row of this wave (tile rows)
+  const int gy0 = ty * FZ_OCY - 4 + y0;
+  const int out_z0 = 4 * a.out_l0, out_z1 = out_z0 + 4 * a.out_nl;
+  // win[s][i][r]: level s, planes (oldest, middle, newest), row y0 - (K - s) + r
+  float win[K][3][NR0];
+#pragma unroll
+  for (int s = 0; s < K; s++)
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+      for (int r = 0; r < NR0; r++) win[s][i][r] = 0.0f;
+  for (int t = 0; t < T; t++) {
+    if (t >= 1 && t <= a.nl) {
+      const int l = t - 1;
+      const float *src = L0 + (l & 1) * (4 * FZ_ICY * FZ_ICX) + (y0 - K) * FZ_ICX + X;
+#pragma unroll
+      for (int c = 0; c < 4; c++) {
+        const int z = 4 * l + c;
+#pragma unroll
+        for (int r = 0; r < NR0; r++) {
+          win[0][0][r] = win[0][1][r];
+          win[0][1][r] = win[0][2][r];
+          win[0][2][r] = src[(c * FZ_ICY + r) * FZ_ICX];
+        }
+#pragma unroll
+        for (int s = 1; s <= K; s++) {
+          const int nr = NR0 - 2 * s;
+          const int gq = a.gz0 + z - s;
+          const bool p_in = x_in && gq >= 0 && gq < a.nz;
+          float nv[NR0];
+#pragma unroll
+          for (int r = 0; r < nr; r++) {
+            const float cur = win[s - 1][1][r + 1];
+            const float v = star7_point(a.c.c0, cur, lane_from_left(cur), lane_from_right(cur),
+                                        win[s - 1][1][r], win[s - 1][1][r + 2], win[s - 1][0][r + 1],
+                                        win[s - 1][2][r + 1], a.c);
+            const int gy = gy0 - (K - s) + r;
+            nv[r] = (p_in && gy >= 0 && gy < a.ny) ? v : 0.0f;
+          }
+          if (s < K) {
+#pragma unroll
+            for (int r = 0; r < nr; r++) {
+              win[s][0][r] = win[s][1][r];
+              win[s][1][r] = win[s][2][r];
+              win[s][2][r] = nv[r];
+            }
+          } else {
+            const int q = z - K;
+            if (q >= out_z0 && q < out_z1 && x_out) {
+              const int m = (q - out_z0) >> 2, pl = (q - out_z0) & 3;
+              float *o = OUT + ((m % FZ_RING) * 4 + pl) * (FZ_OCY * FZ_OCX) + (FZ_SROWS * sw) * FZ_OCX + (X - 4);
+#pragma unroll
+              for (int r = 0; r < FZ_SROWS; r++) o[r * FZ_OCX] = nv[r];
+            }
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <int K>
+__global__ __launch_bounds__(64 * FZ_WAVES) void k_codec_star7(FusedArgs a) {
+  const int tile = (int)blockIdx.x;
+  if (tile >= a.ntx * a.nty) return;   // uniform over the workgroup
+  const int tx = tile % a.ntx, ty = tile / a.ntx;
+  const int w = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+  const int lane = (int)threadIdx.x & 63;
+  float *L0 = reinterpret_cast<float *>(lds_slots);
+  float *OUT = L0 + FZ_L0;
+  uint32_t *DSL = reinterpret_cast<uint32_t *>(OUT + FZ_OUT);
+  uint32_t *ESL = DSL + FZ_DSLOTS * (2 * a.R + 1);
+  // steps: layer t is decoded in step t, stepped in step t + 1; output layer
+  // m is finished in step out_l0 + m + 2 and encoded in the next one.  Every
+  // wave runs all T steps, each ending in the one workgroup barrier.
+  const int T = max(a.nl + 1, a.out_l0 + a.out_nl + 3);
+  if (w < FZ_DEC)
+    fz_decode_role(a, tx, ty, w, lane, T, L0, DSL);
+  else if (w < FZ_DEC + FZ_ENC)
+    fz_encode_role(a, tx, ty, w - FZ_DEC, lane, T, OUT, ESL);
+  else
+    fz_stencil_role<K>(a, tx, ty, w - FZ_DEC - FZ_ENC, lane, T, L0, OUT);
+}
+
 }  // namespace
 
 namespace oc {
@@ -726,6 +628,59 @@ hipError_t launch_diff_error(const float *ref, const float *x, int64_t n, double
   hipLaunchKernelGGL(k_diff_err, dim3((unsigned)nparts), dim3(256), 0, s, (const float4 *)ref,
                      (const float4 *)x, n4, parts);
   hipLaunchKernelGGL(k_reduce_parts, dim3(1), dim3(256), 0, s, (const double *)parts, nparts, d_out3);
+  return hipGetLastError();
+}
+
+size_t codec_star7_lds_bytes(int rate) { return fused_lds_bytes(rate); }
+
+hipError_t launch_codec_star7(const void *in, void *out, int64_t nx, int64_t ny, int rate, int64_t lay_lo,
+                              int64_t lay_hi, int64_t nl, int64_t out_l0, int64_t out_nl, int64_t gz0,
+                              int64_t nz, int levels, const Star7Coef &c, hipStream_t s, KernelTimer *kt) {
+  if (rate < 1 || rate > kCodecStar7MaxRate || levels < 1 || levels > 4) return hipErrorInvalidValue;
+  if (nx <= 0 || ny <= 0 || nx % 4 || ny % 4 || out_l0 < 1 || 4 * out_l0 < levels || out_nl < 1 ||
+      nl != out_nl + 2 * out_l0 || lay_lo < 0 || lay_hi > nl || lay_lo > lay_hi)
+    return hipErrorInvalidValue;
+  if (nx > (1 << 28) || ny > (1 << 28) || nl > (1 << 24) || gz0 < -(1 << 28) || gz0 > (1 << 28) ||
+      nz > (1 << 28))
+    return hipErrorInvalidValue;
+  const int64_t nbx = nx / 4, nby = ny / 4;
+  const int64_t ntx = (nbx + FZ_OBX - 1) / FZ_OBX, nty = (nby + FZ_OBY - 1) / FZ_OBY;
+  if (ntx * nty > 0x7fffffff) return hipErrorInvalidValue;
+  FusedArgs a;
+  a.in = (const uint32_t *)in;
+  a.out = (uint32_t *)out;
+  a.lw = nbx * nby * 2 * rate;
+  a.nx = (int)nx;
+  a.ny = (int)ny;
+  a.nbx = (int)nbx;
+  a.nby = (int)nby;
+  a.R = rate;
+  a.lay_lo = (int)lay_lo;
+  a.lay_hi = (int)lay_hi;
+  a.nl = (int)nl;
+  a.out_l0 = (int)out_l0;
+  a.out_nl = (int)out_nl;
+  a.gz0 = (int)gz0;
+  a.nz = (int)nz;
+  a.ntx = (int)ntx;
+  a.nty = (int)nty;
+  a.c = c;
+  const size_t lds = fused_lds_bytes(rate);
+  const dim3 grid((unsigned)(ntx * nty)), block(64 * FZ_WAVES);
+  switch (levels) {
+    case 1:
+      hipExtLaunchKernelGGL(k_codec_star7<1>, grid, block, lds, s, kt_start(kt), kt_stop(kt), 0, a);
+      break;
+    case 2:
+      hipExtLaunchKernelGGL(k_codec_star7<2>, grid, block, lds, s, kt_start(kt), kt_stop(kt), 0, a);
+      break;
+    case 3:
+      hipExtLaunchKernelGGL(k_codec_star7<3>, grid, block, lds, s, kt_start(kt), kt_stop(kt), 0, a);
+      break;
+    default:
+      hipExtLaunchKernelGGL(k_codec_star7<4>, grid, block, lds, s, kt_start(kt), kt_stop(kt), 0, a);
+      break;
+  }
   return hipGetLastError();
 }
 

@@ -22,25 +22,12 @@
 #include <algorithm>
 
 #include "oc_kernels.h"
+#include "stencil_dev.h"
 
 namespace {
 
 constexpr int TX = 64, TY = 4, ZC = 16;
 constexpr int NXCD = 8;    // XCDs on MI355X: workgroups are dealt to them round-robin
-
-// One cell update in a fixed operation order, shared by every kernel here so
-// that fused and single-step launches give bit-identical results.
-__device__ __forceinline__ float star7_point(float c0, float cur, float xm, float xp, float ym,
-                                             float yp, float zm, float zp, const oc::Star7Coef &c) {
-  float r = c0 * cur;
-  r = fmaf(c.cmx, xm, r);
-  r = fmaf(c.cpx, xp, r);
-  r = fmaf(c.cmy, ym, r);
-  r = fmaf(c.cpy, yp, r);
-  r = fmaf(c.cmz, zm, r);
-  r = fmaf(c.cpz, zp, r);
-  return r;
-}
 
 // XCD-aware tile number of workgroup b among nb tiles: workgroup b runs on
 // XCD b % 8; each XCD gets a contiguous run of tiles.
@@ -111,14 +98,6 @@ __global__ __launch_bounds__(TX *TY) void k_star7(const float *__restrict__ in, 
 // is read.
 constexpr int FW = 8, RY = 4, FTY = FW * RY;
 constexpr int kFusedTargetWgs = 512;   // workgroups a fused launch aims for (z chunks)
-
-// DPP wave shifts by one lane; the lane with no source reads zero (bound_ctrl)
-__device__ __forceinline__ float lane_from_left(float v) {    // value of lane - 1
-  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x138, 0xf, 0xf, true));
-}
-__device__ __forceinline__ float lane_from_right(float v) {   // value of lane + 1
-  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x130, 0xf, 0xf, true));
-}
 
 // One 7-point step with four consecutive x per lane, for rows of whole,
 // 16-byte aligned float4s (nx % 4 == 0): a wave covers 256 contiguous x of a

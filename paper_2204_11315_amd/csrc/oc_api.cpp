@@ -152,6 +152,7 @@ oc::PlanInput plan_input(const oc_grid *g, const oc_stencil *st, const oc_config
   in.fuse = c->fuse_steps ? c->fuse_steps : oc::kMaxFused;
   in.share = c->share_overlap >= 0;
   in.in_place = c->in_place != 0;
+  in.fused_codec = c->fused_codec != 0;
   return in;
 }
 
@@ -168,7 +169,8 @@ void drain(oc_handle *h) {
   for (int i = 0; i < 3; i++) (void)hipStreamSynchronize(h->s[i]);
 }
 
-enum TimedKind { T_DEC, T_STENCIL, T_ENC, T_H2D, T_D2H, T_NONE };
+enum TimedKind { T_DEC, T_STENCIL, T_ENC, T_H2D, T_D2H, T_FUSED, T_NONE };
+constexpr int kTimedKinds = T_NONE;
 
 TimedKind timed_kind(const oc::Op &o) {
   switch (o.type) {
@@ -178,6 +180,7 @@ TimedKind timed_kind(const oc::Op &o) {
     case oc::OP_ENC: return T_ENC;
     case oc::OP_H2D: return T_H2D;
     case oc::OP_D2H: return T_D2H;
+    case oc::OP_FUSED: return T_FUSED;
     default: return T_NONE;
   }
 }
@@ -280,6 +283,17 @@ int issue(oc_handle *h, const std::vector<oc::Op> &ops, const oc::Plan &p) {
       case oc::OP_ZERO:
         x.ok(hipMemsetAsync(h->arena + o.dev_dst, 0, (size_t)o.bytes, s));
         break;
+      case oc::OP_FUSED: {
+        const int64_t nl = o.planes / 4, out_l0 = p.halo / 4;
+        x.ok(oc::launch_codec_star7(h->arena + o.dev_src, h->arena + o.dev_dst, p.in.nx, p.in.ny, p.in.rate,
+                                    o.z_lo, o.z_hi, nl, out_l0, nl - 2 * out_l0, o.gz0, p.in.nz, o.levels, c,
+                                    s, kt));
+        const uint64_t out_layers = (uint64_t)(nl - 2 * out_l0);
+        bdec += blocks_per_layer * (uint64_t)(o.z_hi - o.z_lo);
+        benc += blocks_per_layer * out_layers;
+        cells += (uint64_t)o.levels * out_layers * 4u * (uint64_t)p.in.nx * (uint64_t)p.in.ny;
+        break;
+      }
       case oc::OP_AXPY:
         x.ok(oc::launch_axpy_prod((float *)(h->arena + o.dev_dst), (const float *)(h->arena + o.dev_src),
                                   (const float *)(h->arena + o.dev_src2), (size_t)o.bytes / 4u, s, kt));
@@ -343,8 +357,8 @@ int issue(oc_handle *h, const std::vector<oc::Op> &ops, const oc::Plan &p) {
   h->stats.bytes_stencil = sbytes;
   h->stats.blocks_decode = bdec;
   h->stats.blocks_encode = benc;
-  double ms[5] = {0, 0, 0, 0, 0};
-  uint64_t n[5] = {0, 0, 0, 0, 0};
+  double ms[kTimedKinds] = {};
+  uint64_t n[kTimedKinds] = {};
   if (x.st == OC_OK && h->timing) {
     for (const auto &t : timed) {
       float e = 0.f;
@@ -363,6 +377,8 @@ int issue(oc_handle *h, const std::vector<oc::Op> &ops, const oc::Plan &p) {
   h->stats.n_encode = n[T_ENC];
   h->stats.n_h2d = n[T_H2D];
   h->stats.n_d2h = n[T_D2H];
+  h->stats.ms_fused = ms[T_FUSED];
+  h->stats.n_fused = n[T_FUSED];
   if (x.st != OC_OK) {
     drain(h);
     h->broken = true;
@@ -457,6 +473,35 @@ int encode_field(oc_handle *h, const float *src, uint8_t *dst, int rate, int64_t
   return codec_check_and_clear();
 }
 
+// Device buffers oc_load / oc_store stage a coded field through: two FP32
+// chunks (`work`) and their codes (`stage`); returns the chunk in planes.
+// Three-kernel plans use the working buffers and staging slots 0 and 1 (P
+// planes per chunk); fused plans, which have no FP32 buffers, carve the
+// chunks from the arena: the largest multiple of 4 planes whose two FP32
+// chunks and two code chunks fit it (the planner sizes the arena for >= 4).
+int64_t io_buffers(const oc_handle *h, uint8_t *work[2], uint8_t *stage[2]) {
+  const oc::Plan &p = h->plan;
+  if (!p.fused) {
+    work[0] = h->arena + p.off_work[0][0];
+    work[1] = h->arena + (p.n_work_sets == 1 ? p.off_work[0][1] : p.off_work[1][0]);
+    stage[0] = h->arena + p.off_stage[0];
+    stage[1] = h->arena + p.off_stage[1];
+    return std::max<int64_t>(4, p.P / 4 * 4);
+  }
+  auto up = [](size_t v) { return (v + 255) & ~(size_t)255; };
+  auto need = [&](int64_t c) {
+    return 2u * up((size_t)c * p.plane_bytes) + 2u * up((size_t)(c / 4) * p.layer_bytes);
+  };
+  int64_t c = 4;
+  while (c + 4 <= (p.in.nz + 3) / 4 * 4 && need(c + 4) <= p.arena_bytes) c += 4;
+  const size_t fb = up((size_t)c * p.plane_bytes), cb = up((size_t)(c / 4) * p.layer_bytes);
+  work[0] = h->arena;
+  work[1] = h->arena + fb;
+  stage[0] = h->arena + 2 * fb;
+  stage[1] = h->arena + 2 * fb + cb;
+  return c;
+}
+
 // Loads a host FP32 field into host store `dst`: a copy, or codes at the
 // plan's rate made on the GPU through the plan's first working and staging
 // buffers.
@@ -466,12 +511,8 @@ int load_field(oc_handle *h, const float *src, uint8_t *dst, bool coded) {
     par_bytes(dst, src, p.plane_bytes * (size_t)p.in.nz);
     return OC_OK;
   }
-  // two buffer pairs: working buffers a and b of the shared set (or of the
-  // first two slots), staging slots 0 and 1
-  uint8_t *const work[2] = {h->arena + p.off_work[0][0],
-                            h->arena + (p.n_work_sets == 1 ? p.off_work[0][1] : p.off_work[1][0])};
-  uint8_t *const stage[2] = {h->arena + p.off_stage[0], h->arena + p.off_stage[1]};
-  const int64_t chunk = std::max<int64_t>(4, p.P / 4 * 4);
+  uint8_t *work[2], *stage[2];
+  const int64_t chunk = io_buffers(h, work, stage);
   // level 0 receives the codes; level 1 holds nothing yet
   return encode_field(h, src, dst, p.in.rate, chunk, work, stage, bounce_region(h, 1, chunk));
 }
@@ -489,10 +530,8 @@ int store_field(oc_handle *h, const uint8_t *src, float *dst, bool coded) {
     return OC_OK;
   }
   Exec x{h};
-  const int64_t chunk = std::max<int64_t>(4, p.P / 4 * 4);
-  uint8_t *const work[2] = {h->arena + p.off_work[0][0],
-                            h->arena + (p.n_work_sets == 1 ? p.off_work[0][1] : p.off_work[1][0])};
-  uint8_t *const stage[2] = {h->arena + p.off_stage[0], h->arena + p.off_stage[1]};
+  uint8_t *work[2], *stage[2];
+  const int64_t chunk = io_buffers(h, work, stage);
   uint8_t *const bounce = bounce_region(h, 1 - h->cur, chunk);
   const size_t half = (size_t)chunk * pb;
   hipEvent_t ev[6] = {};   // per buffer pair: codes in, decoded, copied out
@@ -1486,7 +1525,7 @@ int64_t check_plan_impl(const oc_grid *g, const oc_stencil *st, const oc_config 
   } else if (mutate == 2) {  // drop the epilogue: everything after the last kernel
     size_t last = 0;
     for (size_t j = 0; j < ops.size(); j++)
-      if (ops[j].type == oc::OP_STAR7 || ops[j].type == oc::OP_WAVE) last = j;
+      if (ops[j].type == oc::OP_STAR7 || ops[j].type == oc::OP_WAVE || ops[j].type == oc::OP_FUSED) last = j;
     ops.erase(ops.begin() + (ptrdiff_t)last + 1, ops.end() - 1);
   } else if (mutate == 3) {  // swap op i with the next op of the same stream
     if (i < 0 || (size_t)i >= ops.size() || ops[(size_t)i].stream < 0) return OC_ERR_ARG;

@@ -57,6 +57,21 @@ struct Star7Coef {
   float c0, cmx, cpx, cmy, cpy, cmz, cpz;
 };
 
+// One coded slab residency in one launch: decode the slot's block layers,
+// `levels` (1..4) 7-point steps with constant coefficients, encode the
+// interior.  in: local block layers [0, nl) of the slab (layers outside
+// [lay_lo, lay_hi) are outside the grid and read as zero planes); out: the
+// out_nl interior layers, starting at local layer out_l0 (the halo, >= 1
+// layer and >= levels planes); nl = out_nl + 2 * out_l0.  The codes equal
+// those of launch_decode, launch_star7_multi and launch_encode on the same
+// slab.  Needs codec_star7_lds_bytes(rate) of LDS per workgroup.
+constexpr int kCodecStar7MaxRate = 16;
+size_t codec_star7_lds_bytes(int rate);
+hipError_t launch_codec_star7(const void *in, void *out, int64_t nx, int64_t ny, int rate, int64_t lay_lo,
+                              int64_t lay_hi, int64_t nl, int64_t out_l0, int64_t out_nl, int64_t gz0,
+                              int64_t nz, int levels, const Star7Coef &c, hipStream_t s,
+                              KernelTimer *kt = nullptr);
+
 // One 7-point step on a slab buffer of `planes` planes whose local plane 0 is
 // global plane gz0: writes local planes [z_lo, z_hi) of out from in.  Cells
 // outside the global grid [0,nx) x [0,ny) x [0,nz) read as zero.  c0f

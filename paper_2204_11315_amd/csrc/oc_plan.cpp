@@ -53,6 +53,19 @@ static size_t carve(Plan *p) {
   p->P = p->S + 2 * p->halo;
   p->work_bytes = align256((size_t)p->P * p->plane_bytes);
   size_t off = 0;
+  if (p->fused) {
+    // slots of input codes + interior codes; the arena also has to hold the
+    // two FP32 chunks of at least 4 planes (and their codes) that oc_load and
+    // oc_store stage through it
+    p->fused_out = align256((size_t)(p->P / 4) * p->layer_bytes);
+    p->stage_bytes = p->fused_out + align256((size_t)(p->S / 4) * p->layer_bytes);
+    for (int s = 0; s < p->slots; s++) {
+      p->off_stage[s] = off;
+      off += p->stage_bytes;
+    }
+    const size_t io = 2u * align256(4u * p->plane_bytes) + 2u * align256(p->layer_bytes);
+    return std::max(off, io);
+  }
   for (int s = 0; s < p->n_work_sets; s++)
     for (int b = 0; b < p->n_work_bufs; b++) {
       p->off_work[s][b] = off;
@@ -105,6 +118,13 @@ int make_plan(const PlanInput &in, Plan *out) {
   p.prefetch = in.prefetch < 0 ? in.slots - 1 : in.prefetch;
   p.r = stencil_radius(in.kind);
   p.coded = in.rate > 0;
+  if (in.fused_codec) {
+    // the fused kernel: coded 7-point runs with constant coefficients, up to
+    // four steps per residency (one block layer of halo), rates its LDS holds
+    if (!p.coded || in.kind != KIND_STAR7 || in.c0_field || in.k > kMaxFused || in.rate > kFusedMaxRate)
+      return ST_UNSUPPORTED;
+    p.fused = true;
+  }
   if (p.coded && (in.nx % 4 || in.ny % 4 || in.nz % 4)) return ST_SHAPE;
   if (p.coded && in.slab_planes % 4) return ST_SHAPE;
   if (in.nx > (int64_t)1 << 30 || in.ny > (int64_t)1 << 30 || in.nz > (int64_t)1 << 30)
@@ -456,6 +476,24 @@ void build_ops(const Plan &p, int64_t sweeps, int steps_last, int src, int64_t s
       }
       B.rec(S_COMPUTE, B.ev.shr(x.pq));
     }
+    if (p.fused) {
+      // one kernel: the slot's codes in, the interior's codes out past them
+      Op o = B.blank(OP_FUSED, S_COMPUTE);
+      o.dev_src = (int64_t)p.off_stage[x.q];
+      o.dev_dst = (int64_t)(p.off_stage[x.q] + p.fused_out);
+      o.z_lo = x.loc0 / 4;
+      o.z_hi = (x.loc0 + x.nload) / 4;
+      o.bytes = (int64_t)((size_t)(x.nz_int / 4) * p.layer_bytes);
+      o.levels = x.ks;
+      o.gz0 = x.sl->gz0;
+      o.planes = x.sl->planes;
+      o.slab = x.j;
+      o.sweep = x.t;
+      B.push(o);
+      res[0] = res[1] = 0;
+      B.rec(S_COMPUTE, B.ev.out(x.q));
+      return;
+    }
     int ncoded = 0;
     for (int f = 0; f < nin; f++) {
       if (fin[f].coded) {
@@ -576,7 +614,11 @@ void build_ops(const Plan &p, int64_t sweeps, int steps_last, int src, int64_t s
     for (int f = 0; f < p.n_rw; f++) {
       Op o = B.blank(OP_D2H, S_OUT);
       o.host_id = (int8_t)x.dstl;
-      if (p.coded) {
+      if (p.fused) {
+        o.dev_src = (int64_t)(p.off_stage[x.q] + p.fused_out);
+        o.host_off = (int64_t)((size_t)(x.sl->z0 / 4) * p.layer_bytes);
+        o.bytes = (int64_t)((size_t)(x.nz_int / 4) * p.layer_bytes);
+      } else if (p.coded) {
         o.dev_src = (int64_t)(p.off_stage[x.q] + (size_t)f * (size_t)(x.sl->planes / 4) * p.layer_bytes);
         o.host_off = (int64_t)((size_t)f * p.host_field_bytes + (size_t)(x.sl->z0 / 4) * p.layer_bytes);
         o.bytes = (int64_t)((size_t)(x.nz_int / 4) * p.layer_bytes);
@@ -961,7 +1003,7 @@ void build_adjoint_ops(const AdjPlan &a, int lsrc, std::vector<Op> *ops) {
 
 std::string dump_ops(const std::vector<Op> &ops) {
   static const char *names[] = {"H2D", "D2H", "DEC", "ENC", "STAR7", "WAVE", "AXPY", "REC", "WAIT", "SYNC",
-                                "ZERO"};
+                                "ZERO", "FUSED"};
   std::string out;
   char line[256];
   for (size_t i = 0; i < ops.size(); i++) {
@@ -1019,6 +1061,11 @@ void accesses(const Plan &p, const Op &o, std::vector<Access> *a) {
       break;
     }
     case OP_ZERO:
+      dev(o.dev_dst, o.bytes, true);
+      break;
+    case OP_FUSED:
+      // reads the slot's coded layers, writes the interior's codes
+      dev(o.dev_src + o.z_lo * (int64_t)p.layer_bytes, (o.z_hi - o.z_lo) * (int64_t)p.layer_bytes, false);
       dev(o.dev_dst, o.bytes, true);
       break;
     case OP_AXPY:

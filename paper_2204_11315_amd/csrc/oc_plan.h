@@ -31,7 +31,10 @@ enum OpType : uint8_t {
   OP_REC,    // record event ev on stream
   OP_WAIT,   // stream waits for the latest record of ev
   OP_SYNC,   // host waits for every stream (end of a run)
-  OP_ZERO    // dev_dst[0, bytes) = 0 on the op's stream
+  OP_ZERO,   // dev_dst[0, bytes) = 0 on the op's stream
+  OP_FUSED   // coded slab in one kernel: dev_src = slot codes (local layer 0),
+             // layers [z_lo, z_hi) hold codes; decode, `levels` 7-point steps,
+             // encode the interior (`bytes` of codes) into dev_dst
 };
 
 struct Op {
@@ -72,6 +75,7 @@ struct PlanInput {
   int fuse = 4;           // STAR7: time steps per stencil launch (1..kMaxFused)
   bool share = false;     // keep the overlap of consecutive slabs on the device
   bool in_place = false;  // one host level, updated in place (needs sharing or one slab)
+  bool fused_codec = false;  // coded STAR7: one decode / k steps / encode kernel per slab
 };
 
 constexpr int kMaxSlots = 8;
@@ -100,6 +104,10 @@ struct Plan {
   int n_work_bufs = 2;
   size_t stage_bytes = 0;  // one coded staging buffer
   size_t off_stage[kMaxSlots] = {};
+  // fused codec: no working buffers; a slot holds the slab's input codes and,
+  // at byte fused_out of the slot, the codes of its interior
+  bool fused = false;
+  size_t fused_out = 0;
   size_t off_ro_stage[kMaxSlots] = {};  // STAR7 raw c0 slab per ring slot (single working buffer)
   // WAVE25 raw with region sharing: per slot, the 2h planes of p^n and
   // p^{n-1} the next slab shares, set aside before the leapfrog overwrites them
@@ -114,7 +122,9 @@ struct Plan {
 };
 
 // Status codes mirror include/oc.h.
-constexpr int ST_OK = 0, ST_ARG = -1, ST_SHAPE = -2, ST_BUDGET = -3;
+constexpr int ST_OK = 0, ST_ARG = -1, ST_SHAPE = -2, ST_BUDGET = -3, ST_UNSUPPORTED = -7;
+// Highest rate the fused codec kernel takes (its LDS use grows with the rate).
+constexpr int kFusedMaxRate = 16;
 
 int stencil_radius(int kind);
 size_t coded_layer_bytes(int64_t nx, int64_t ny, int rate);

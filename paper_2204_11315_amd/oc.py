@@ -49,7 +49,8 @@ class Config(ctypes.Structure):
                 ("ring_slots", ctypes.c_int32), ("prefetch", ctypes.c_int32),
                 ("fuse_steps", ctypes.c_int32), ("copy_back", ctypes.c_int32),
                 ("share_overlap", ctypes.c_int32), ("in_place", ctypes.c_int32),
-                ("error_budget", ctypes.c_float), ("error_steps", ctypes.c_int32)]
+                ("error_budget", ctypes.c_float), ("error_steps", ctypes.c_int32),
+                ("fused_codec", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -69,7 +70,8 @@ class Stats(ctypes.Structure):
                 ("host_ms_kernels", ctypes.c_double), ("host_ms_copies", ctypes.c_double),
                 ("host_ms_events", ctypes.c_double), ("host_ms_sync", ctypes.c_double),
                 ("rate_bits", ctypes.c_int64), ("pilot_rel_l2", ctypes.c_double),
-                ("pilot_planes", ctypes.c_int64), ("pilot_runs", ctypes.c_int64)]
+                ("pilot_planes", ctypes.c_int64), ("pilot_runs", ctypes.c_int64),
+                ("ms_fused", ctypes.c_double), ("n_fused", ctypes.c_uint64)]
 
 
 _lock = threading.Lock()
@@ -189,7 +191,7 @@ def host_aux_bytes(shape, stencil: Stencil, rate: int) -> int:
 def plan_config(k: int, slab_planes: int, rate: int, single_buffer: bool = True,
                 budget: int = 0, ring_slots: int = 0, prefetch: int = 0, fuse: int = 0,
                 share: bool = False, in_place: bool = False, error_budget: float = 0.0,
-                error_steps: int = 0) -> Config:
+                error_steps: int = 0, fused_codec: bool = False) -> Config:
     """A Config carrying only the plan fields."""
     cfg = Config()
     cfg.k = int(k)
@@ -204,28 +206,29 @@ def plan_config(k: int, slab_planes: int, rate: int, single_buffer: bool = True,
     cfg.in_place = 1 if in_place else 0
     cfg.error_budget = float(error_budget)
     cfg.error_steps = int(error_steps)
+    cfg.fused_codec = 1 if fused_codec else 0
     return cfg
 
 
 def plan_bytes(shape, stencil: Stencil, k: int, slab_planes: int, rate: int,
                single_buffer: bool = True, budget: int = 0, ring_slots: int = 0,
                prefetch: int = 0, fuse: int = 0, share: bool = False,
-               error_budget: float = 0.0, error_steps: int = 0) -> int:
+               error_budget: float = 0.0, error_steps: int = 0, fused_codec: bool = False) -> int:
     """Device bytes of the plan (with an error budget: at least the pilot's
     sample within `budget`)."""
     g = make_grid(shape)
     cfg = plan_config(k, slab_planes, rate, single_buffer, budget, ring_slots, prefetch, fuse, share,
-                      error_budget=error_budget, error_steps=error_steps)
+                      error_budget=error_budget, error_steps=error_steps, fused_codec=fused_codec)
     return int(lib().oc_plan_bytes(_ref(g), _ref(stencil), _ref(cfg)))
 
 
 def check_plan(shape, stencil: Stencil, k: int, slab_planes: int, rate: int, sweeps: int,
                single_buffer: bool = True, budget: int = 0, mutate: int = 0, i: int = 0,
                ring_slots: int = 0, prefetch: int = 0, fuse: int = 0, share: bool = False,
-               in_place: bool = False) -> int:
+               in_place: bool = False, fused_codec: bool = False) -> int:
     g = make_grid(shape)
     cfg = plan_config(k, slab_planes, rate, single_buffer, budget, ring_slots, prefetch, fuse, share,
-                      in_place)
+                      in_place, fused_codec=fused_codec)
     return int(lib().oc_debug_check_plan(_ref(g), _ref(stencil), _ref(cfg), int(sweeps),
                                          int(mutate), int(i)))
 
@@ -245,10 +248,10 @@ def check_plan_ckpt(shape, stencil: Stencil, k: int, slab_planes: int, sweeps: i
 def plan_ops(shape, stencil: Stencil, k: int, slab_planes: int, rate: int, sweeps: int,
              single_buffer: bool = True, budget: int = 0, ring_slots: int = 0, prefetch: int = 0,
              fuse: int = 0, share: bool = False,
-             in_place: bool = False):
+             in_place: bool = False, fused_codec: bool = False):
     g = make_grid(shape)
     cfg = plan_config(k, slab_planes, rate, single_buffer, budget, ring_slots, prefetch, fuse, share,
-                      in_place)
+                      in_place, fused_codec=fused_codec)
     nw = ctypes.c_int64(0)
     n = int(lib().oc_debug_plan_ops(_ref(g), _ref(stencil), _ref(cfg), int(sweeps), _ref(nw)))
     return n, int(nw.value)
@@ -257,11 +260,11 @@ def plan_ops(shape, stencil: Stencil, k: int, slab_planes: int, rate: int, sweep
 def plan_dump(shape, stencil: Stencil, k: int, slab_planes: int, rate: int, sweeps: int,
               single_buffer: bool = True, budget: int = 0, ring_slots: int = 0,
               prefetch: int = 0, fuse: int = 0, share: bool = False,
-              in_place: bool = False) -> str:
+              in_place: bool = False, fused_codec: bool = False) -> str:
     """Text listing of the operation list the executor would issue."""
     g = make_grid(shape)
     cfg = plan_config(k, slab_planes, rate, single_buffer, budget, ring_slots, prefetch, fuse, share,
-                      in_place)
+                      in_place, fused_codec=fused_codec)
     n = int(lib().oc_debug_plan_dump(_ref(g), _ref(stencil), _ref(cfg), int(sweeps), None, 0))
     if n < 0:
         raise OCError(n, "oc_debug_plan_dump", status_str(n))
@@ -459,7 +462,7 @@ class OutOfCore:
                  timing: bool = False, ring_slots: int = 0, prefetch: int = 0, device=None,
                  stencil: Stencil = None, fuse: int = 0, copy_back: int = 0, share: bool = True,
                  in_place: bool = False, full_arena: bool = False, error_budget: float = 0.0,
-                 error_steps: int = 0):
+                 error_steps: int = 0, fused_codec: bool = False):
         torch = _torch()
         self.shape = tuple(int(v) for v in shape)
         self.rate = int(rate)
@@ -470,8 +473,13 @@ class OutOfCore:
         self.device = torch.device(device if device is not None else "cuda")
         need = plan_bytes(self.shape, self.stencil, k, slab_planes, rate, single_buffer, budget,
                           ring_slots, prefetch, fuse, share, error_budget=error_budget,
-                          error_steps=error_steps)
+                          error_steps=error_steps, fused_codec=fused_codec)
         if need == 0:
+            if fused_codec and not (rate > 0 and self.stencil.kind == OC_STAR7 and not c0_field
+                                    and k <= 4 and rate <= 16):
+                raise OCError(OC_ERR_UNSUPPORTED, "plan",
+                              "the fused codec kernel needs a coded 7-point run with constant c0, "
+                              "k <= 4 and rate <= 16")
             raise OCError(OC_ERR_BUDGET, "plan", "no slab depth fits the budget")
         # the plan's bytes fit `budget`; planning again with exactly those bytes
         # as the budget picks the same slab depth (plan bytes grow with it)
@@ -506,6 +514,7 @@ class OutOfCore:
         cfg.in_place = 1 if in_place else 0
         cfg.error_budget = float(error_budget)
         cfg.error_steps = int(error_steps)
+        cfg.fused_codec = 1 if fused_codec else 0
         self.cfg = cfg
         h = ctypes.c_void_p()
         torch.cuda.synchronize(self.device)

@@ -44,19 +44,29 @@ def sample_points():
     return pts
 
 
-@pytest.mark.parametrize("R,tol", [(0, 1e-5), (16, 1e-3)])
-def test_fullsize_sampled_vs_oracle(u0, R, tol):
-    o = oc.OutOfCore(SHAPE, k=4, rate=R, budget=512 << 20, slab_planes=64)
+def run_full(u0, R, fused=False):
+    o = oc.OutOfCore(SHAPE, k=4, rate=R, budget=512 << 20, slab_planes=64, fused_codec=fused)
     try:
         o.load(u0)
         o.run(STEPS)
-        got = o.store()
-        st = o.stats()
+        return o.store(), o.stats()
     finally:
         o.close()
+
+
+# R = 8 is the smallest rate within 1e-3 over the full grid (9.3e-4, measured
+# by the benchmark); on 12 sampled cells the bar is looser
+@pytest.mark.parametrize("R,tol", [(0, 1e-5), (16, 1e-4), (8, 3e-3)])
+def test_fullsize_sampled_vs_oracle(u0, R, tol):
+    got, st = run_full(u0, R)
     pts = sample_points()
     want = sampled_reference(u0, pts, STEPS)
     have = np.array([got[p] for p in pts], dtype=np.float64)
     assert np.linalg.norm(have - want) <= tol * np.linalg.norm(want)
     assert st["n_slabs"] == 32 and st["slab_visits"] == 32 * 16
-    assert st["peak_dev_bytes"] == (432 << 20 if R == 0 else 252 << 20)
+    assert st["peak_dev_bytes"] == {0: 432 << 20, 16: 252 << 20, 8: 198 << 20}[R]
+    if R == 8:
+        # the fused codec kernel at full size: the same output, 102 MiB
+        fused, sf = run_full(u0, R, fused=True)
+        assert np.array_equal(fused.view(np.uint32), got.view(np.uint32))
+        assert sf["peak_dev_bytes"] == 102 << 20 and sf["n_slabs"] == 32
