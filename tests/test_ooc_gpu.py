@@ -89,17 +89,29 @@ def test_compressed_ooc_equals_incore_composition_bitwise(R, swb, k, S, steps):
     assert np.array_equal(got.view(np.uint32), want.view(np.uint32))
 
 
-@pytest.mark.parametrize("R", [16, 8])
-def test_compressed_ooc_close_to_oracle_composition(R):
-    u0 = inputs.grf_field(SHAPE, seed=8)
-    got, _ = run_ooc(u0, 12, k=4, rate=R, slab_planes=8)
-    want = oracle.compressed_sweeps(u0, C, 12, 4, R)
-    ref64 = oracle.star7_run(u0, C, 12)
-    # FP32 stencil vs FP64 stencil only moves codes within the codec's own
-    # error, so the two compositions agree to about that error
-    e_codec = rel_l2(want, ref64)
-    assert rel_l2(got, want) <= max(2 * e_codec, 1e-6)
-    assert abs(rel_l2(got, ref64) - e_codec) <= 0.5 * e_codec + 1e-7
+@pytest.mark.parametrize("R", [16, 12, 8])
+@pytest.mark.parametrize("shape,S,seed", [(SHAPE, 8, 8), (SHAPE, 8, 9), ((64, 64, 64), 16, 8)])
+def test_compressed_ooc_close_to_oracle_composition(R, shape, S, seed):
+    # 10 steps at k = 4: two residencies of 4 steps and a short one of 2
+    steps, k = 10, 4
+    u0 = inputs.grf_field(shape, seed=seed)
+    got, _ = run_ooc(u0, steps, k=k, rate=R, slab_planes=S)
+    want = oracle.compressed_sweeps(u0, C, steps, k, R)
+    ref64 = oracle.star7_run(u0, C, steps)
+    e_comp = rel_l2(want, ref64)
+    # The GPU steps in FP32 and the oracle in FP64 rounded to FP32 once per
+    # residency: inputs to each re-encode differ by a few ulp, which changes a
+    # block's codes only where a digit at the budget's cut flips; such a flip
+    # costs about the block's codec error.  The expected squared difference
+    # is then ~ (flip probability ~ ulp / codec error) x (codec error)^2 per
+    # residency: rel-L2 ~ sqrt(n_res * 2^-24 * e_comp), bounded with a factor
+    # of 10 (measured at 0.05-0.6 of the bound at R = 8, 12 and 16).
+    n_res = -(-steps // k)
+    assert rel_l2(got, want) <= 10.0 * np.sqrt(n_res * 2.0 ** -24 * e_comp)
+    if R == 16:
+        assert rel_l2(got, want) <= 1e-5
+    # and the job's error against FP64 is the composition's, to that bound
+    assert abs(rel_l2(got, ref64) - e_comp) <= 10.0 * np.sqrt(n_res * 2.0 ** -24 * e_comp)
 
 
 def test_compressed_r16_meets_error_bar():

@@ -48,11 +48,14 @@ def gpu_incore(p0, pm1, vel, st, n0, steps):
 
 
 def test_incore_vs_fp64_oracle():
+    # the FP32 leapfrog against FP64: 1.3e-6 after 20 steps (growing from
+    # 5e-8 after one step, about linearly in the step count), inside the
+    # 1e-5 bar of the uncompressed path
     vel, dt, st, p0, pm1 = setup()
     cur, prev = gpu_incore(p0, pm1, vel, st, 0, 20)
     rp, rc = oracle.wave25_run(pm1, p0, vel, H, dt, SRC, F, T0, 0, 20)
-    assert rel_l2(cur, rc) < 2e-5
-    assert rel_l2(prev, rp) < 2e-5
+    assert rel_l2(cur, rc) < 1e-5
+    assert rel_l2(prev, rp) < 1e-5
 
 
 def test_source_only_first_step_matches_oracle():
@@ -153,4 +156,4 @@ def test_four_x_kernel_equals_one_x_kernel_bitwise(shape, src):
         assert np.array_equal(wc.cpu().numpy().view(np.uint32), mc.cpu().numpy().view(np.uint32))
         assert np.array_equal(wp.cpu().numpy().view(np.uint32), mp.cpu().numpy().view(np.uint32))
     rp, rc = oracle.wave25_run(pm1, p0, vel, H, dt, src, F, T0, 0, 6)
-    assert rel_l2(wc.cpu().numpy(), rc) < 2e-5
+    assert rel_l2(wc.cpu().numpy(), rc) < 1e-5
