@@ -261,6 +261,7 @@ __device__ __forceinline__ uint32_t lds_index(uint32_t i, int nw, uint32_t magic
 // Codes the block whose first value is at `base` (rows of 4 floats, row pitch
 // nx, plane pitch nx*ny) into the lane's own LDS slot `my` of 2R + 1 zeroed
 // dwords; returns true if the block holds an infinity or NaN.
+template <bool ROLLED = false>
 __device__ __forceinline__ bool encode_block(const float *__restrict__ base, int64_t nx, int64_t ny,
                                              int R, uint32_t *my) {
   const int NW = 2 * R;        // dwords per slot
@@ -321,8 +322,9 @@ __device__ __forceinline__ bool encode_block(const float *__restrict__ base, int
   w.widx = 0;
   w.put(Eb, 8);
   int n = 0;
-#pragma unroll
-  for (int p = 31; p >= 0; p--) {
+  // one bit plane; `plane` is the plane index
+  auto code_plane = [&](int plane) __attribute__((always_inline)) {
+    const int p = plane;
     if (w.pos() < BITS) {
       const uint64_t x = (uint64_t)lo[p] | ((uint64_t)hi[p] << 32);
       w.put64(x & lowmask64(n), n);
@@ -361,6 +363,15 @@ __device__ __forceinline__ bool encode_block(const float *__restrict__ base, int
         if (n < 64) w.put(0u, 1);            // group test: nothing left
       }
     }
+  };
+  if constexpr (ROLLED) {
+    // one loop body (the plane words indexed by the uniform plane number):
+    // small code, for kernels whose waves run other code beside the coder
+#pragma unroll 1
+    for (int p = 31; p >= 0; p--) code_plane(p);
+  } else {
+#pragma unroll
+    for (int p = 31; p >= 0; p--) code_plane(p);
   }
   w.flush();
   return bad;
@@ -383,7 +394,10 @@ __device__ __forceinline__ int decode_block(const uint32_t *slot, int R, int32_t
   // where the budget ended the stream: plane cut_p, with the digits of
   // coefficients [0, cut_m) of that plane read (cut_p = -1: every plane read)
   int cut_p = -1, cut_m = 0;
-#pragma unroll
+  // one loop body (plane words indexed by the uniform plane number): the
+  // fused kernel's decode waves run beside encode and stencil waves, and a
+  // fully unrolled decoder alone is larger than the instruction cache
+#pragma unroll 1
   for (int p = 31; p >= 0; p--) {
     uint64_t x = 0;
     if (!done) {

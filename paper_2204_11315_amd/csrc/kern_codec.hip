@@ -384,6 +384,12 @@ __device__ __forceinline__ void wave_lds_order() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// dwords of one block row's slots per lane (16 blocks x 2R dwords / 64 lanes,
+// R <= kCodecStar7MaxRate)
+constexpr int FZ_CPL = (FZ_IBX * 2 * oc::kCodecStar7MaxRate + 63) / 64;
+// the same for one output block row (14 blocks)
+constexpr int FZ_EPL = (FZ_OBX * 2 * oc::kCodecStar7MaxRate + 63) / 64;
+
 __device__ __forceinline__ void fz_decode_role(const FusedArgs &a, int tx, int ty, int w, int lane, int T,
                                                float *L0, uint32_t *DSL) {
   const int NW = 2 * a.R;
@@ -393,28 +399,56 @@ __device__ __forceinline__ void fz_decode_role(const FusedArgs &a, int tx, int t
   const int bx = bx0 + bxl, by = by0 + byl;
   const bool xy_in = bx >= 0 && bx < a.nbx && by >= 0 && by < a.nby;
   const int cx_lo = max(bx0, 0), cx_hi = min(bx0 + FZ_IBX, a.nbx);
+  const int n = max(cx_hi - cx_lo, 0) * NW;   // dwords of one block row's slots
   uint32_t *my = DSL + (64 * w + lane) * (NW + 1);
+  // This wave's four block rows of a layer are four contiguous runs of
+  // slots.  The codes of layer t + 1 are loaded into registers while layer t
+  // is decoded (coalesced dwords, all loads in flight together) and moved
+  // into the lanes' LDS slots at the start of the next step.
+  uint32_t buf[4][FZ_CPL];
+  auto row_ok = [&](int r) {
+    const int gby = by0 + 4 * w + r;
+    return gby >= 0 && gby < a.nby && n > 0;
+  };
+  auto lay_in = [&](int t) { return t >= a.lay_lo && t < a.lay_hi; };
+  auto load_layer = [&](int t) {
+#pragma unroll
+    for (int r = 0; r < 4; r++) {
+      const uint32_t *src = a.in + (int64_t)t * a.lw + ((int64_t)(by0 + 4 * w + r) * a.nbx + cx_lo) * NW;
+      const bool ok = row_ok(r);
+#pragma unroll
+      for (int j = 0; j < FZ_CPL; j++) {
+        const int i = lane + 64 * j;
+        buf[r][j] = (ok && i < n) ? src[i] : 0u;
+      }
+    }
+  };
+  auto store_layer = [&]() {
+#pragma unroll
+    for (int r = 0; r < 4; r++) {
+      const bool ok = row_ok(r);
+      const int s0 = 64 * w + 16 * r + (cx_lo - bx0);
+#pragma unroll
+      for (int j = 0; j < FZ_CPL; j++) {
+        const int i = lane + 64 * j;
+        if (ok && i < n) {
+          const int sl = (int)__umulhi((uint32_t)i, magic);   // i / NW
+          DSL[(s0 + sl) * (NW + 1) + (i - sl * NW)] = buf[r][j];
+        }
+      }
+    }
+  };
+  if (a.nl > 0 && lay_in(0)) load_layer(0);
   for (int t = 0; t < T; t++) {
     if (t < a.nl) {
-      const bool lay_in = t >= a.lay_lo && t < a.lay_hi;
-      if (lay_in) {
-        // this wave's four block rows of the layer: a contiguous run of slots
-        // per row, copied coalesced into the lanes' LDS slots
-        for (int r = 0; r < 4; r++) {
-          const int gby = by0 + 4 * w + r;
-          if (gby < 0 || gby >= a.nby || cx_hi <= cx_lo) continue;
-          const uint32_t *src = a.in + (int64_t)t * a.lw + ((int64_t)gby * a.nbx + cx_lo) * NW;
-          const int n = (cx_hi - cx_lo) * NW;
-          const int s0 = 64 * w + 16 * r + (cx_lo - bx0);
-          for (int i = lane; i < n; i += 64) {
-            const int sl = (int)__umulhi((uint32_t)i, magic);   // i / NW
-            DSL[(s0 + sl) * (NW + 1) + (i - sl * NW)] = src[i];
-          }
-        }
+      if (lay_in(t)) {
+        store_layer();
         wave_lds_order();
       }
+      if (t + 1 < a.nl && lay_in(t + 1)) load_layer(t + 1);
+      const bool have = lay_in(t) && xy_in;
       float *dst = L0 + (t & 1) * (4 * FZ_ICY * FZ_ICX) + (4 * byl) * FZ_ICX + 4 * bxl;
-      if (lay_in && xy_in) {
+      if (have) {
         int32_t q[64];
         const int e = decode_block(my, a.R, q) - 153;
 #pragma unroll
@@ -457,19 +491,28 @@ __device__ __forceinline__ void fz_encode_role(const FusedArgs &a, int tx, int t
       if (mine) {
         for (int i = 0; i <= NW; i++) my[i] = 0u;
         const float *base = OUT + (m % FZ_RING) * (4 * FZ_OCY * FZ_OCX) + (4 * oyl) * FZ_OCX + 4 * oxl;
-        if (encode_block(base, FZ_OCX, FZ_OCY, a.R, my)) atomicOr(&g_oc_codec_err, 1);
+        if (encode_block<true>(base, FZ_OCX, FZ_OCY, a.R, my)) atomicOr(&g_oc_codec_err, 1);
       }
       wave_lds_order();
+      // this wave's block rows of the output layer: contiguous runs of
+      // slots, copied out coalesced (every LDS read of a row issued first)
+      const int n = ncols * NW;
+#pragma unroll
       for (int r = 0; r < FZ_EROWS; r++) {
         const int gby = ty * FZ_OBY + FZ_EROWS * ew + r;
         if (gby >= a.nby) continue;
         uint32_t *dst = a.out + (int64_t)m * a.lw + ((int64_t)gby * a.nbx + tx * FZ_OBX) * NW;
-        const int n = ncols * NW;
         const int s0 = FZ_EROWS * FZ_OBX * ew + FZ_OBX * r;
-        for (int i = lane; i < n; i += 64) {
+        uint32_t v[FZ_EPL];
+#pragma unroll
+        for (int j = 0; j < FZ_EPL; j++) {
+          const int i = lane + 64 * j;
           const int sl = (int)__umulhi((uint32_t)i, magic);
-          dst[i] = ESL[(s0 + sl) * (NW + 1) + (i - sl * NW)];
+          v[j] = i < n ? ESL[(s0 + sl) * (NW + 1) + (i - sl * NW)] : 0u;
         }
+#pragma unroll
+        for (int j = 0; j < FZ_EPL; j++)
+          if (lane + 64 * j < n) dst[lane + 64 * j] = v[j];
       }
     }
     __syncthreads();
@@ -499,7 +542,9 @@ __device__ __forceinline__ void fz_stencil_role(const FusedArgs &a, int tx, int 
     if (t >= 1 && t <= a.nl) {
       const int l = t - 1;
       const float *src = L0 + (l & 1) * (4 * FZ_ICY * FZ_ICX) + (y0 - K) * FZ_ICX + X;
-#pragma unroll
+      // one loop body for the layer's four planes (the windows move by
+      // register copies): the three roles' code together must stay small
+#pragma unroll 1
       for (int c = 0; c < 4; c++) {
         const int z = 4 * l + c;
 #pragma unroll
