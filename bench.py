@@ -220,7 +220,11 @@ ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # 256 MiB device copy) over the algorithmic bytes, read and write weighted by
 # their algorithmic bytes.
 KERNEL_COUNTERS = {
-    ("stencil", None): {"traffic": 1.195,
+    ("decode", 8): {"traffic": 1.011, "valu_per_wave": 6736, "active_lanes": 0.460,
+                    "source": "profiles/codec_stencil_kernels_slab_512x512x72.md"},
+    ("encode", 8): {"traffic": 1.010, "valu_per_wave": 5830, "active_lanes": 0.642,
+                    "source": "profiles/codec_stencil_kernels_slab_512x512x72.md"},
+    ("stencil", None): {"traffic": 1.194,
                         "source": "profiles/codec_stencil_kernels_slab_512x512x72.md"},
 }
 

@@ -56,11 +56,20 @@ __global__ __launch_bounds__(256) void k_encode(const float *__restrict__ in, in
       atomicOr(&g_oc_codec_err, 1);
   }
   __syncthreads();
-  // coalesced copy of the workgroup's slots to global memory
+  // coalesced copy of the workgroup's slots to global memory, eight LDS
+  // reads in flight per thread before their stores
   const uint32_t magic = div_magic(NW);
   uint32_t *dst = out + b0 * NW;
   const uint32_t total = (uint32_t)(nslots * NW);
-  for (uint32_t i = threadIdx.x; i < total; i += blockDim.x) dst[i] = lds_slots[lds_index(i, NW, magic)];
+  uint32_t i = threadIdx.x;
+  for (; i + 7 * blockDim.x < total; i += 8 * blockDim.x) {
+    uint32_t v[8];
+#pragma unroll
+    for (int j = 0; j < 8; j++) v[j] = lds_slots[lds_index(i + j * blockDim.x, NW, magic)];
+#pragma unroll
+    for (int j = 0; j < 8; j++) dst[i + j * blockDim.x] = v[j];
+  }
+  for (; i < total; i += blockDim.x) dst[i] = lds_slots[lds_index(i, NW, magic)];
 }
 
 // ---- workgroup sums of error statistics --------------------------------------
@@ -165,12 +174,22 @@ __global__ __launch_bounds__(256) void k_decode_t(const uint32_t *__restrict__ i
   const int64_t b0 = (int64_t)blockIdx.x * blockDim.x;
   const int64_t b = b0 + threadIdx.x;
   if (!ROUNDTRIP) {
-    // coalesced copy of the workgroup's slots into LDS
+    // coalesced copy of the workgroup's slots into LDS, eight loads in flight
+    // per thread before their LDS stores (every workgroup of a launch starts
+    // with this copy, so its latency is not hidden by other waves' work)
     const int nslots = (int)min<int64_t>(blockDim.x, nblocks - b0);
     const uint32_t magic = div_magic(NW);
     const uint32_t *src = in + b0 * NW;
     const uint32_t total = (uint32_t)(nslots * NW);
-    for (uint32_t i = threadIdx.x; i < total; i += blockDim.x) lds_slots[lds_index(i, NW, magic)] = src[i];
+    uint32_t i = threadIdx.x;
+    for (; i + 7 * blockDim.x < total; i += 8 * blockDim.x) {
+      uint32_t v[8];
+#pragma unroll
+      for (int j = 0; j < 8; j++) v[j] = src[i + j * blockDim.x];
+#pragma unroll
+      for (int j = 0; j < 8; j++) lds_slots[lds_index(i + j * blockDim.x, NW, magic)] = v[j];
+    }
+    for (; i < total; i += blockDim.x) lds_slots[lds_index(i, NW, magic)] = src[i];
     __syncthreads();
     if (b >= nblocks) return;
   }
