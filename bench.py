@@ -410,8 +410,10 @@ def kernel_probe(rate, reps=20):
     18-layer encodes that make the decoder's input are helpers.  The grid is
     evolved through the c0-field stencil kernel (c0 = 0.4 everywhere), a
     separate kernel from the constant-c0 launches probed on the slab: `reps`
-    single steps and `reps` four-step launches over 72 planes.  Last, `reps`
-    plain 256 MiB device copies as the counter reference."""
+    single steps and `reps` four-step launches over 72 planes.  For each
+    state the fused codec kernel also runs on the slab's codes (decode of
+    state t, four steps, encode of state t + 4's interior; rates <= 16).
+    Last, `reps` plain 256 MiB device copies as the counter reference."""
     import torch
     from paper_2204_11315_amd import inputs, oc
     P = S + 2 * 4
@@ -423,6 +425,8 @@ def kernel_probe(rate, reps=20):
     torch.cuda.synchronize()
     for t in range(0, STEPS, K):
         oc.decompress(codes, out.shape, rate, out=out)         # decode, state t
+        if rate <= 16:                                         # fused: decode t, 4 steps, encode t + 4
+            oc.codec_star7(codes, (P, 512, 512), m, P + 2 * m, rate, K)
         v = oc.star7_incore(v, C, K, c0f=c0)
         oc.compress(v[m + 4:m + 4 + S].contiguous(), rate)    # encode, state t + 4
         codes = oc.compress(v[m:m + P].contiguous(), rate)    # helper

@@ -356,6 +356,20 @@ int64_t oc_debug_plan_ops(const oc_grid *g, const oc_stencil *st, const oc_confi
 int oc_debug_copy_to_host(void *host_base, size_t host_off, const void *dev_src, size_t bytes,
                           int32_t workgroups, oc_stream stream);
 
+/* Tuning aid: one launch of the fused codec kernel (oc_config.fused_codec) on
+ * device buffers, for a slab of out_nl interior block layers with one halo
+ * layer on either side: d_in holds the slab's nl = out_nl + 2 layers of codes
+ * at rate_bits (1..16) in the z-major block layout; layers [lay_lo, lay_hi)
+ * are read, the others count as planes outside the grid (zeros); gz0 is the
+ * global z of the slab's first plane (a multiple of 4, lay_lo / lay_hi and
+ * the interior inside [0, nz)).  d_out receives the out_nl interior layers
+ * after `steps` (1..4) 7-point steps with coefficients c[7], bit for bit the
+ * codes of decode, steps and encode.  4-byte aligned device pointers; returns
+ * after the enqueue on `stream`. */
+int oc_debug_codec_star7(const void *d_in, void *d_out, int64_t nx, int64_t ny, int64_t nz, int64_t gz0,
+                         int64_t out_nl, int64_t lay_lo, int64_t lay_hi, int32_t rate_bits, int32_t steps,
+                         const float *c, oc_stream stream);
+
 /* GPU timeline of the last oc_run (timing on): for each timed op, its class
  * (0 decode, 1 stencil, 2 encode, 3 host-to-device, 4 device-to-host), its
  * sweep * 100000 + slab, and its start / end in ms after the first timed op

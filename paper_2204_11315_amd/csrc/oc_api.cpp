@@ -1364,6 +1364,33 @@ int oc_debug_copy_to_host(void *host_base, size_t host_off, const void *dev_src,
   }
 }
 
+int oc_debug_codec_star7(const void *d_in, void *d_out, int64_t nx, int64_t ny, int64_t nz, int64_t gz0,
+                         int64_t out_nl, int64_t lay_lo, int64_t lay_hi, int32_t rate_bits, int32_t steps,
+                         const float *c, oc_stream stream) {
+  try {
+    if (!d_in || !d_out || !c || nx <= 0 || ny <= 0 || nz <= 0 || out_nl < 1) return OC_ERR_ARG;
+    if (((uintptr_t)d_in | (uintptr_t)d_out) & 3) return OC_ERR_ARG;
+    if (nx % 4 || ny % 4 || nz % 4 || gz0 % 4) return OC_ERR_SHAPE;
+    if (rate_bits < 1 || rate_bits > oc::kCodecStar7MaxRate || steps < 1 || steps > 4)
+      return OC_ERR_UNSUPPORTED;
+    const int64_t nl = out_nl + 2;
+    if (lay_lo < 0 || lay_hi > nl || lay_lo > lay_hi) return OC_ERR_ARG;
+    // coded layers must lie inside the grid, the interior too
+    if (gz0 + 4 * lay_lo < 0 || gz0 + 4 * lay_hi > nz || gz0 + 4 < 0 || gz0 + 4 * (1 + out_nl) > nz)
+      return OC_ERR_ARG;
+    const oc::Star7Coef cf{c[0], c[1], c[2], c[3], c[4], c[5], c[6]};
+    hipError_t e = oc::launch_codec_star7(d_in, d_out, nx, ny, rate_bits, lay_lo, lay_hi, nl, 1, out_nl, gz0,
+                                          nz, steps, cf, (hipStream_t)stream);
+    if (e != hipSuccess) {
+      g_last_hip = e;
+      return OC_ERR_HIP;
+    }
+    return OC_OK;
+  } catch (...) {
+    return OC_ERR_HOST;
+  }
+}
+
 int64_t oc_debug_timeline(const oc_handle *h, int32_t *kind, int64_t *slab, double *start_ms,
                           double *end_ms, int64_t cap) {
   try {

@@ -114,6 +114,8 @@ _SIGS = {
     "oc_debug_plan_dump": (_I64, [_P, _P, _P, _I64, ctypes.c_char_p, _SZ]),
     "oc_debug_timeline": (_I64, [_P, _P, _P, _P, _P, _I64]),
     "oc_debug_copy_to_host": (ctypes.c_int, [_P, _SZ, _P, _SZ, _I32, _P]),
+    "oc_debug_codec_star7": (ctypes.c_int, [_P, _P, _I64, _I64, _I64, _I64, _I64, _I64, _I64, _I32, _I32,
+                                            _P, _P]),
 }
 EXPORTED = tuple(_SIGS)
 
@@ -387,6 +389,27 @@ def codec_error_noalloc(d_in, rate: int, out=None, stream=None):
            "oc_codec_error_noalloc")
     torch.cuda.synchronize(d_in.device)
     return tuple(float(v) for v in out.cpu())
+
+
+def codec_star7(codes, shape, gz0: int, nz: int, rate: int, steps: int, c=C_CONFIG1, lay=None, out=None,
+                stream=None):
+    """The fused codec kernel on one slab (tuning aid): `codes` holds the slab's
+    layers (shape = (planes, ny, nx), one halo layer on either side of the
+    interior); returns the interior's codes after `steps` 7-point steps.
+    lay = (lay_lo, lay_hi): the coded layers (default all)."""
+    torch = _torch()
+    planes, ny, nx = shape
+    nl = planes // 4
+    out_nl = nl - 2
+    lb = codec_bytes((4, ny, nx), rate)
+    if out is None:
+        out = torch.empty(out_nl * lb, dtype=torch.uint8, device=codes.device)
+    lo, hi = lay if lay is not None else (0, nl)
+    cc = (ctypes.c_float * 7)(*c)
+    _check(lib().oc_debug_codec_star7(_dev(codes, torch.uint8, "codes"), _dev(out, torch.uint8, "out"), nx, ny,
+                                      int(nz), int(gz0), out_nl, int(lo), int(hi), int(rate), int(steps), cc,
+                                      _stream_handle(stream)), "oc_debug_codec_star7")
+    return out
 
 
 def copy_to_host(host_dst, host_off: int, dev_src, nbytes: int, workgroups: int = 4, stream=None):

@@ -130,3 +130,32 @@ def test_fused_with_an_error_budget_runs_the_picked_rate():
         o.close()
     fixed, _, _ = run(u0, 16, False, k=4, rate=R, slab_planes=16, budget=64 << 20)
     assert np.array_equal(got.view(np.uint32), fixed.view(np.uint32))
+
+
+@pytest.mark.parametrize("R,steps", [(8, 4), (16, 3), (5, 1)])
+def test_fused_kernel_on_one_slab_equals_three_kernels(R, steps):
+    # an interior slab of a ragged grid (120 x 100 cells: partial tiles in x
+    # and y), 16 interior planes and a 4-plane halo on either side
+    nz, ny, nx = 48, 100, 120
+    gz0, planes = 12, 24
+    f = inputs.grf_field((nz, ny, nx), seed=36)
+    slab = torch.from_numpy(np.ascontiguousarray(f[gz0:gz0 + planes])).cuda()
+    codes = oc.compress(slab, R)
+    got = oc.codec_star7(codes, (planes, ny, nx), gz0, nz, R, steps)
+    u = oc.decompress(codes, (planes, ny, nx), R)
+    u = oc.star7_incore(u, C, steps)
+    want = oc.compress(u[4:planes - 4].contiguous(), R)
+    assert torch.equal(got.cpu(), want.cpu())
+    assert oc.codec_status() == oc.OC_OK
+
+
+def test_fused_kernel_entry_checks_its_arguments():
+    t = torch.zeros(1 << 16, dtype=torch.uint8, device="cuda")
+    for kw, st in ((dict(R=17), oc.OC_ERR_UNSUPPORTED), (dict(steps=5), oc.OC_ERR_UNSUPPORTED),
+                   (dict(gz0=2), oc.OC_ERR_SHAPE), (dict(lay=(0, 7)), oc.OC_ERR_ARG),
+                   (dict(gz0=-8), oc.OC_ERR_ARG)):
+        with pytest.raises(oc.OCError) as e:
+            oc.codec_star7(t, (24, 8, 8), kw.get("gz0", 0), 32, kw.get("R", 8), kw.get("steps", 4),
+                           lay=kw.get("lay"), out=t)
+        assert e.value.status == st, kw
+
