@@ -81,6 +81,8 @@ def _load():
             "ocref_decompress": (ctypes.c_int, [P, I64, I64, I64, ctypes.c_int, P]),
             "ocref_fwd_xform": (None, [P]),
             "ocref_inv_xform": (None, [P]),
+            "ocref_fwd_lift_line": (None, [P]),
+            "ocref_inv_lift_line": (None, [P]),
             "ocref_to_negabinary": (ctypes.c_uint32, [ctypes.c_int32]),
             "ocref_from_negabinary": (ctypes.c_int32, [ctypes.c_uint32]),
             "ocref_unread_mean": (ctypes.c_int32, [ctypes.c_int]),
@@ -233,6 +235,19 @@ def inv_xform(q) -> np.ndarray:
     q = np.ascontiguousarray(np.asarray(q, dtype=np.int32).reshape(64)).copy()
     _load().ocref_inv_xform(_ptr(q))
     return q
+
+
+def fwd_lift_line(x) -> np.ndarray:
+    """The transform of one line of four integers (step 4, one axis)."""
+    x = np.ascontiguousarray(np.asarray(x, dtype=np.int32).reshape(4)).copy()
+    _load().ocref_fwd_lift_line(_ptr(x))
+    return x
+
+
+def inv_lift_line(x) -> np.ndarray:
+    x = np.ascontiguousarray(np.asarray(x, dtype=np.int32).reshape(4)).copy()
+    _load().ocref_inv_lift_line(_ptr(x))
+    return x
 
 
 def to_negabinary(c: int) -> int:

@@ -6,11 +6,13 @@
  * The paper compresses each chunk on the GPU before the device-to-host copy and
  * decompresses it after the host-to-device copy (Sec. 1 and Sec. 4.2), at a
  * user-specified fixed rate (Sec. 5: 32 bits per 64-bit value).  It uses a
- * third-party compressor whose format it does not state.  This file defines our
- * own fixed-rate format in the spirit of that compressor's published method
- * (block floating point, an exactly invertible integer decorrelating transform,
- * embedded bit-plane coding with group tests).  Each step below is numbered as
- * in the format definition; nothing is blocked, fused or reordered.
+ * third-party compressor (cuZFP, Sec. 4) and does not restate its format.  This
+ * file defines our own fixed-rate format after that compressor's published
+ * method (Lindstrom, "Fixed-Rate Compressed Floating-Point Arrays", IEEE TVCG
+ * 2014): block floating point, its non-orthogonal integer decorrelating
+ * transform, embedded bit-plane coding with group tests.  Each step below is
+ * numbered as in the format definition; nothing is blocked, fused or
+ * reordered.
  *
  * Format, per 4x4x4 block at R bits per value (1 <= R <= 32):
  *  1. The block owns a slot of B = 64*R bits.  Stream bit j lives in slot byte
@@ -20,9 +22,13 @@
  *     The first 8 stream bits hold Eb.
  *  3. Quantise (integers only): q = (-1)^s ((M << 3) >> (Eb - Ee)), a shift of
  *     27 or more giving 0.  |q| < 2^27.
- *  4. Transform: a two-level integer S-transform (lifting, exactly invertible)
- *     applied to every line along x, then y, then z.  Arithmetic wraps mod 2^32
- *     and >> is a floor (arithmetic) shift.
+ *  4. Transform: along x, then y, then z, every line of four integers is taken
+ *     through the published decorrelating transform, the 4x4 matrix
+ *     A = (1/16) [[4 4 4 4] [5 1 -1 -5] [-4 4 4 -4] [-2 6 -6 2]], computed as
+ *     five lifting steps with floor halvings (see lift_fwd).  The halvings drop
+ *     low bits, so the inverse (lift_inv, the steps undone in reverse order)
+ *     returns the input to within a few units in the last place of the 27-bit
+ *     integers.  Arithmetic wraps mod 2^32 and >> is a floor (arithmetic) shift.
  *  5. Reorder: output position p holds the coefficient whose (i,j,k) sorts p-th
  *     by the key (i+j+k, i^2+j^2+k^2, t).
  *  6. Negabinary: u = (c + 0xAAAAAAAA) ^ 0xAAAAAAAA as 32-bit unsigned.
@@ -53,28 +59,40 @@ static int32_t wadd(int32_t a, int32_t b) { return (int32_t)((uint32_t)a + (uint
 static int32_t wsub(int32_t a, int32_t b) { return (int32_t)((uint32_t)a - (uint32_t)b); }
 
 /* ---- step 4: transform ------------------------------------------------- */
-/* forward lift of one line (a, b, c, d) -> (S, D, d0, d1) */
+/* Forward transform of one line (a, b, c, d) = (x0, x1, x2, x3).  Without the
+ * floors the five steps compute, with s = x0 + x1 + x2 + x3:
+ *   after 1: a = (x0 + x3)/2, d = (x3 - x0)/2
+ *   after 2: c = (x1 + x2)/2, b = (x1 - x2)/2
+ *   after 3: a = s/4,         c = (x1 + x2 - x0 - x3)/4
+ *   after 4: d = (x3 - x0 + x1 - x2)/4, b = (x0 + x1 - x2 - x3)/4
+ *   after 5: d = d + b/2 = (-2x0 + 6x1 - 6x2 + 2x3)/16,
+ *            b = b - d/2 = (5x0 + x1 - x2 - 5x3)/16
+ * so (a, b, c, d) are rows 1, 2, 3 and 4 of A applied to the line. */
 static void lift_fwd(int32_t *a, int32_t *b, int32_t *c, int32_t *d) {
-  int32_t d0 = wsub(*b, *a);
-  int32_t s0 = wadd(*a, asr(d0, 1));
-  int32_t d1 = wsub(*d, *c);
-  int32_t s1 = wadd(*c, asr(d1, 1));
-  int32_t D = wsub(s1, s0);
-  int32_t S = wadd(s0, asr(D, 1));
-  *a = S; *b = D; *c = d0; *d = d1;
+  int32_t x0 = *a, x1 = *b, x2 = *c, x3 = *d;
+  x0 = asr(wadd(x0, x3), 1); x3 = wsub(x3, x0);        /* 1: outer pair */
+  x2 = asr(wadd(x2, x1), 1); x1 = wsub(x1, x2);        /* 2: inner pair */
+  x0 = asr(wadd(x0, x2), 1); x2 = wsub(x2, x0);        /* 3: the two means */
+  x3 = asr(wadd(x3, x1), 1); x1 = wsub(x1, x3);        /* 4: the two differences */
+  x3 = wadd(x3, asr(x1, 1)); x1 = wsub(x1, asr(x3, 1)); /* 5: shear of the differences */
+  *a = x0; *b = x1; *c = x2; *d = x3;
 }
-/* inverse lift: undoes lift_fwd exactly */
+/* Inverse: each step undone, in reverse order.  Step 5 is a pair of shears and
+ * is undone exactly; steps 1-4 replace (u, v) by (m, v - m) with m = (u + v) >> 1,
+ * undone as v = (v - m) + m, u = 2m - v (exact when u + v is even). */
 static void lift_inv(int32_t *a, int32_t *b, int32_t *c, int32_t *d) {
-  int32_t S = *a, D = *b, d0 = *c, d1 = *d;
-  int32_t s0 = wsub(S, asr(D, 1));
-  int32_t s1 = wadd(D, s0);
-  int32_t x2 = wsub(s1, asr(d1, 1));
-  int32_t x3 = wadd(d1, x2);
-  int32_t x0 = wsub(s0, asr(d0, 1));
-  int32_t x1 = wadd(d0, x0);
+  int32_t x0 = *a, x1 = *b, x2 = *c, x3 = *d;
+  x1 = wadd(x1, asr(x3, 1)); x3 = wsub(x3, asr(x1, 1)); /* 5 */
+  x1 = wadd(x1, x3); x3 = wsub(wadd(x3, x3), x1);       /* 4 */
+  x2 = wadd(x2, x0); x0 = wsub(wadd(x0, x0), x2);       /* 3 */
+  x1 = wadd(x1, x2); x2 = wsub(wadd(x2, x2), x1);       /* 2 */
+  x3 = wadd(x3, x0); x0 = wsub(wadd(x0, x0), x3);       /* 1 */
   *a = x0; *b = x1; *c = x2; *d = x3;
 }
 static int tix(int i, int j, int k) { return i + 4 * j + 16 * k; }
+
+void ocref_fwd_lift_line(int32_t *x) { lift_fwd(&x[0], &x[1], &x[2], &x[3]); }
+void ocref_inv_lift_line(int32_t *x) { lift_inv(&x[0], &x[1], &x[2], &x[3]); }
 
 void ocref_fwd_xform(int32_t *q) {
   for (int k = 0; k < 4; k++)           /* along x */

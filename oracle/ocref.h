@@ -70,6 +70,9 @@ int ocref_decompress(const uint8_t *in, int64_t nx, int64_t ny, int64_t nz, int 
 /* sub-steps, exported so that tests can pin each one */
 void ocref_fwd_xform(int32_t *q);
 void ocref_inv_xform(int32_t *q);
+/* the transform of one line of four integers, forward and inverse */
+void ocref_fwd_lift_line(int32_t *x);
+void ocref_inv_lift_line(int32_t *x);
 uint32_t ocref_to_negabinary(int32_t c);
 int32_t ocref_from_negabinary(uint32_t u);
 /* floor((1 - (-2)^d) / 6), 0 <= d <= 31: the value added at decode to a

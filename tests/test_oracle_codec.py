@@ -1,8 +1,8 @@
 """Pins of the scalar reference codec (CPU only).
 
 Each step of the fixed-rate format is tied to something other than the C code:
-exact invertibility, the linear Haar map on inputs whose shifts are exact, the
-definition of base -2, the sort key of the coefficient order, an independent
+the published decorrelating matrix on inputs whose shifts are exact, a
+brute-forced bound on the inverse's error, the definition of base -2, the sort key of the coefficient order, an independent
 closed form of the embedded coder's stream length per bit plane, the embedded
 prefix property across rates, the reconstruction of digits a budget cut off
 (against an independent model of the coder and the exact mean of the unread
@@ -41,42 +41,81 @@ def rand_blocks(n, rng=RNG):
 
 
 # ---- step 4: transform -----------------------------------------------------
-def test_transform_is_exactly_invertible_full_range():
-    for _ in range(200):
-        q = RNG.integers(-2 ** 31, 2 ** 31, size=64, dtype=np.int64).astype(np.int32)
-        assert np.array_equal(oracle.inv_xform(oracle.fwd_xform(q)), q)
-    for _ in range(200):
-        q = RNG.integers(-2 ** 27 + 1, 2 ** 27, size=64).astype(np.int32)
-        assert np.array_equal(oracle.inv_xform(oracle.fwd_xform(q)), q)
+# The published decorrelating matrix of the compressor the paper runs (Lindstrom
+# 2014): one line of four integers maps to A x, applied along x, then y, then z.
+A_ZFP = np.array([[4, 4, 4, 4],
+                  [5, 1, -1, -5],
+                  [-4, 4, 4, -4],
+                  [-2, 6, -6, 2]], dtype=np.float64) / 16.0
+# Largest |inv(fwd(q)) - q| over a block, in units of the 27-bit integers: the
+# floor halvings of the forward steps drop low bits that the inverse cannot
+# restore.  A line loses at most 2 (brute force below); an error e entering the
+# inverse of an axis undone later leaves it as about 3.75 |e| (the largest
+# absolute row sum of the inverse matrix) on top of that axis's own 2, so over
+# the three axes about 2 + 3.75 (2 + 3.75 * 2) = 40 units, below 64.
+XFORM_ROUND_TRIP_ULPS = 64
 
 
-def _haar_axis():
-    # rows: S = mean, D = mean(c,d) - mean(a,b), d0 = b - a, d1 = d - c
-    return np.array([[0.25, 0.25, 0.25, 0.25],
-                     [-0.5, -0.5, 0.5, 0.5],
-                     [-1.0, 1.0, 0.0, 0.0],
-                     [0.0, 0.0, -1.0, 1.0]])
+def _lines_3d(q, M):
+    blk = q.astype(np.float64).reshape(4, 4, 4)               # [k][j][i]
+    w = np.einsum("ai,kji->kja", M, blk)                      # along x
+    w = np.einsum("bj,kja->kba", M, w)                        # along y
+    return np.einsum("ck,kba->cba", M, w)                     # along z
 
 
-def test_transform_equals_linear_haar_when_shifts_are_exact():
-    H = _haar_axis()
-    for _ in range(50):
-        q = (RNG.integers(-2 ** 20, 2 ** 20, size=64) * 64).astype(np.int32)
-        blk = q.astype(np.float64).reshape(4, 4, 4)          # [k][j][i]
-        want = np.einsum("ai,kji->kja", H, blk)               # along x
-        want = np.einsum("bj,kja->kba", H, want)              # along y
-        want = np.einsum("ck,kba->cba", H, want)              # along z
+def test_transform_equals_the_published_matrix_when_shifts_are_exact():
+    # inputs that are multiples of 2^12 keep every floor halving exact on all
+    # three axes (each axis divides by at most 16), so the integer transform
+    # must equal the linear map, and its inverse must return the input exactly
+    for _ in range(100):
+        q = (RNG.integers(-2 ** 14, 2 ** 14, size=64) * 4096).astype(np.int32)
         got = oracle.fwd_xform(q).astype(np.float64).reshape(4, 4, 4)
-        assert np.array_equal(got, want)
+        assert np.array_equal(got, _lines_3d(q, A_ZFP))
+        assert np.array_equal(oracle.inv_xform(oracle.fwd_xform(q)), q)
+    # and the linear inverse of the published matrix, applied in reverse axis
+    # order, maps those coefficients back
+    Ainv = np.linalg.inv(A_ZFP)
+    q = (RNG.integers(-2 ** 14, 2 ** 14, size=64) * 4096).astype(np.int32)
+    c = oracle.fwd_xform(q).astype(np.float64).reshape(4, 4, 4)
+    assert np.allclose(_lines_3d(c.reshape(64), Ainv).reshape(64), q, rtol=0, atol=1e-6)
+
+
+def test_one_line_transform_and_round_trip_brute_force():
+    # Adding 16 m to a line adds 16 A m (integers: every halving stays exact) to
+    # its coefficients, and the inverse then adds 16 m back, so a line's
+    # round-trip error depends only on its residues mod 16: all 16^4 of them.
+    base = (RNG.integers(-2 ** 20, 2 ** 20, size=4) * 16).astype(np.int64)
+    shift = np.rint(A_ZFP @ base).astype(np.int64)
+    worst = 0
+    for a in range(16):
+        for b in range(16):
+            for c in range(16):
+                for d in range(16):
+                    r = np.array([a, b, c, d], dtype=np.int64)
+                    f0 = oracle.fwd_lift_line(r)
+                    f1 = oracle.fwd_lift_line(base + r)
+                    assert np.array_equal(f1.astype(np.int64) - f0, shift)
+                    e = oracle.inv_lift_line(f1).astype(np.int64) - (base + r)
+                    worst = max(worst, int(np.abs(e).max()))
+    # the halvings lose at most 2 units on a line
+    assert 0 < worst <= 2
+
+
+def test_transform_round_trip_error_bound():
+    for _ in range(2000):
+        q = RNG.integers(-2 ** 27 + 1, 2 ** 27, size=64).astype(np.int32)
+        e = oracle.inv_xform(oracle.fwd_xform(q)).astype(np.int64) - q
+        assert np.abs(e).max() <= XFORM_ROUND_TRIP_ULPS
 
 
 def test_transform_range_growth_bound():
-    # |q| < 2^27 stays below 2^30 in magnitude: at most 2x growth per axis
+    # every row of A has absolute sum <= 1, so the exact map cannot grow a
+    # magnitude; the floors add at most a few units
     worst = 0
     for _ in range(300):
         q = RNG.choice([-(2 ** 27 - 1), 2 ** 27 - 1], size=64).astype(np.int32)
         worst = max(worst, int(np.abs(oracle.fwd_xform(q).astype(np.int64)).max()))
-    assert worst < 2 ** 30
+    assert worst <= 2 ** 27 + 8
 
 
 # ---- step 6: negabinary ---------------------------------------------------------
@@ -321,7 +360,10 @@ def test_lossless_bound_when_every_plane_fits():
             continue
         _, eb = oracle.quantize(v)
         d = oracle.block_decode(s, 32).astype(np.float64)
-        assert np.abs(d - v.astype(np.float64)).max() < math.ldexp(1.0, eb - 153)
+        # truncation to 27 bits (< 1 unit) plus the transform's round trip, in
+        # units of 2^(eb-153), plus the FP32 rounding of the reconstruction
+        tol = (XFORM_ROUND_TRIP_ULPS + 1) * math.ldexp(1.0, eb - 153)
+        assert np.abs(d - v.astype(np.float64)).max() < tol + np.abs(v).max() * 2.0 ** -24
 
 
 def test_aggregate_error_decreases_with_rate():
