@@ -4,8 +4,8 @@
 // One lane codes one 4x4x4 block from start to finish, with all per-block
 // state in registers; the slot a lane reads or writes (2R dwords, R bits per
 // value) lives in LDS.  Format: 8-bit block exponent, quantisation to 27-bit
-// integers, two-level integer S-transform lifting along x, y and z (exactly
-// invertible, wrapping arithmetic, floor shifts), sequency order, negabinary,
+// integers, the ZFP method's decorrelating transform along x, y and z (lifting
+// steps, wrapping arithmetic, floor shifts), sequency order, negabinary,
 // embedded group-test bit-plane coding (the budget may end the stream inside
 // any plane), reconstruction ldexp((float)q, Eb - 153).
 #pragma once
@@ -44,31 +44,38 @@ constexpr SeqOrder make_seq_order() {
 }
 constexpr SeqOrder kSeq = make_seq_order();
 
-// ---- integer lifting (wrapping, floor shifts) -----------------------------
+// ---- decorrelating transform of one line (wrapping, floor shifts) ----------
+// The published matrix of the ZFP method, (1/16) [[4 4 4 4] [5 1 -1 -5]
+// [-4 4 4 -4] [-2 6 -6 2]], as five lifting steps: halve-and-difference of the
+// outer pair, of the inner pair, of the two means and of the two differences,
+// then a shear of the differences.  The halvings drop low bits, so the inverse
+// (the steps undone in reverse order) is exact only to a few units of the
+// 27-bit integers.
+__device__ __forceinline__ int32_t wadd(int32_t u, int32_t v) { return (int32_t)((uint32_t)u + (uint32_t)v); }
+__device__ __forceinline__ int32_t wsub(int32_t u, int32_t v) { return (int32_t)((uint32_t)u - (uint32_t)v); }
 __device__ __forceinline__ void lift_fwd(int32_t &a, int32_t &b, int32_t &c, int32_t &d) {
-  uint32_t d0 = (uint32_t)b - (uint32_t)a;
-  uint32_t s0 = (uint32_t)a + (uint32_t)((int32_t)d0 >> 1);
-  uint32_t d1 = (uint32_t)d - (uint32_t)c;
-  uint32_t s1 = (uint32_t)c + (uint32_t)((int32_t)d1 >> 1);
-  uint32_t D = s1 - s0;
-  uint32_t S = s0 + (uint32_t)((int32_t)D >> 1);
-  a = (int32_t)S;
-  b = (int32_t)D;
-  c = (int32_t)d0;
-  d = (int32_t)d1;
+  int32_t x0 = a, x1 = b, x2 = c, x3 = d;
+  x0 = wadd(x0, x3) >> 1;  x3 = wsub(x3, x0);
+  x2 = wadd(x2, x1) >> 1;  x1 = wsub(x1, x2);
+  x0 = wadd(x0, x2) >> 1;  x2 = wsub(x2, x0);
+  x3 = wadd(x3, x1) >> 1;  x1 = wsub(x1, x3);
+  x3 = wadd(x3, x1 >> 1);  x1 = wsub(x1, x3 >> 1);
+  a = x0;
+  b = x1;
+  c = x2;
+  d = x3;
 }
 __device__ __forceinline__ void lift_inv(int32_t &a, int32_t &b, int32_t &c, int32_t &d) {
-  uint32_t S = (uint32_t)a, D = (uint32_t)b, d0 = (uint32_t)c, d1 = (uint32_t)d;
-  uint32_t s0 = S - (uint32_t)((int32_t)D >> 1);
-  uint32_t s1 = D + s0;
-  uint32_t x2 = s1 - (uint32_t)((int32_t)d1 >> 1);
-  uint32_t x3 = d1 + x2;
-  uint32_t x0 = s0 - (uint32_t)((int32_t)d0 >> 1);
-  uint32_t x1 = d0 + x0;
-  a = (int32_t)x0;
-  b = (int32_t)x1;
-  c = (int32_t)x2;
-  d = (int32_t)x3;
+  int32_t x0 = a, x1 = b, x2 = c, x3 = d;
+  x1 = wadd(x1, x3 >> 1);  x3 = wsub(x3, x1 >> 1);
+  x1 = wadd(x1, x3);       x3 = wsub(wadd(x3, x3), x1);
+  x2 = wadd(x2, x0);       x0 = wsub(wadd(x0, x0), x2);
+  x1 = wadd(x1, x2);       x2 = wsub(wadd(x2, x2), x1);
+  x3 = wadd(x3, x0);       x0 = wsub(wadd(x0, x0), x3);
+  a = x0;
+  b = x1;
+  c = x2;
+  d = x3;
 }
 
 __device__ __forceinline__ void xform_fwd(int32_t *q) {

@@ -3,8 +3,9 @@
 // The paper compresses each chunk on the GPU before it is copied back and
 // decompresses it after it is copied in (Sec. 1, Sec. 4.2), at a fixed,
 // user-specified rate (Sec. 5).  The format is this library's own fixed-rate
-// block-transform code (block floating point, exactly invertible integer
-// lifting transform, embedded bit-plane coding with group tests); every slot
+// block-transform code after the method of the compressor the paper runs
+// (block floating point, the ZFP decorrelating transform in integer lifting
+// steps, embedded bit-plane coding with group tests); every slot
 // holds one 4x4x4 block in exactly 64*R bits, so a block's position in the
 // stream is known without any index, and every group of four planes is one
 // contiguous byte range.
