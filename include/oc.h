@@ -303,6 +303,20 @@ int oc_wave25_incore(float *d_prev, float *d_cur, const float *d_vel, float *d_t
 
 const char *oc_status_str(int status);
 
+/* ---- stream check -------------------------------------------------------- */
+/* Whether two streams run their kernels side by side.  The pipeline overlaps
+ * the copy-back of one slab with the kernels of the next (Sec. 4.2, Fig. 4);
+ * the copy-back is a kernel, so the kernel stream and the copy-back stream
+ * must not be serialized.  The runtime maps streams onto a few hardware
+ * queues in creation order, and two streams on one queue run in line; oc_run
+ * cannot see that.  This runs a one-wave kernel of 2 ms (timed on the device's
+ * constant-rate clock) on each stream at once, after a short first launch on
+ * each, and writes into *overlap the share of the shorter run during which
+ * both ran: about 1 when the streams run side by side, 0 when they are
+ * serialized (for instance a == b).  Synchronizes both streams; the current
+ * device must own both.  Errors: OC_ERR_ARG (null argument), OC_ERR_HIP. */
+int oc_stream_overlap(oc_stream a, oc_stream b, double *overlap);
+
 /* ---- test and debug hooks ----------------------------------------------- */
 /* Makes the n-th HIP call issued by the executor from now on fail with
  * OC_ERR_HIP (n >= 1); n < 0 disables. */

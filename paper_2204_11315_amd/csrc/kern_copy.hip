@@ -16,6 +16,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "oc_kernels.h"
 
 namespace {
@@ -43,9 +45,50 @@ __global__ __launch_bounds__(kThreads) void k_copy1(uint8_t *__restrict__ dst,
     dst[i] = src[i];
 }
 
+// Start and end of the two probe kernels on the device's constant-rate clock.
+__device__ unsigned long long g_probe_clock[4];
+
+// One wave that runs for `ticks` of the constant-rate clock (at most 2^24
+// clock reads) and records its start and end in slot `slot`: two of them on
+// two streams show whether the streams run their kernels side by side.
+__global__ __launch_bounds__(64) void k_busy(int slot, unsigned long long ticks) {
+  const unsigned long long t0 = wall_clock64();
+  unsigned long long t = t0;
+  for (int i = 0; i < (1 << 24) && t - t0 < ticks; i++) t = wall_clock64();
+  if (threadIdx.x == 0) {
+    g_probe_clock[2 * slot] = t0;
+    g_probe_clock[2 * slot + 1] = t;
+  }
+}
+
 }  // namespace
 
 namespace oc {
+
+hipError_t probe_stream_overlap(hipStream_t a, hipStream_t b, double *overlap) {
+  int dev = 0, khz = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev);
+  if (e != hipSuccess) return e;
+  if (khz <= 0) return hipErrorInvalidValue;
+  const unsigned long long ticks = (unsigned long long)khz * 2;   // 2 ms
+  // first launches on each stream carry one-time costs (code object, queue)
+  for (int pass = 0; pass < 2; pass++) {
+    hipLaunchKernelGGL(k_busy, dim3(1), dim3(64), 0, a, 0, pass ? ticks : ticks / 20);
+    hipLaunchKernelGGL(k_busy, dim3(1), dim3(64), 0, b, 1, pass ? ticks : ticks / 20);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(a);
+    if (e == hipSuccess) e = hipStreamSynchronize(b);
+    if (e != hipSuccess) return e;
+  }
+  unsigned long long c[4] = {};
+  e = hipMemcpyFromSymbol(c, HIP_SYMBOL(g_probe_clock), sizeof(c), 0, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return e;
+  const double lo = (double)std::max(c[0], c[2]), hi = (double)std::min(c[1], c[3]);
+  const double shorter = (double)std::min(c[1] - c[0], c[3] - c[2]);
+  *overlap = shorter > 0 ? std::max(0.0, hi - lo) / shorter : 0.0;
+  return hipSuccess;
+}
 
 hipError_t launch_copy_to_host(void *dst, const void *src, size_t bytes, int workgroups, hipStream_t s,
                                KernelTimer *kt) {

@@ -1391,6 +1391,20 @@ int oc_debug_codec_star7(const void *d_in, void *d_out, int64_t nx, int64_t ny, 
   }
 }
 
+int oc_stream_overlap(oc_stream a, oc_stream b, double *overlap) {
+  try {
+    if (!a || !b || !overlap) return OC_ERR_ARG;
+    hipError_t e = oc::probe_stream_overlap((hipStream_t)a, (hipStream_t)b, overlap);
+    if (e != hipSuccess) {
+      g_last_hip = e;
+      return OC_ERR_HIP;
+    }
+    return OC_OK;
+  } catch (...) {
+    return OC_ERR_HOST;
+  }
+}
+
 int64_t oc_debug_timeline(const oc_handle *h, int32_t *kind, int64_t *slab, double *start_ms,
                           double *end_ms, int64_t cap) {
   try {

@@ -104,6 +104,10 @@ hipError_t launch_wave25(const float *pn, float *pnm1, const float *vel, int64_t
 
 // Copies `bytes` from device memory into host memory that the device can
 // address (pinned, mapped); a small grid so that it overlaps other kernels.
+// Runs a 2 ms one-wave kernel on each of two streams at once and writes the
+// share of the shorter one's run during which both ran (1: side by side, 0:
+// one after the other).  Synchronizes both streams.
+hipError_t probe_stream_overlap(hipStream_t a, hipStream_t b, double *overlap);
 hipError_t launch_copy_to_host(void *dst, const void *src, size_t bytes, int workgroups, hipStream_t s,
                          KernelTimer *kt = nullptr);
 

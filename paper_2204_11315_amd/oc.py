@@ -9,6 +9,7 @@ from __future__ import annotations
 import ctypes
 import os
 import threading
+import warnings
 
 import numpy as np
 
@@ -116,6 +117,7 @@ _SIGS = {
     "oc_debug_copy_to_host": (ctypes.c_int, [_P, _SZ, _P, _SZ, _I32, _P]),
     "oc_debug_codec_star7": (ctypes.c_int, [_P, _P, _I64, _I64, _I64, _I64, _I64, _I64, _I64, _I32, _I32,
                                             _P, _P]),
+    "oc_stream_overlap": (ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_double)]),
 }
 EXPORTED = tuple(_SIGS)
 
@@ -305,6 +307,7 @@ def _stream_handle(stream):
 
 
 _stream_pool = {}
+_stream_overlap = {}
 
 
 def pipeline_streams(device=None):
@@ -313,15 +316,50 @@ def pipeline_streams(device=None):
     and once there are more streams than queues, streams share queues; the
     kernel and copy-back streams must not share one (the copy-back kernel
     would then run in line with the decode / stencil / encode kernels), so a
-    program should call this before it creates streams of its own."""
+    program should call this before it creates streams of its own.  On
+    creation the two are probed (oc_stream_overlap) and a RuntimeWarning is
+    raised when they turn out serialized."""
     torch = _torch()
     dev = torch.device(device if device is not None else "cuda")
     if dev.index is None:
         dev = torch.device("cuda", torch.cuda.current_device())
     with _lock:
-        if dev not in _stream_pool:
-            _stream_pool[dev] = [torch.cuda.Stream(device=dev) for _ in range(3)]
-        return _stream_pool[dev]
+        streams = _stream_pool.get(dev)
+        created = streams is None
+        if created:
+            streams = _stream_pool[dev] = [torch.cuda.Stream(device=dev) for _ in range(3)]
+    if created:
+        with torch.cuda.device(dev):
+            ov = stream_overlap(streams[1], streams[2])
+        _stream_overlap[dev] = ov
+        if ov < 0.5:
+            warnings.warn(
+                "the kernel and copy-back streams on %s run one after the other (probe overlap %.2f): "
+                "they share a hardware queue, so the copy-back kernel runs in line with the "
+                "decode / stencil / encode kernels and jobs slow down; call "
+                "oc.pipeline_streams() before the program creates streams of its own" % (dev, ov),
+                RuntimeWarning, stacklevel=2)
+    return streams
+
+
+def pipeline_stream_overlap(device=None) -> float:
+    """The probe overlap measured when pipeline_streams() created the streams
+    of `device` (about 1: the kernel and copy-back streams run side by side)."""
+    torch = _torch()
+    dev = torch.device(device if device is not None else "cuda")
+    if dev.index is None:
+        dev = torch.device("cuda", torch.cuda.current_device())
+    pipeline_streams(dev)
+    return _stream_overlap.get(dev, float("nan"))
+
+
+def stream_overlap(a, b) -> float:
+    """Share of a 2 ms one-wave kernel's run on stream a or b (the shorter)
+    during which the same kernel ran on the other stream, both launched at
+    once: about 1 when the two streams run side by side, 0 when serialized."""
+    r = ctypes.c_double(0.0)
+    _check(lib().oc_stream_overlap(_stream_handle(a), _stream_handle(b), ctypes.byref(r)), "oc_stream_overlap")
+    return float(r.value)
 
 
 def _dev(t, dtype, what):
