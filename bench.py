@@ -220,11 +220,11 @@ ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # 256 MiB device copy) over the algorithmic bytes, read and write weighted by
 # their algorithmic bytes.
 KERNEL_COUNTERS = {
-    ("decode", 8): {"traffic": 1.011, "valu_per_wave": 6736, "active_lanes": 0.460,
+    ("decode", 5): {"traffic": 1.013, "valu_per_wave": 6375, "active_lanes": 0.54,
                     "source": "profiles/codec_stencil_kernels_slab_512x512x72.md"},
-    ("encode", 8): {"traffic": 1.010, "valu_per_wave": 5830, "active_lanes": 0.642,
+    ("encode", 5): {"traffic": 1.009, "valu_per_wave": 5724, "active_lanes": 0.75,
                     "source": "profiles/codec_stencil_kernels_slab_512x512x72.md"},
-    ("stencil", None): {"traffic": 1.194,
+    ("stencil", None): {"traffic": 1.195,
                         "source": "profiles/codec_stencil_kernels_slab_512x512x72.md"},
 }
 
@@ -705,7 +705,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--rate", type=int, default=0,
                     help="headline rate (bits/value); 0 = smallest candidate meeting --budget")
-    ap.add_argument("--rates", default="8,9,10,12,16", help="candidate rates")
+    ap.add_argument("--rates", default="4,5,6,8,12", help="candidate rates")
     ap.add_argument("--budget", type=float, default=1e-3, help="rel-L2 error budget vs FP64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--error", choices=["none", "sampled", "full"], default="full",
@@ -714,7 +714,7 @@ def main():
                     help="launch each hot kernel at slab shape (for rocprofv3), then exit")
     ap.add_argument("--workload", choices=["star7", "wave", "adjoint", "incore"], default="star7")
     ap.add_argument("--wave-nz", type=int, default=4096)
-    ap.add_argument("--wave-rates", default="12,14,16",
+    ap.add_argument("--wave-rates", default="10,12,14",
                     help="coded legs of the wave workload (an uncompressed leg always runs)")
     ap.add_argument("--fd-dirs", type=int, default=32)
     ap.add_argument("--no-fused", action="store_true",
@@ -732,6 +732,8 @@ def main():
         sys.exit(2)
     oc.lib()
     oc.pipeline_streams()   # the pipeline's streams take their hardware queues first
+    log("kernel / copy-back streams: probe overlap %.2f (1: side by side, 0: serialized)"
+        % oc.pipeline_stream_overlap())
     if args.kernels:
         kernel_probe(args.rate or 16)
         return
@@ -847,6 +849,7 @@ def main():
                         "hipMemGetInfo drop are in legs[*]",
         "roofline": roof,
         "link_roofline": main_leg["link_roofline"],
+        "stream_overlap": oc.pipeline_stream_overlap(),
         "uncompressed_link_roofline": base_leg["link_roofline"],
         "link_probe_gbs": link,
         "library_rate_pick": auto,

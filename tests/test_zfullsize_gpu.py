@@ -54,9 +54,9 @@ def run_full(u0, R, fused=False):
         o.close()
 
 
-# R = 8 is the smallest rate within 1e-3 over the full grid (9.3e-4, measured
-# by the benchmark); on 12 sampled cells the bar is looser
-@pytest.mark.parametrize("R,tol", [(0, 1e-5), (16, 1e-4), (8, 3e-3)])
+# R = 5 is the smallest rate within 1e-3 over the full grid (6.6e-4, measured
+# by the benchmark; R = 8: 8.3e-5); on 12 sampled cells the bar is looser
+@pytest.mark.parametrize("R,tol", [(0, 1e-5), (16, 1e-4), (8, 1e-3), (5, 3e-3)])
 def test_fullsize_sampled_vs_oracle(u0, R, tol):
     got, st = run_full(u0, R)
     pts = sample_points()
@@ -64,9 +64,10 @@ def test_fullsize_sampled_vs_oracle(u0, R, tol):
     have = np.array([got[p] for p in pts], dtype=np.float64)
     assert np.linalg.norm(have - want) <= tol * np.linalg.norm(want)
     assert st["n_slabs"] == 32 and st["slab_visits"] == 32 * 16
-    assert st["peak_dev_bytes"] == {0: 432 << 20, 16: 252 << 20, 8: 198 << 20}[R]
-    if R == 8:
-        # the fused codec kernel at full size: the same output, 102 MiB
+    MiB = 1 << 20
+    assert st["peak_dev_bytes"] == {0: 432 * MiB, 16: 252 * MiB, 8: 198 * MiB, 5: int(177.75 * MiB)}[R]
+    if R in (5, 8):
+        # the fused codec kernel at full size: the same output, in 63.75 / 102 MiB
         fused, sf = run_full(u0, R, fused=True)
         assert np.array_equal(fused.view(np.uint32), got.view(np.uint32))
-        assert sf["peak_dev_bytes"] == 102 << 20 and sf["n_slabs"] == 32
+        assert sf["peak_dev_bytes"] == {5: int(63.75 * MiB), 8: 102 * MiB}[R] and sf["n_slabs"] == 32
