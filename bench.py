@@ -705,7 +705,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--rate", type=int, default=0,
                     help="headline rate (bits/value); 0 = smallest candidate meeting --budget")
-    ap.add_argument("--rates", default="4,5,6,8,12", help="candidate rates")
+    ap.add_argument("--rates", default="4,5,6,8,12,16", help="candidate rates")
     ap.add_argument("--budget", type=float, default=1e-3, help="rel-L2 error budget vs FP64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--error", choices=["none", "sampled", "full"], default="full",

@@ -314,7 +314,9 @@ const char *oc_status_str(int status);
  * each, and writes into *overlap the share of the shorter run during which
  * both ran: about 1 when the streams run side by side, 0 when they are
  * serialized (for instance a == b).  Synchronizes both streams; the current
- * device must own both.  Errors: OC_ERR_ARG (null argument), OC_ERR_HIP. */
+ * device must own both.  The two kernels record their clocks in one static
+ * device array per device, so calls that overlap on one device race.
+ * Errors: OC_ERR_ARG (null argument), OC_ERR_HIP. */
 int oc_stream_overlap(oc_stream a, oc_stream b, double *overlap);
 
 /* ---- test and debug hooks ----------------------------------------------- */

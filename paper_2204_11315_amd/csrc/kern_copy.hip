@@ -82,7 +82,8 @@ hipError_t probe_stream_overlap(hipStream_t a, hipStream_t b, double *overlap) {
     if (e != hipSuccess) return e;
   }
   unsigned long long c[4] = {};
-  e = hipMemcpyFromSymbol(c, HIP_SYMBOL(g_probe_clock), sizeof(c), 0, hipMemcpyDeviceToHost);
+  e = hipMemcpyFromSymbolAsync(c, HIP_SYMBOL(g_probe_clock), sizeof(c), 0, hipMemcpyDeviceToHost, a);
+  if (e == hipSuccess) e = hipStreamSynchronize(a);
   if (e != hipSuccess) return e;
   const double lo = (double)std::max(c[0], c[2]), hi = (double)std::min(c[1], c[3]);
   const double shorter = (double)std::min(c[1] - c[0], c[3] - c[2]);
