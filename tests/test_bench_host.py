@@ -1,0 +1,75 @@
+"""Host-side logic of bench.py (CPU only): the one-GPU guard, the host-link
+roofline and the per-kernel roofline arithmetic on synthetic figures."""
+import importlib.util
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def bench():
+    spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(ROOT, "bench.py"))
+    m = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(m)
+    return m
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def _link(ah, ad, xh, xd):
+    return {"h2d_alone": ah, "d2h_alone": ad, "h2d_with_d2h": xh, "d2h_with_h2d": xd}
+
+
+def test_link_roofline_closed_forms(bench):
+    B = 8e9
+    leg = {"bytes_h2d": B, "bytes_d2h": B, "ms_per_job": 500.0}
+    # both directions at full rate together: the bound is one direction's time
+    r = bench.link_roofline(leg, _link(40, 40, 40, 40))
+    assert r["bound_ms"] == pytest.approx(B / 40e9 * 1e3)
+    # sharing halves each rate: running both at once or one after the other
+    # takes the same time
+    r = bench.link_roofline(leg, _link(40, 40, 20, 20))
+    assert r["bound_ms"] == pytest.approx(2 * B / 40e9 * 1e3)
+    assert r["frac"] == pytest.approx(r["bound_ms"] / 500.0)
+    # one direction only: its alone rate
+    r = bench.link_roofline({"bytes_h2d": B, "bytes_d2h": 0, "ms_per_job": 500.0}, _link(50, 40, 30, 30))
+    assert r["bound_ms"] == pytest.approx(B / 50e9 * 1e3)
+
+
+def test_link_roofline_is_a_lower_bound_of_every_split(bench):
+    # no split of the job's time between "both busy" and "each alone" beats it
+    leg = {"bytes_h2d": 6e9, "bytes_d2h": 4e9, "ms_per_job": 1000.0}
+    link = _link(55, 43, 47, 41)
+    bound = bench.link_roofline(leg, link)["bound_ms"] * 1e-3
+    bh, bd = 6e9, 4e9
+    for i in range(201):
+        tc = i / 200 * max(bh / 47e9, bd / 41e9)
+        t = tc + max(0.0, bh - tc * 47e9) / 55e9 + max(0.0, bd - tc * 41e9) / 43e9
+        assert t >= bound * (1 - 1e-12)
+
+
+def test_kernel_roofline_arithmetic(bench):
+    rate = 5
+    st = {"ms_decode": 2.0, "n_decode": 20, "ms_encode": 1.0, "n_encode": 20, "ms_stencil": 3.0,
+          "n_stencil": 30, "ms_fused": 0.0, "n_fused": 0, "blocks_decode": 20 * 1000,
+          "blocks_encode": 20 * 800, "bytes_stencil": 30 * 1e6}
+    k = bench.kernel_roofline([st], rate)
+    assert set(k) == {"decode", "encode", "stencil"}
+    d = k["decode"]
+    assert d["avg_ms"] == pytest.approx(0.1) and d["launches"] == 20
+    assert d["bytes_per_launch"] == pytest.approx(1000 * (8 * rate + 256))
+    assert d["gbs"] == pytest.approx(1000 * (8 * rate + 256) / 1e-4 / 1e9)
+    assert k["stencil"]["bytes_per_launch"] == pytest.approx(1e6)
+    roof = bench.roofline_of(k, rate)
+    assert roof["kernel"] == "stencil"            # the largest total time
+    assert roof["frac"] == pytest.approx(roof["achieved"] / roof["peak"])
+    assert roof["unit"] == "GB/s" and roof["bound"] == "hbm"
