@@ -116,7 +116,7 @@ def test_bad_arguments_rejected_before_launch():
         oc.compress(d, 8, out=small)
 
 
-@pytest.mark.parametrize("R", [8, 16])
+@pytest.mark.parametrize("R", [5, 8, 16])
 def test_full_slab_shape_diffused_field(R):
     # a slab-sized piece of the field after 32 stencil steps (the decoder's
     # longest loops: many planes and significant coefficients per block)
@@ -128,11 +128,13 @@ def test_full_slab_shape_diffused_field(R):
     assert np.array_equal(back.view(np.uint32), oracle.decompress(want, f.shape, R).view(np.uint32))
 
 
-def test_full_slab_shape_grf_r16():
-    # the shape of one C2/C3 slab interior (64 planes of 512 x 512)
+@pytest.mark.parametrize("R", [5, 16])
+def test_full_slab_shape_grf(R):
+    # the shape of one C2/C3 slab interior (64 planes of 512 x 512), at the
+    # bench job's headline rate and at 16 bits per value
     f = inputs.grf_field((64, 512, 512), seed=2)
-    want = oracle.compress(f, 16)
-    got = oc.compress(_dev(f), 16).cpu().numpy()
+    want = oracle.compress(f, R)
+    got = oc.compress(_dev(f), R).cpu().numpy()
     assert np.array_equal(got, want)
-    back = oc.decompress(_dev(want), f.shape, 16).cpu().numpy()
-    assert np.array_equal(back.view(np.uint32), oracle.decompress(want, f.shape, 16).view(np.uint32))
+    back = oc.decompress(_dev(want), f.shape, R).cpu().numpy()
+    assert np.array_equal(back.view(np.uint32), oracle.decompress(want, f.shape, R).view(np.uint32))

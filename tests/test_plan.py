@@ -498,3 +498,29 @@ def test_device_entry_points_check_pointer_alignment_before_any_launch():
     assert lib.oc_codec_decompress(ok16, 4, 4, 4, 8, ok4, None) == oc.OC_ERR_ARG
     c = (ctypes.c_float * 7)(*([0.1] * 7))
     assert lib.oc_star7_incore(bad, ok16, ok16, 4, 4, 4, c, None, 1, None) == oc.OC_ERR_ARG
+
+
+def test_codec_entry_points_check_arguments_before_touching_a_device():
+    # every rejected call returns its status before the first HIP call, so the
+    # pointers below are never dereferenced (no GPU in this test)
+    import ctypes
+    L = oc.lib()
+    p16 = ctypes.c_void_p(0x10000)            # 16-byte aligned, never read
+    p4 = ctypes.c_void_p(0x10004)             # 4-byte aligned only
+    nbytes = 8 * 8 * 8 // 64 * 8 * 5          # 8 blocks of 8R bytes
+    assert L.oc_codec_bytes(8, 8, 8, 5) == nbytes == oc.codec_bytes((8, 8, 8), 5)
+    # empty and negative extents, rates outside 1..32
+    for nx, ny, nz, R in ((8, 8, 0, 5), (0, 8, 8, 5), (8, -4, 8, 5), (8, 8, 8, 0), (8, 8, 8, 33)):
+        assert L.oc_codec_compress(p16, nx, ny, nz, R, p16, 1 << 20, None) == oc.OC_ERR_ARG
+        assert L.oc_codec_decompress(p16, nx, ny, nz, R, p16, None) == oc.OC_ERR_ARG
+    # null pointers, misaligned field (float4 moves) or codes (dword moves)
+    assert L.oc_codec_compress(None, 8, 8, 8, 5, p16, nbytes, None) == oc.OC_ERR_ARG
+    assert L.oc_codec_compress(p4, 8, 8, 8, 5, p16, nbytes, None) == oc.OC_ERR_ARG
+    assert L.oc_codec_compress(p16, 8, 8, 8, 5, ctypes.c_void_p(0x10002), nbytes, None) == oc.OC_ERR_ARG
+    assert L.oc_codec_decompress(p16, 8, 8, 8, 5, p4, None) == oc.OC_ERR_ARG
+    # extents that are not whole 4x4x4 blocks, and an output smaller than the codes
+    assert L.oc_codec_compress(p16, 8, 8, 6, 5, p16, nbytes, None) == oc.OC_ERR_SHAPE
+    assert L.oc_codec_decompress(p16, 8, 10, 8, 5, p16, None) == oc.OC_ERR_SHAPE
+    assert L.oc_codec_compress(p16, 8, 8, 8, 5, p16, nbytes - 1, None) == oc.OC_ERR_ARG
+    # the stream check rejects null arguments
+    assert L.oc_stream_overlap(None, None, None) == oc.OC_ERR_ARG
