@@ -20,6 +20,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <atomic>
 
 #include "oc_kernels.h"
 #include "stencil_dev.h"
@@ -96,8 +97,9 @@ __global__ __launch_bounds__(TX *TY) void k_star7(const float *__restrict__ in, 
 // identical to K single steps.  The caller guarantees that input planes
 // [zo_lo - K, zo_hi + K) lie inside the buffers; no plane outside that range
 // is read.
-constexpr int FW = 8, RY = 4, FTY = FW * RY;
-constexpr int kFusedTargetWgs = 512;   // workgroups a fused launch aims for (z chunks)
+// Five rows per wave: a 40-row tile writes 40 - 2K rows, 32 at K = 4, which
+// tiles a 512-row plane exactly (16 tiles; 4 rows gave 24 of 32 and 22 tiles).
+constexpr int FW = 8, RY = 5, FTY = FW * RY;
 
 // One 7-point step with four consecutive x per lane, for rows of whole,
 // 16-byte aligned float4s (nx % 4 == 0): a wave covers 256 contiguous x of a
@@ -311,6 +313,26 @@ __global__ __launch_bounds__(64 * FW) void k_star7_fused(const float *__restrict
     fused_march<K, FIELD, true>(st, edge, in, out, c0f, plane, col0, nx, gz0, nz, zlo, zhi, lane, w, c);
 }
 
+// Workgroups of k_star7_fused<K, FIELD> the device holds at once (occupancy x
+// compute units), looked up once per kernel.
+template <int K>
+int64_t fused_resident_wgs(bool field) {
+  static std::atomic<int> per_cu[2] = {{0}, {0}};
+  int n = per_cu[field].load(std::memory_order_relaxed);
+  if (n <= 0) {
+    int blocks = 0;
+    hipError_t e = field ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_star7_fused<K, true>, 64 * FW, 0)
+                         : hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_star7_fused<K, false>, 64 * FW, 0);
+    n = (e == hipSuccess && blocks > 0) ? blocks : 1;
+    per_cu[field].store(n, std::memory_order_relaxed);
+  }
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+    cus = 256;
+  return (int64_t)n * cus;
+}
+
 template <int K>
 hipError_t launch_fused(const float *in, float *out, const float *c0f, int64_t nx, int64_t ny,
                         int64_t zo_lo, int64_t zo_hi, int64_t gz0, int64_t nz, const oc::Star7Coef &c,
@@ -318,10 +340,13 @@ hipError_t launch_fused(const float *in, float *out, const float *c0f, int64_t n
   constexpr int OX = 64 - 2 * K, OY = FTY - 2 * K;
   const int nbx = (int)((nx + OX - 1) / OX);
   const int nby = (int)((ny + OY - 1) / OY);
-  // z chunk: enough workgroups to cover the chip about twice
+  // z chunks: as many as keep every workgroup of the launch resident at once
+  // (one round over the chip), since each chunk recomputes 2K planes of
+  // halo; at least 2K output planes per chunk
   const int64_t nz_out = zo_hi - zo_lo;
   const int64_t xy = (int64_t)nbx * nby;
-  int64_t nbz = std::max<int64_t>(1, std::min<int64_t>(nz_out / (2 * K), (kFusedTargetWgs + xy - 1) / xy));
+  const int64_t resident = fused_resident_wgs<K>(c0f != nullptr);
+  int64_t nbz = std::max<int64_t>(1, std::min<int64_t>(nz_out / (2 * K), resident / xy));
   const int fz = (int)((nz_out + nbz - 1) / nbz);
   nbz = (nz_out + fz - 1) / fz;
   const int64_t nb = xy * nbz;
