@@ -224,6 +224,8 @@ KERNEL_COUNTERS = {
                     "source": "profiles/codec_stencil_kernels_slab_512x512x72.md"},
     ("encode", 5): {"traffic": 1.009, "valu_per_wave": 5724, "active_lanes": 0.75,
                     "source": "profiles/codec_stencil_kernels_slab_512x512x72.md"},
+    ("stencil", None): {"traffic": 1.180,
+                        "source": "profiles/codec_stencil_kernels_slab_512x512x72.md"},
 }
 
 
