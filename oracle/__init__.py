@@ -278,21 +278,25 @@ def quantize(v):
 
 
 # ---- compressed out-of-core path as a composition ------------------------
-def compressed_sweeps(u0, c, steps: int, k: int, R: int, c0f=None) -> np.ndarray:
+def compressed_sweeps(u0, c, steps: int, k: int, R: int, c0f=None, load_rate: int = 0) -> np.ndarray:
     """Dec(Enc(S^{k_last} ... Dec(Enc(S^k(Dec(Enc(u0))))))) with S = FP64 stencil.
 
-    The host holds the field compressed: loading encodes the FP32 input; every
-    residency decodes, runs k steps (the last one runs steps mod k when k does
-    not divide steps), and encodes its FP32-rounded result; storing decodes.
+    The host holds the field compressed: loading encodes the FP32 input (at
+    `load_rate` when it is set, else at R); every residency decodes the codes
+    it finds (the first one at the load rate), runs k steps (the last one runs
+    steps mod k when k does not divide steps), and encodes its FP32-rounded
+    result at R; storing decodes the last codes at their rate.
     """
     u0 = np.ascontiguousarray(np.asarray(u0, dtype=np.float32))
     shape = u0.shape
-    buf = compress(u0, R)
+    rate = load_rate if load_rate else R
+    buf = compress(u0, rate)
     done = 0
     while done < steps:
         s = min(k, steps - done)
-        u = decompress(buf, shape, R)
+        u = decompress(buf, shape, rate)
         u = star7_run(u, c, s, c0f)
-        buf = compress(u.astype(np.float32), R)
+        rate = R
+        buf = compress(u.astype(np.float32), rate)
         done += s
-    return decompress(buf, shape, R)
+    return decompress(buf, shape, rate)

@@ -94,3 +94,31 @@ def test_zero_steps_is_one_codec_round_trip(R):
     u0 = block_constant_field((2, 2, 2), seed=13)
     got = oracle.compressed_sweeps(u0, DIAG, 0, 4, R)
     assert np.array_equal(got.view(np.uint32), u0.view(np.uint32))
+
+
+@pytest.mark.parametrize("R,L", [(3, 8), (5, 9), (1, 32)])
+@pytest.mark.parametrize("steps,k", [(10, 4), (4, 4), (1, 4)])
+def test_load_rate_keeps_the_residency_structure(R, L, steps, k):
+    # a separate rate for the load-time encode changes no residency: the
+    # block-constant closed form holds whatever the two rates are
+    u0 = block_constant_field((3, 2, 5), seed=300 + steps + R)
+    got = oracle.compressed_sweeps(u0, DIAG, steps, k, R, load_rate=L)
+    want = diag_chain(u0, 1.0 / 3.0, steps, k)
+    assert np.array_equal(got.view(np.uint32), want.view(np.uint32))
+
+
+def test_load_rate_decides_the_first_decode_and_a_store_without_steps():
+    # with no residency the store decodes the load's codes: one round trip at
+    # the load rate, whose error is the codec's at that rate (smaller than at R)
+    from paper_2204_11315_amd import inputs
+    u0 = inputs.grf_field((16, 16, 16), seed=4)
+    a = oracle.compressed_sweeps(u0, (0.4,) + (0.1,) * 6, 0, 4, 3, load_rate=9)
+    assert np.array_equal(a.view(np.uint32), oracle.decompress(oracle.compress(u0, 9), u0.shape, 9).view(np.uint32))
+    # the load rate equal to R is the plain composition
+    b = oracle.compressed_sweeps(u0, (0.4,) + (0.1,) * 6, 6, 4, 5, load_rate=5)
+    assert np.array_equal(b.view(np.uint32), oracle.compressed_sweeps(u0, (0.4,) + (0.1,) * 6, 6, 4, 5).view(np.uint32))
+    # a finer load rate lowers the job's error on a rough field
+    ref = oracle.star7_run(u0, (0.4,) + (0.1,) * 6, 8)
+    err = lambda v: np.linalg.norm(v.astype(np.float64) - ref) / np.linalg.norm(ref)
+    assert err(oracle.compressed_sweeps(u0, (0.4,) + (0.1,) * 6, 8, 4, 3, load_rate=10)) < \
+        err(oracle.compressed_sweeps(u0, (0.4,) + (0.1,) * 6, 8, 4, 3))
