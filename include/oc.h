@@ -128,6 +128,15 @@ typedef struct {
                               k <= 4, rate_bits 1..16, else OC_ERR_UNSUPPORTED.  The codes
                               are those of the three-kernel path, bit for bit.  0 = decode,
                               stencil and encode kernels over a full-size working buffer   */
+  int32_t load_rate_bits;  /* rate of the codes oc_load writes, which the first residency
+                              after it decodes; every residency encodes at rate_bits, and
+                              oc_store decodes the codes at the rate they were written.  A
+                              field's roughest state is usually its first: after a few steps
+                              the stencil has smoothed it and fewer bits keep the same error.
+                              0 = rate_bits; else rate_bits..32 (with error_budget: the rate
+                              picked, if that is higher), 7-point stencil without
+                              fused_codec (else OC_ERR_UNSUPPORTED).  Host levels and ring
+                              slots are sized for the larger of the two rates               */
 } oc_config;
 
 typedef struct {

@@ -37,6 +37,7 @@ struct oc_handle {
   uint8_t *adj_work = nullptr;
   size_t adj_off[4] = {};   // checkpoint store, lambda A, lambda B, gradient store
   int cur = 0;            // host level holding the current state
+  int level_rate = 0;     // rate of the codes in that level (the load rate after oc_load)
   bool loaded = false;
   bool broken = false;
   int64_t time_index = 0; // time steps applied since load
@@ -57,7 +58,7 @@ struct oc_handle {
   std::vector<TimedOp> last_timed;
   // cached operation list
   std::vector<oc::Op> ops;
-  int64_t ops_key[4] = {-1, -1, -1, -1};
+  int64_t ops_key[5] = {-1, -1, -1, -1, -1};
   // rate per error budget: the plan input at the largest rate (slab depth
   // pinned), replanned at the rate each oc_load picks
   bool auto_rate = false;
@@ -153,6 +154,10 @@ oc::PlanInput plan_input(const oc_grid *g, const oc_stencil *st, const oc_config
   in.share = c->share_overlap >= 0;
   in.in_place = c->in_place != 0;
   in.fused_codec = c->fused_codec != 0;
+  in.load_rate = c->load_rate_bits;
+  // with an error budget, rate_bits is the largest rate the pilot may pick:
+  // the plan is sized for a load rate of at least that
+  if (c->error_budget > 0.f && c->load_rate_bits > 0) in.load_rate = std::max(c->load_rate_bits, c->rate_bits);
   return in;
 }
 
@@ -247,7 +252,7 @@ int issue(oc_handle *h, const std::vector<oc::Op> &ops, const oc::Plan &p) {
           x.ok(hipMemcpyAsync(h->arena + o.dev_dst, h->arena + o.dev_src, (size_t)o.bytes,
                               hipMemcpyDeviceToDevice, s));
         } else {
-          x.ok(oc::launch_decode(h->arena + o.dev_src, p.in.nx, p.in.ny, o.z_hi, p.in.rate,
+          x.ok(oc::launch_decode(h->arena + o.dev_src, p.in.nx, p.in.ny, o.z_hi, o.rate > 0 ? o.rate : p.in.rate,
                                  (float *)(h->arena + o.dev_dst), s, kt));
           bdec += blocks_per_layer * (uint64_t)o.z_hi;
         }
@@ -513,8 +518,8 @@ int load_field(oc_handle *h, const float *src, uint8_t *dst, bool coded) {
   }
   uint8_t *work[2], *stage[2];
   const int64_t chunk = io_buffers(h, work, stage);
-  // level 0 receives the codes; level 1 holds nothing yet
-  return encode_field(h, src, dst, p.in.rate, chunk, work, stage, bounce_region(h, 1, chunk));
+  // level 0 receives the codes (at the load rate); level 1 holds nothing yet
+  return encode_field(h, src, dst, p.load_rate, chunk, work, stage, bounce_region(h, 1, chunk));
 }
 
 // Host store `src` back to a host FP32 field: a copy, or the codes decoded on
@@ -525,6 +530,8 @@ int load_field(oc_handle *h, const float *src, uint8_t *dst, bool coded) {
 int store_field(oc_handle *h, const uint8_t *src, float *dst, bool coded) {
   const oc::Plan &p = h->plan;
   const size_t pb = p.plane_bytes;
+  const int rate = coded ? (h->level_rate > 0 ? h->level_rate : p.in.rate) : 0;
+  const size_t lb = coded ? oc::coded_layer_bytes(p.in.nx, p.in.ny, rate) : 0;
   if (!coded) {
     par_bytes(dst, src, pb * (size_t)p.in.nz);
     return OC_OK;
@@ -548,11 +555,11 @@ int store_field(oc_handle *h, const uint8_t *src, float *dst, bool coded) {
     const int b = (int)(c & 1);
     const int64_t n = std::min<int64_t>(chunk, p.in.nz - z);
     if (c >= 2) x.ok(hipStreamWaitEvent(h->s[0], ev[3 * b + 2], 0));   // pair b copied out
-    x.ok(hipMemcpyAsync(stage[b], src + (size_t)(z / 4) * p.layer_bytes, (size_t)(n / 4) * p.layer_bytes,
-                        hipMemcpyHostToDevice, h->s[0]));
+    x.ok(hipMemcpyAsync(stage[b], src + (size_t)(z / 4) * lb, (size_t)(n / 4) * lb, hipMemcpyHostToDevice,
+                        h->s[0]));
     x.ok(hipEventRecord(ev[3 * b], h->s[0]));
     x.ok(hipStreamWaitEvent(h->s[1], ev[3 * b], 0));
-    x.ok(oc::launch_decode(stage[b], p.in.nx, p.in.ny, n / 4, p.in.rate, (float *)work[b], h->s[1]));
+    x.ok(oc::launch_decode(stage[b], p.in.nx, p.in.ny, n / 4, rate, (float *)work[b], h->s[1]));
     x.ok(hipEventRecord(ev[3 * b + 1], h->s[1]));
     x.ok(hipStreamWaitEvent(h->s[2], ev[3 * b + 1], 0));
     uint8_t *to = bounce ? bounce + b * half : (uint8_t *)dst + (size_t)z * pb;
@@ -595,7 +602,7 @@ PilotLayout pilot_layout(const oc::PlanInput &in, int64_t planes) {
   L.x = o, o += fb;
   L.y = o, o += fb;
   if (in.c0_field) L.c0 = o, o += fb;
-  L.codes = o, o += up((size_t)(planes / 4) * oc::coded_layer_bytes(in.nx, in.ny, in.rate));
+  L.codes = o, o += up((size_t)(planes / 4) * oc::coded_layer_bytes(in.nx, in.ny, std::max(in.rate, in.load_rate)));
   L.parts = o, o += up((size_t)oc::kDiffErrParts * 3u * sizeof(double));
   L.out = o, o += up(3u * sizeof(double));
   L.need = o;
@@ -665,17 +672,21 @@ int pick_rate(oc_handle *h, const float *u, const float *c0f) {
   const int64_t layers = planes / 4;
   std::vector<double> err((size_t)rmax + 1, -1.0);
   int runs = 0;
+  // the loaded field is encoded at the load rate (at least R), the residencies at R
+  const int load_user = h->cfg.load_rate_bits;
   auto run = [&](int R) -> double {
     if (err[(size_t)R] >= 0.0) return err[(size_t)R];
-    x.ok(oc::launch_encode(U0, nx, ny, layers, R, CD, s));
+    int rin = std::max(load_user, R);
+    x.ok(oc::launch_encode(U0, nx, ny, layers, rin, CD, s));
     for (int64_t done = 0; done < steps && x.st == OC_OK;) {
       const int64_t n = std::min<int64_t>(k, steps - done);
-      x.ok(oc::launch_decode(CD, nx, ny, layers, R, X, s));
+      x.ok(oc::launch_decode(CD, nx, ny, layers, rin, X, s));
+      rin = R;
       const float *res = steps_on(X, n, Y, X);
       x.ok(oc::launch_encode(res, nx, ny, layers, R, CD, s));
       done += n;
     }
-    x.ok(oc::launch_decode(CD, nx, ny, layers, R, X, s));
+    x.ok(oc::launch_decode(CD, nx, ny, layers, rin, X, s));
     x.ok(oc::launch_diff_error(RF, X, planes * nx * ny, parts, dout, s));
     double sums[3] = {0.0, 0.0, 0.0};
     x.ok(hipMemcpyAsync(sums, dout, sizeof sums, hipMemcpyDeviceToHost, s));
@@ -708,6 +719,7 @@ int pick_rate(oc_handle *h, const float *u, const float *c0f) {
   if (cr) return cr;
   oc::PlanInput pin = in;
   pin.rate = best;
+  pin.load_rate = load_user > 0 ? std::max(load_user, best) : 0;
   oc::Plan np;
   const int pr = oc::make_plan(pin, &np);
   if (pr != oc::ST_OK) return pr;
@@ -1066,6 +1078,7 @@ int oc_load(oc_handle *h, const float *u, const float *aux, const float *vel) {
       return r;
     }
     if (p.in.c0_field) par_bytes(h->host[2], aux, (size_t)p.host_aux_bytes);
+    h->level_rate = p.coded ? p.load_rate : 0;
     h->loaded = true;
     h->time_index = 0;
     return OC_OK;
@@ -1085,12 +1098,13 @@ int run_steps(oc_handle *h, int64_t steps, const oc::CkptOut *ck) {
   const int64_t sweeps = (steps + k - 1) / k;
   const int steps_last = (int)(steps - (sweeps - 1) * k);
   const int64_t t_key = p.in.kind == oc::KIND_WAVE25 ? h->time_index : 0;
-  int64_t key[4] = {sweeps, steps_last, h->cur, t_key};
+  const int rate0 = p.coded ? h->level_rate : 0;
+  int64_t key[5] = {sweeps, steps_last, h->cur, t_key, rate0};
   if (ck) {
-    oc::build_ops(p, sweeps, steps_last, h->cur, h->time_index, &h->ops, ck);
+    oc::build_ops(p, sweeps, steps_last, h->cur, h->time_index, &h->ops, ck, rate0);
     std::memset(h->ops_key, 0xff, sizeof h->ops_key);   // not a valid key
   } else if (std::memcmp(key, h->ops_key, sizeof key) != 0) {
-    oc::build_ops(p, sweeps, steps_last, h->cur, h->time_index, &h->ops);
+    oc::build_ops(p, sweeps, steps_last, h->cur, h->time_index, &h->ops, nullptr, rate0);
     std::memcpy(h->ops_key, key, sizeof key);
   }
   auto t0 = std::chrono::steady_clock::now();
@@ -1099,6 +1113,7 @@ int run_steps(oc_handle *h, int64_t steps, const oc::CkptOut *ck) {
   if (r) return r;
   int cr = p.coded ? codec_check_and_clear() : OC_OK;
   if (!p.in_place) h->cur = (int)((h->cur + sweeps) & 1);
+  if (p.coded) h->level_rate = p.in.rate;   // every sweep encodes at the rate
   h->time_index += steps;
   double wall = std::chrono::duration<double>(t1 - t0).count();
   h->stats.wall_s = wall;
@@ -1495,7 +1510,7 @@ int64_t oc_debug_plan_ops(const oc_grid *g, const oc_stencil *st, const oc_confi
     int r = oc::make_plan(plan_input(g, st, cfg), &p);
     if (r != oc::ST_OK) return r;
     std::vector<oc::Op> ops;
-    oc::build_ops(p, sweeps, p.in.k, 0, 0, &ops);
+    oc::build_ops(p, sweeps, p.in.k, 0, 0, &ops, nullptr, p.load_rate);
     if (n_waits) {
       int64_t w = 0;
       for (const auto &o : ops) w += o.type == oc::OP_WAIT;
@@ -1515,7 +1530,7 @@ int64_t oc_debug_plan_dump(const oc_grid *g, const oc_stencil *st, const oc_conf
     int r = oc::make_plan(plan_input(g, st, cfg), &p);
     if (r != oc::ST_OK) return r;
     std::vector<oc::Op> ops;
-    oc::build_ops(p, sweeps, p.in.k, 0, 0, &ops);
+    oc::build_ops(p, sweeps, p.in.k, 0, 0, &ops, nullptr, p.load_rate);
     std::string s = oc::dump_ops(ops);
     if (buf && len) {
       size_t n = std::min(len - 1, s.size());
@@ -1547,7 +1562,7 @@ int64_t check_plan_impl(const oc_grid *g, const oc_stencil *st, const oc_config 
     ck.rate = ckpt_rate;
   }
   std::vector<oc::Op> ops;
-  oc::build_ops(p, sweeps, p.in.k, 0, 0, &ops, ckpt_rate >= 0 ? &ck : nullptr);
+  oc::build_ops(p, sweeps, p.in.k, 0, 0, &ops, ckpt_rate >= 0 ? &ck : nullptr, p.load_rate);
   if (mutate == 0 && i == -1) {   // the number of waits
     int64_t n = 0;
     for (const oc::Op &o : ops) n += o.type == oc::OP_WAIT;

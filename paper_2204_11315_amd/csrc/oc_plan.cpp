@@ -76,7 +76,7 @@ static size_t carve(Plan *p) {
   p->stage_bytes = 0;
   if (p->coded) {
     int fields_in = p->n_rw + (p->ro_coded ? 1 : 0);
-    p->stage_bytes = align256((size_t)(p->P / 4) * p->layer_bytes * (size_t)fields_in);
+    p->stage_bytes = align256((size_t)(p->P / 4) * p->max_layer_bytes * (size_t)fields_in);
     for (int s = 0; s < p->slots; s++) {
       p->off_stage[s] = off;
       off += p->stage_bytes;
@@ -111,6 +111,13 @@ int make_plan(const PlanInput &in, Plan *out) {
   if (in.nx <= 0 || in.ny <= 0 || in.nz <= 0 || in.k < 1 || in.rate < 0 || in.rate > 32 ||
       in.slab_planes < 0 || (in.kind != KIND_STAR7 && in.kind != KIND_WAVE25))
     return ST_ARG;
+  // a load rate: coded runs only, at least the rate; the 25-point fields and
+  // the fused kernel (one rate in and out) take one rate
+  if (in.load_rate < 0 || in.load_rate > 32 || (in.load_rate > 0 && (in.rate == 0 || in.load_rate < in.rate)))
+    return ST_ARG;
+  // (one host level updated in place would hold codes at both strides at once)
+  if (in.load_rate > in.rate && (in.kind != KIND_STAR7 || in.fused_codec || in.in_place))
+    return ST_UNSUPPORTED;
   if (in.kind == KIND_WAVE25 && in.c0_field) return ST_ARG;
   if (in.slots < 2 || in.slots > kMaxSlots || in.prefetch >= in.slots) return ST_ARG;
   if (in.fuse < 1 || in.fuse > kMaxFused) return ST_ARG;
@@ -134,6 +141,8 @@ int make_plan(const PlanInput &in, Plan *out) {
   p.ro_coded = p.coded && in.kind == KIND_WAVE25;
   p.plane_bytes = (size_t)in.nx * (size_t)in.ny * 4u;
   p.layer_bytes = p.coded ? coded_layer_bytes(in.nx, in.ny, in.rate) : 0;
+  p.load_rate = std::max(in.load_rate, in.rate);
+  p.max_layer_bytes = p.coded ? coded_layer_bytes(in.nx, in.ny, p.load_rate) : 0;
   int64_t h = (int64_t)in.k * p.r;
   p.halo = p.coded ? (h + 3) / 4 * 4 : h;
   // working buffers: STAR7 a, b (+ c0 slab); WAVE25 v, pa, pb
@@ -181,7 +190,7 @@ int make_plan(const PlanInput &in, Plan *out) {
   }
   // host storage
   int64_t cells = in.nx * in.ny * in.nz;
-  p.host_field_bytes = p.coded ? (size_t)(in.nz / 4) * p.layer_bytes : (size_t)cells * 4u;
+  p.host_field_bytes = p.coded ? (size_t)(in.nz / 4) * p.max_layer_bytes : (size_t)cells * 4u;
   p.host_level_bytes = p.host_field_bytes * (size_t)p.n_rw;
   p.host_aux_bytes = 0;
   if (in.kind == KIND_WAVE25) p.host_aux_bytes = p.host_field_bytes;
@@ -302,8 +311,15 @@ bool ckpt_out_supported(const Plan &p, int rate) {
 }
 
 void build_ops(const Plan &p, int64_t sweeps, int steps_last, int src, int64_t step0,
-               std::vector<Op> *ops, const CkptOut *ck) {
+               std::vector<Op> *ops, const CkptOut *ck, int rate0) {
   if (ck && !ckpt_out_supported(p, ck->rate)) ck = nullptr;
+  // the first sweep reads codes at rate0 (the loaded codes), later sweeps at
+  // the plan's rate; coded layers keep their positions, at each rate's stride
+  const int in_rate0 = (p.coded && rate0 > 0) ? rate0 : p.in.rate;
+  auto rate_in = [&](int t) { return t == 0 ? in_rate0 : p.in.rate; };
+  auto lb_in = [&](int t) {
+    return rate_in(t) == p.in.rate ? p.layer_bytes : coded_layer_bytes(p.in.nx, p.in.ny, rate_in(t));
+  };
   ops->clear();
   Builder B(p, ops);
   const int ns = (int)p.slabs.size();
@@ -411,10 +427,11 @@ void build_ops(const Plan &p, int64_t sweeps, int steps_last, int src, int64_t s
       if (fin[f].coded) {
         // staging slot: layer of local plane z at position z / 4, so the
         // planes shared with the next slab lie past the encoder's output
-        o.dev_dst = (int64_t)(p.off_stage[x.q] + (size_t)ncoded * (size_t)(x.sl->planes / 4) * p.layer_bytes +
-                              (size_t)((x.loc0 + skip) / 4) * p.layer_bytes);
-        o.host_off = (int64_t)(fin[f].host_base + (size_t)((x.sl->l0 + skip) / 4) * p.layer_bytes);
-        o.bytes = (int64_t)((size_t)((x.nload - skip) / 4) * p.layer_bytes);
+        const size_t lb = lb_in(x.t);
+        o.dev_dst = (int64_t)(p.off_stage[x.q] + (size_t)ncoded * (size_t)(x.sl->planes / 4) * lb +
+                              (size_t)((x.loc0 + skip) / 4) * lb);
+        o.host_off = (int64_t)(fin[f].host_base + (size_t)((x.sl->l0 + skip) / 4) * lb);
+        o.bytes = (int64_t)((size_t)((x.nload - skip) / 4) * lb);
         ncoded++;
       } else if (c0_staged && fin[f].buf == 2) {
         o.dev_dst = (int64_t)(p.off_ro_stage[x.q] + (size_t)(x.loc0 + skip) * p.plane_bytes);
@@ -449,11 +466,12 @@ void build_ops(const Plan &p, int64_t sweeps, int steps_last, int src, int64_t s
         if (!shared_in(fin[f], f)) continue;
         Op o = B.blank(OP_DEC, S_COMPUTE);
         if (fin[f].coded) {
-          o.dev_src = (int64_t)(p.off_stage[x.pq] + (size_t)nsh * (size_t)(x.pv_planes / 4) * p.layer_bytes +
-                                (size_t)(x.sh_src / 4) * p.layer_bytes);
-          o.dev_dst = (int64_t)(p.off_stage[x.q] + (size_t)nsh * (size_t)(x.sl->planes / 4) * p.layer_bytes +
-                                (size_t)(x.loc0 / 4) * p.layer_bytes);
-          o.bytes = (int64_t)((size_t)(x.sh / 4) * p.layer_bytes);
+          const size_t lb = lb_in(x.t);   // the previous slab is of the same sweep
+          o.dev_src = (int64_t)(p.off_stage[x.pq] + (size_t)nsh * (size_t)(x.pv_planes / 4) * lb +
+                                (size_t)(x.sh_src / 4) * lb);
+          o.dev_dst = (int64_t)(p.off_stage[x.q] + (size_t)nsh * (size_t)(x.sl->planes / 4) * lb +
+                                (size_t)(x.loc0 / 4) * lb);
+          o.bytes = (int64_t)((size_t)(x.sh / 4) * lb);
           nsh++;
         } else if (stash && fin[f].buf != bv) {
           // a pressure field of an uncompressed wave run: from the stash
@@ -498,8 +516,10 @@ void build_ops(const Plan &p, int64_t sweeps, int steps_last, int src, int64_t s
     for (int f = 0; f < nin; f++) {
       if (fin[f].coded) {
         Op o = B.blank(OP_DEC, S_COMPUTE);
-        o.dev_src = (int64_t)(p.off_stage[x.q] + (size_t)ncoded * (size_t)(x.sl->planes / 4) * p.layer_bytes +
-                              (size_t)(x.loc0 / 4) * p.layer_bytes);
+        const size_t lb = lb_in(x.t);
+        if (rate_in(x.t) != p.in.rate) o.rate = rate_in(x.t);
+        o.dev_src = (int64_t)(p.off_stage[x.q] + (size_t)ncoded * (size_t)(x.sl->planes / 4) * lb +
+                              (size_t)(x.loc0 / 4) * lb);
         o.dev_dst = (int64_t)(B.work(x.q, fin[f].buf) + (size_t)x.loc0 * p.plane_bytes);
         o.z_hi = x.nload / 4;
         o.planes = x.nload;
@@ -694,6 +714,7 @@ int make_adj_plan(const PlanInput &in0, int m, int64_t steps, AdjPlan *out) {
   PlanInput in = in0;
   in.slots = 2;        // two full working sets: the copy-in of the next slab
   in.prefetch = 1;     // overlaps the kernels of the current one
+  in.load_rate = 0;    // the reverse sweeps read checkpoints at their own rate
   AdjPlan a;
   a.m = m;
   a.steps = steps;
@@ -710,6 +731,8 @@ int make_adj_plan(const PlanInput &in0, int m, int64_t steps, AdjPlan *out) {
   p.n_rw = 1;
   p.plane_bytes = (size_t)in.nx * (size_t)in.ny * 4u;
   p.layer_bytes = p.coded ? coded_layer_bytes(in.nx, in.ny, in.rate) : 0;
+  p.load_rate = in.rate;
+  p.max_layer_bytes = p.layer_bytes;
   p.halo = p.coded ? ((int64_t)m + 3) / 4 * 4 : m;
   p.n_work_sets = 2;
   p.n_work_bufs = 7;
@@ -1011,10 +1034,11 @@ std::string dump_ops(const std::vector<Op> &ops) {
     if (o.type == OP_REC || o.type == OP_WAIT)
       snprintf(line, sizeof line, "%zu s%d %s ev=%d\n", i, o.stream, names[o.type], o.ev);
     else
-      snprintf(line, sizeof line, "%zu s%d %s sweep=%d slab=%d src=%lld dst=%lld host=%d off=%lld bytes=%lld z=[%lld,%lld) lv=%d\n",
+      snprintf(line, sizeof line,
+               "%zu s%d %s sweep=%d slab=%d src=%lld dst=%lld host=%d off=%lld bytes=%lld z=[%lld,%lld) lv=%d rate=%d\n",
                i, o.stream, names[o.type], o.sweep, o.slab, (long long)o.dev_src, (long long)o.dev_dst,
                o.host_id, (long long)o.host_off, (long long)o.bytes, (long long)o.z_lo, (long long)o.z_hi,
-               (int)o.levels);
+               (int)o.levels, (int)o.rate);
     out += line;
   }
   return out;
@@ -1050,7 +1074,8 @@ void accesses(const Plan &p, const Op &o, std::vector<Access> *a) {
         dev(o.dev_src, o.bytes, false);
         dev(o.dev_dst, o.bytes, true);
       } else {
-        dev(o.dev_src, (int64_t)((size_t)o.z_hi * p.layer_bytes), false);
+        const size_t lb = o.rate > 0 ? coded_layer_bytes(p.in.nx, p.in.ny, o.rate) : p.layer_bytes;
+        dev(o.dev_src, (int64_t)((size_t)o.z_hi * lb), false);
         dev(o.dev_dst, (int64_t)((size_t)o.z_hi * 4 * p.plane_bytes), true);
       }
       break;
@@ -1202,6 +1227,11 @@ int64_t check_ops(const Plan &p, const std::vector<Op> &ops, std::string *why,
     }
   }
   // every sweep must write back each host store it writes, whole and once
+  // (a level sized for a larger load rate is written up to the codes at the rate)
+  const int64_t level_written =
+      (p.coded && p.load_rate > p.in.rate)
+          ? (int64_t)((size_t)(p.n_rw - 1) * p.host_field_bytes + (size_t)(p.in.nz / 4) * p.layer_bytes)
+          : (int64_t)p.host_level_bytes;
   if (check_writeback) {
     int max_sweep = -1;
     for (const Op &o : ops) max_sweep = std::max(max_sweep, (int)o.sweep);
@@ -1223,7 +1253,7 @@ int64_t check_ops(const Plan &p, const std::vector<Op> &ops, std::string *why,
           if (r.first != at) break;
           at = r.second;
         }
-        if (id > HOST_LEVEL1 ? at != rs.back().second : at != (int64_t)p.host_level_bytes) {
+        if (id > HOST_LEVEL1 ? at != rs.back().second : at != level_written) {
           bad++;
           if (why && why->empty())
             *why = "sweep " + std::to_string(t) + " does not write back store " +

@@ -76,6 +76,7 @@ struct PlanInput {
   bool share = false;     // keep the overlap of consecutive slabs on the device
   bool in_place = false;  // one host level, updated in place (needs sharing or one slab)
   bool fused_codec = false;  // coded STAR7: one decode / k steps / encode kernel per slab
+  int load_rate = 0;         // rate of the loaded codes (0 = rate), >= rate; STAR7, three kernels
 };
 
 constexpr int kMaxSlots = 8;
@@ -93,6 +94,8 @@ struct Plan {
   bool ro_coded = false;   // read-only field kept coded on the host
   size_t plane_bytes = 0;  // nx*ny*4
   size_t layer_bytes = 0;  // coded bytes of 4 planes
+  int load_rate = 0;       // rate of the codes oc_load writes (= in.rate unless set)
+  size_t max_layer_bytes = 0;   // coded bytes of 4 planes at the larger of the two rates
   bool share = false;      // region sharing in effect (STAR7; raw only with one stencil group)
   bool in_place = false;   // every sweep reads and writes host level 0
   int slots = 3;           // staging ring slots
@@ -161,8 +164,11 @@ struct CkptOut {
   size_t host_off = 0;   // byte offset of this checkpoint in the store
 };
 bool ckpt_out_supported(const Plan &p, int rate);
+// rate0: the rate of the codes in host level `src` (the plan's load rate right
+// after oc_load, its rate after any sweep; 0 = the plan's rate).  The first
+// sweep copies and decodes them at that rate; every sweep encodes at the rate.
 void build_ops(const Plan &p, int64_t sweeps, int steps_last, int src, int64_t step0,
-               std::vector<Op> *ops, const CkptOut *ck = nullptr);
+               std::vector<Op> *ops, const CkptOut *ck = nullptr, int rate0 = 0);
 
 // ---- adjoint (reverse sweeps over checkpoint segments) ------------------
 // Forward states u_{s*m} (s = 0 .. nseg-1) are kept as checkpoints; segment s

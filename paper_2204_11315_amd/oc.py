@@ -51,7 +51,7 @@ class Config(ctypes.Structure):
                 ("fuse_steps", ctypes.c_int32), ("copy_back", ctypes.c_int32),
                 ("share_overlap", ctypes.c_int32), ("in_place", ctypes.c_int32),
                 ("error_budget", ctypes.c_float), ("error_steps", ctypes.c_int32),
-                ("fused_codec", ctypes.c_int32)]
+                ("fused_codec", ctypes.c_int32), ("load_rate_bits", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -195,7 +195,7 @@ def host_aux_bytes(shape, stencil: Stencil, rate: int) -> int:
 def plan_config(k: int, slab_planes: int, rate: int, single_buffer: bool = True,
                 budget: int = 0, ring_slots: int = 0, prefetch: int = 0, fuse: int = 0,
                 share: bool = False, in_place: bool = False, error_budget: float = 0.0,
-                error_steps: int = 0, fused_codec: bool = False) -> Config:
+                error_steps: int = 0, fused_codec: bool = False, load_rate: int = 0) -> Config:
     """A Config carrying only the plan fields."""
     cfg = Config()
     cfg.k = int(k)
@@ -211,28 +211,31 @@ def plan_config(k: int, slab_planes: int, rate: int, single_buffer: bool = True,
     cfg.error_budget = float(error_budget)
     cfg.error_steps = int(error_steps)
     cfg.fused_codec = 1 if fused_codec else 0
+    cfg.load_rate_bits = int(load_rate)
     return cfg
 
 
 def plan_bytes(shape, stencil: Stencil, k: int, slab_planes: int, rate: int,
                single_buffer: bool = True, budget: int = 0, ring_slots: int = 0,
                prefetch: int = 0, fuse: int = 0, share: bool = False,
-               error_budget: float = 0.0, error_steps: int = 0, fused_codec: bool = False) -> int:
+               error_budget: float = 0.0, error_steps: int = 0, fused_codec: bool = False,
+               load_rate: int = 0, in_place: bool = False) -> int:
     """Device bytes of the plan (with an error budget: at least the pilot's
-    sample within `budget`)."""
+    sample within `budget`); 0 if no plan exists."""
     g = make_grid(shape)
     cfg = plan_config(k, slab_planes, rate, single_buffer, budget, ring_slots, prefetch, fuse, share,
-                      error_budget=error_budget, error_steps=error_steps, fused_codec=fused_codec)
+                      in_place, error_budget=error_budget, error_steps=error_steps,
+                      fused_codec=fused_codec, load_rate=load_rate)
     return int(lib().oc_plan_bytes(_ref(g), _ref(stencil), _ref(cfg)))
 
 
 def check_plan(shape, stencil: Stencil, k: int, slab_planes: int, rate: int, sweeps: int,
                single_buffer: bool = True, budget: int = 0, mutate: int = 0, i: int = 0,
                ring_slots: int = 0, prefetch: int = 0, fuse: int = 0, share: bool = False,
-               in_place: bool = False, fused_codec: bool = False) -> int:
+               in_place: bool = False, fused_codec: bool = False, load_rate: int = 0) -> int:
     g = make_grid(shape)
     cfg = plan_config(k, slab_planes, rate, single_buffer, budget, ring_slots, prefetch, fuse, share,
-                      in_place, fused_codec=fused_codec)
+                      in_place, fused_codec=fused_codec, load_rate=load_rate)
     return int(lib().oc_debug_check_plan(_ref(g), _ref(stencil), _ref(cfg), int(sweeps),
                                          int(mutate), int(i)))
 
@@ -252,10 +255,10 @@ def check_plan_ckpt(shape, stencil: Stencil, k: int, slab_planes: int, sweeps: i
 def plan_ops(shape, stencil: Stencil, k: int, slab_planes: int, rate: int, sweeps: int,
              single_buffer: bool = True, budget: int = 0, ring_slots: int = 0, prefetch: int = 0,
              fuse: int = 0, share: bool = False,
-             in_place: bool = False, fused_codec: bool = False):
+             in_place: bool = False, fused_codec: bool = False, load_rate: int = 0):
     g = make_grid(shape)
     cfg = plan_config(k, slab_planes, rate, single_buffer, budget, ring_slots, prefetch, fuse, share,
-                      in_place, fused_codec=fused_codec)
+                      in_place, fused_codec=fused_codec, load_rate=load_rate)
     nw = ctypes.c_int64(0)
     n = int(lib().oc_debug_plan_ops(_ref(g), _ref(stencil), _ref(cfg), int(sweeps), _ref(nw)))
     return n, int(nw.value)
@@ -264,11 +267,11 @@ def plan_ops(shape, stencil: Stencil, k: int, slab_planes: int, rate: int, sweep
 def plan_dump(shape, stencil: Stencil, k: int, slab_planes: int, rate: int, sweeps: int,
               single_buffer: bool = True, budget: int = 0, ring_slots: int = 0,
               prefetch: int = 0, fuse: int = 0, share: bool = False,
-              in_place: bool = False, fused_codec: bool = False) -> str:
+              in_place: bool = False, fused_codec: bool = False, load_rate: int = 0) -> str:
     """Text listing of the operation list the executor would issue."""
     g = make_grid(shape)
     cfg = plan_config(k, slab_planes, rate, single_buffer, budget, ring_slots, prefetch, fuse, share,
-                      in_place, fused_codec=fused_codec)
+                      in_place, fused_codec=fused_codec, load_rate=load_rate)
     n = int(lib().oc_debug_plan_dump(_ref(g), _ref(stencil), _ref(cfg), int(sweeps), None, 0))
     if n < 0:
         raise OCError(n, "oc_debug_plan_dump", status_str(n))
@@ -523,7 +526,7 @@ class OutOfCore:
                  timing: bool = False, ring_slots: int = 0, prefetch: int = 0, device=None,
                  stencil: Stencil = None, fuse: int = 0, copy_back: int = 0, share: bool = True,
                  in_place: bool = False, full_arena: bool = False, error_budget: float = 0.0,
-                 error_steps: int = 0, fused_codec: bool = False):
+                 error_steps: int = 0, fused_codec: bool = False, load_rate: int = 0):
         torch = _torch()
         self.shape = tuple(int(v) for v in shape)
         self.rate = int(rate)
@@ -534,8 +537,13 @@ class OutOfCore:
         self.device = torch.device(device if device is not None else "cuda")
         need = plan_bytes(self.shape, self.stencil, k, slab_planes, rate, single_buffer, budget,
                           ring_slots, prefetch, fuse, share, error_budget=error_budget,
-                          error_steps=error_steps, fused_codec=fused_codec)
+                          error_steps=error_steps, fused_codec=fused_codec, load_rate=load_rate)
         if need == 0:
+            if load_rate and (rate == 0 or load_rate > 32 or (load_rate < rate and not error_budget)):
+                raise OCError(OC_ERR_ARG, "plan", "the load rate must lie in rate..32 on a coded run")
+            if load_rate > rate and (self.stencil.kind != OC_STAR7 or fused_codec):
+                raise OCError(OC_ERR_UNSUPPORTED, "plan",
+                              "a separate load rate needs the 7-point stencil and three kernels")
             if fused_codec and not (rate > 0 and self.stencil.kind == OC_STAR7 and not c0_field
                                     and k <= 4 and rate <= 16):
                 raise OCError(OC_ERR_UNSUPPORTED, "plan",
@@ -547,7 +555,8 @@ class OutOfCore:
         arena_bytes = int(budget) if full_arena else int(need)
         self.arena = torch.empty(arena_bytes, dtype=torch.uint8, device=self.device)
         self.streams = pipeline_streams(self.device)
-        lb = host_level_bytes(self.shape, self.stencil, rate)
+        # host levels hold codes at the larger of the rate and the load rate
+        lb = host_level_bytes(self.shape, self.stencil, max(int(rate), int(load_rate)))
         self.levels = [torch.empty(lb, dtype=torch.uint8, pin_memory=True)
                        for _ in range(1 if in_place else 2)]
         ab = host_aux_bytes(self.shape, self.stencil, rate)
@@ -576,6 +585,7 @@ class OutOfCore:
         cfg.error_budget = float(error_budget)
         cfg.error_steps = int(error_steps)
         cfg.fused_codec = 1 if fused_codec else 0
+        cfg.load_rate_bits = int(load_rate)
         self.cfg = cfg
         h = ctypes.c_void_p()
         torch.cuda.synchronize(self.device)

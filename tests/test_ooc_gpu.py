@@ -31,17 +31,24 @@ def rel_l2(a, b):
     return np.linalg.norm(a - b) / np.linalg.norm(b)
 
 
-def gpu_compressed_incore(u0, R, k, steps, c=C):
+def gpu_compressed_incore(u0, R, k, steps, c=C, load_rate=0, runs=None):
+    """The compressed path as a composition of the GPU's own codec and in-core
+    steps: the load at `load_rate` (else R), residencies of k steps within each
+    of `runs` (the job split into oc_run calls; default one run of `steps`),
+    every encode after a residency at R."""
     shape = u0.shape
-    codes = oc.compress(_dev(u0), R)
-    done = 0
-    while done < steps:
-        s = min(k, steps - done)
-        u = oc.decompress(codes, shape, R)
-        u = oc.star7_incore(u, c, s)
-        codes = oc.compress(u, R)
-        done += s
-    out = oc.decompress(codes, shape, R).cpu().numpy()
+    rate = load_rate or R
+    codes = oc.compress(_dev(u0), rate)
+    for n in (runs or [steps]):
+        done = 0
+        while done < n:
+            s = min(k, n - done)
+            u = oc.decompress(codes, shape, rate)
+            u = oc.star7_incore(u, c, s)
+            rate = R
+            codes = oc.compress(u, rate)
+            done += s
+    out = oc.decompress(codes, shape, rate).cpu().numpy()
     assert oc.codec_status() == oc.OC_OK
     return out
 
@@ -333,3 +340,54 @@ def test_overlapping_host_levels_are_rejected():
             assert st == oc.OC_ERR_ARG
     finally:
         o.close()
+
+
+# ---- a separate rate for the loaded codes -------------------------------------------------
+@pytest.mark.parametrize("R,L", [(3, 8), (5, 9)])
+@pytest.mark.parametrize("swb", [True, False])
+@pytest.mark.parametrize("k,S,runs", [(4, 8, [12]), (3, 12, [7]), (4, 8, [5, 6]), (2, 44, [0, 4])])
+def test_load_rate_ooc_equals_incore_composition_bitwise(R, L, swb, k, S, runs):
+    # the first residency after oc_load decodes at the load rate; a second
+    # oc_run (or a run after an empty one) continues from codes at R
+    u0 = inputs.grf_field(SHAPE, seed=11)
+    got, st = run_ooc(u0, sum(runs), runs=runs, k=k, rate=R, slab_planes=S, single_buffer=swb,
+                      budget=64 << 20, load_rate=L)
+    want = gpu_compressed_incore(u0, R, k, sum(runs), load_rate=L, runs=[r for r in runs if r])
+    assert np.array_equal(got.view(np.uint32), want.view(np.uint32))
+    assert st["peak_dev_bytes"] == oc.plan_bytes(SHAPE, oc.make_star7(C), k, S, R, swb, 64 << 20,
+                                                 share=True, load_rate=L)
+
+
+def test_load_rate_store_without_steps_decodes_at_the_load_rate():
+    u0 = inputs.grf_field(SHAPE, seed=12)
+    got, _ = run_ooc(u0, 0, runs=[], k=4, rate=3, slab_planes=8, budget=64 << 20, load_rate=10)
+    want = oc.decompress(oc.compress(_dev(u0), 10), SHAPE, 10).cpu().numpy()
+    assert np.array_equal(got.view(np.uint32), want.view(np.uint32))
+
+
+@pytest.mark.parametrize("shape,S,seed", [(SHAPE, 8, 8), ((64, 64, 64), 16, 8)])
+def test_load_rate_close_to_oracle_composition(shape, S, seed):
+    steps, k, R, L = 10, 4, 3, 8
+    u0 = inputs.grf_field(shape, seed=seed)
+    got, _ = run_ooc(u0, steps, k=k, rate=R, slab_planes=S, load_rate=L)
+    want = oracle.compressed_sweeps(u0, C, steps, k, R, load_rate=L)
+    ref64 = oracle.star7_run(u0, C, steps)
+    e_comp = rel_l2(want, ref64)
+    n_res = -(-steps // k)
+    assert rel_l2(got, want) <= 10.0 * np.sqrt(n_res * 2.0 ** -24 * e_comp)
+    # and the load rate helps: the same job with every encode at R is worse
+    plain = oracle.compressed_sweeps(u0, C, steps, k, R)
+    assert e_comp < rel_l2(plain, ref64)
+
+
+def test_load_rate_refused_where_unsupported():
+    u0 = inputs.grf_field(SHAPE, seed=13)
+    with pytest.raises(oc.OCError) as e:
+        oc.OutOfCore(SHAPE, k=4, rate=3, slab_planes=8, budget=64 << 20, load_rate=8, fused_codec=True)
+    assert e.value.status == oc.OC_ERR_UNSUPPORTED
+    with pytest.raises(oc.OCError) as e:
+        oc.OutOfCore(SHAPE, k=4, rate=5, slab_planes=8, budget=64 << 20, load_rate=4)
+    assert e.value.status == oc.OC_ERR_ARG
+    with pytest.raises(oc.OCError) as e:
+        oc.OutOfCore(SHAPE, k=4, rate=3, slab_planes=8, budget=64 << 20, load_rate=8, in_place=True)
+    assert e.value.status == oc.OC_ERR_UNSUPPORTED

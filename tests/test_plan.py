@@ -524,3 +524,61 @@ def test_codec_entry_points_check_arguments_before_touching_a_device():
     assert L.oc_codec_compress(p16, 8, 8, 8, 5, p16, nbytes - 1, None) == oc.OC_ERR_ARG
     # the stream check rejects null arguments
     assert L.oc_stream_overlap(None, None, None) == oc.OC_ERR_ARG
+
+
+# ---- a separate rate for the loaded codes ------------------------------------------------
+@pytest.mark.parametrize("shape,k,S", [((40, 12, 16), 4, 8), ((44, 8, 8), 4, 12), ((36, 8, 12), 3, 8),
+                                       ((16, 8, 8), 2, 16)])
+@pytest.mark.parametrize("R,L,swb", [(3, 8, True), (5, 9, False), (1, 32, True)])
+def test_load_rate_operation_list_race_free_and_minimal(shape, k, S, R, L, swb):
+    n, nw = oc.plan_ops(shape, ST, k, S, R, 3, single_buffer=swb, load_rate=L)
+    assert n > 0 and nw > 0
+    assert oc.check_plan(shape, ST, k, S, R, 3, single_buffer=swb, load_rate=L) == 0
+    for i in range(nw):
+        assert oc.check_plan(shape, ST, k, S, R, 3, single_buffer=swb, load_rate=L, mutate=1, i=i) > 0, i
+    assert oc.check_plan(shape, ST, k, S, R, 3, single_buffer=swb, load_rate=L, mutate=2) > 0
+
+
+def test_load_rate_ops_first_sweep_reads_at_the_load_rate():
+    import re
+    shape, k, S, R, L = (40, 12, 16), 4, 8, 3, 8
+    dump = oc.plan_dump(shape, ST, k, S, R, 3, load_rate=L)
+    lb = {r: oc.codec_bytes((4, 12, 16), r) for r in (R, L)}   # bytes of one block layer
+    ops = [dict(re.findall(r"(\w+)=([-\w\[\],)]+)", line), kind=line.split()[2])
+           for line in dump.splitlines() if " ev=" not in line and "SYNC" not in line]
+    decs = [o for o in ops if o["kind"] == "DEC" and not o["z"].startswith("[0,-1")]
+    assert decs and all(int(o["rate"]) == (L if int(o["sweep"]) == 0 else 0) for o in decs)
+    for o in ops:
+        if o["kind"] == "H2D":
+            assert int(o["bytes"]) % lb[L if int(o["sweep"]) == 0 else R] == 0
+        if o["kind"] == "D2H":                                  # every sweep writes at R
+            assert int(o["bytes"]) % lb[R] == 0 and int(o["bytes"]) // lb[R] == 2   # 8 planes
+        if o["kind"] == "ENC":
+            assert int(o["rate"]) == 0
+    # the same plan without a load rate reads every sweep at R
+    plain = oc.plan_dump(shape, ST, k, S, R, 3)
+    assert plain != dump and " rate=8" not in plain
+
+
+def test_load_rate_sizes_slots_and_levels_for_the_larger_rate():
+    shape, k, S = (40, 12, 16), 4, 8
+    lay = lambda r: oc.codec_bytes((4, 12, 16), r)
+    base = oc.plan_bytes(shape, ST, k, S, 3)
+    big = oc.plan_bytes(shape, ST, k, S, 3, load_rate=8)
+    # three ring slots of (S + 2h) / 4 layers each (256-byte aligned) grow from rate 3 to rate 8
+    up = lambda v: (v + 255) // 256 * 256
+    assert big - base == 3 * (up((S + 8) // 4 * lay(8)) - up((S + 8) // 4 * lay(3)))
+    assert oc.plan_bytes(shape, ST, k, S, 3, load_rate=3) == base
+
+
+def test_load_rate_combinations_refused():
+    shape, k, S = (40, 12, 16), 4, 8
+    assert oc.plan_bytes(shape, ST, k, S, 5, load_rate=4) == 0        # below the rate
+    assert oc.plan_bytes(shape, ST, k, S, 5, load_rate=33) == 0
+    assert oc.plan_bytes(shape, ST, k, S, 0, load_rate=8) == 0        # uncompressed
+    assert oc.plan_bytes(shape, ST, k, S, 3, load_rate=8, fused_codec=True) == 0
+    assert oc.plan_bytes(shape, ST, k, S, 3, load_rate=8, in_place=True, share=True) == 0
+    wave = oc.make_wave25(10.0, 1e-3, (4, 4, 4), 15.0, 0.07)
+    assert oc.plan_bytes((48, 16, 16), wave, 2, 16, 8, load_rate=12) == 0
+    # equal rates are the plain plan, for every kind
+    assert oc.plan_bytes((48, 16, 16), wave, 2, 16, 8, load_rate=8) == oc.plan_bytes((48, 16, 16), wave, 2, 16, 8)

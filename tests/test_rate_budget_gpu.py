@@ -139,3 +139,19 @@ def test_budget_needs_the_7_point_stencil_and_steps():
     with pytest.raises(oc.OCError) as e:
         oc.OutOfCore((16, 16, 16), rate=12, k=2, budget=32 << 20, error_budget=1e-3, error_steps=0)
     assert e.value.status == oc.OC_ERR_ARG
+
+
+def test_pick_with_a_load_rate(field):
+    # the pilot encodes the loaded field at the load rate and its residencies
+    # at the candidate rate, as the job does: the pick is no higher than the
+    # pick without a load rate, meets the budget, and the auto-rate handle
+    # runs the fixed-rate plan of its pick with that load rate bit for bit
+    u0, ref = field
+    budget = 1e-3
+    _, st0 = run_job(u0, 16, error_budget=budget, error_steps=STEPS)
+    got, st = run_job(u0, 16, error_budget=budget, error_steps=STEPS, load_rate=12)
+    R = st["rate_bits"]
+    assert R <= st0["rate_bits"]
+    assert st["pilot_rel_l2"] <= budget and rel_l2(got, ref) <= budget
+    fixed, _ = run_job(u0, R, load_rate=max(12, R))
+    assert np.array_equal(got.view(np.uint32), fixed.view(np.uint32))
