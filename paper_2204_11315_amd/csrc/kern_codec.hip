@@ -169,7 +169,8 @@ template <bool ROUNDTRIP>
 __global__ __launch_bounds__(256) void k_decode_t(const uint32_t *__restrict__ in, const float *__restrict__ field,
                                                   int64_t nx, int64_t ny, int64_t nbx, int64_t nby,
                                                   int64_t nblocks, int R, float *__restrict__ out,
-                                                  ErrSums err) {
+                                                  ErrSums err, const uint32_t *__restrict__ in_lo,
+                                                  int64_t lo_words) {
   const int NW = 2 * R;
   const int BITS = 64 * R;
   const int64_t b0 = (int64_t)blockIdx.x * blockDim.x;
@@ -177,20 +178,30 @@ __global__ __launch_bounds__(256) void k_decode_t(const uint32_t *__restrict__ i
   if (!ROUNDTRIP) {
     // coalesced copy of the workgroup's slots into LDS, eight loads in flight
     // per thread before their LDS stores (every workgroup of a launch starts
-    // with this copy, so its latency is not hidden by other waves' work)
+    // with this copy, so its latency is not hidden by other waves' work).
+    // Input words below lo_words come from in_lo.
     const int nslots = (int)min<int64_t>(blockDim.x, nblocks - b0);
     const uint32_t magic = div_magic(NW);
-    const uint32_t *src = in + b0 * NW;
+    const int64_t w0 = b0 * NW;
     const uint32_t total = (uint32_t)(nslots * NW);
-    uint32_t i = threadIdx.x;
-    for (; i + 7 * blockDim.x < total; i += 8 * blockDim.x) {
-      uint32_t v[8];
+    if (w0 < lo_words && w0 + total > lo_words) {
+      // the workgroup straddles the two sources: word by word
+      for (uint32_t i = threadIdx.x; i < total; i += blockDim.x) {
+        const int64_t wi = w0 + i;
+        lds_slots[lds_index(i, NW, magic)] = wi < lo_words ? in_lo[wi] : in[wi];
+      }
+    } else {
+      const uint32_t *src = (w0 < lo_words ? in_lo : in) + w0;
+      uint32_t i = threadIdx.x;
+      for (; i + 7 * blockDim.x < total; i += 8 * blockDim.x) {
+        uint32_t v[8];
 #pragma unroll
-      for (int j = 0; j < 8; j++) v[j] = src[i + j * blockDim.x];
+        for (int j = 0; j < 8; j++) v[j] = src[i + j * blockDim.x];
 #pragma unroll
-      for (int j = 0; j < 8; j++) lds_slots[lds_index(i + j * blockDim.x, NW, magic)] = v[j];
+        for (int j = 0; j < 8; j++) lds_slots[lds_index(i + j * blockDim.x, NW, magic)] = v[j];
+      }
+      for (; i < total; i += blockDim.x) lds_slots[lds_index(i, NW, magic)] = src[i];
     }
-    for (; i < total; i += blockDim.x) lds_slots[lds_index(i, NW, magic)] = src[i];
     __syncthreads();
     if (b >= nblocks) return;
   }
@@ -652,15 +663,19 @@ hipError_t launch_encode(const float *d_in, int64_t nx, int64_t ny, int64_t nlay
 }
 
 hipError_t launch_decode(const void *d_in, int64_t nx, int64_t ny, int64_t nlayers, int rate,
-                         float *d_out, hipStream_t s, KernelTimer *kt) {
+                         float *d_out, hipStream_t s, KernelTimer *kt, const void *d_in_lo,
+                         int64_t lo_bytes) {
   if (rate < 1 || rate > 32) return hipErrorInvalidValue;
   const int64_t nbx = nx / 4, nby = ny / 4, nb = nbx * nby * nlayers;
+  if (lo_bytes < 0 || lo_bytes % 4 || (lo_bytes > 0 && !d_in_lo) || lo_bytes > nb * 8 * rate)
+    return hipErrorInvalidValue;
   if (nb <= 0) return hipSuccess;
   const int threads = codec_threads(rate);
   dim3 grid((unsigned)((nb + threads - 1) / threads));
   hipExtLaunchKernelGGL(k_decode_t<false>, grid, dim3(threads), codec_lds_bytes(rate, threads), s,
                         kt_start(kt), kt_stop(kt), 0, (const uint32_t *)d_in, (const float *)nullptr,
-                        nx, ny, nbx, nby, nb, rate, d_out, ErrSums{nullptr});
+                        nx, ny, nbx, nby, nb, rate, d_out, ErrSums{nullptr},
+                        (const uint32_t *)d_in_lo, lo_bytes / 4);
   return hipGetLastError();
 }
 
@@ -680,7 +695,8 @@ hipError_t launch_codec_error(const float *d_in, int64_t nx, int64_t ny, int64_t
   const int64_t nparts = codec_error_parts(nx, ny, nlayers, rate);
   hipLaunchKernelGGL(k_decode_t<true>, dim3((unsigned)nparts), dim3(threads),
                      codec_lds_bytes(rate, threads), s, (const uint32_t *)nullptr, d_in, nx, ny, nbx,
-                     nby, nb, rate, (float *)nullptr, ErrSums{parts});
+                     nby, nb, rate, (float *)nullptr, ErrSums{parts}, (const uint32_t *)nullptr,
+                     (int64_t)0);
   hipLaunchKernelGGL(k_reduce_parts, dim3(1), dim3(256), 0, s, (const double *)parts, nparts, d_out3);
   return hipGetLastError();
 }

@@ -252,8 +252,12 @@ int issue(oc_handle *h, const std::vector<oc::Op> &ops, const oc::Plan &p) {
           x.ok(hipMemcpyAsync(h->arena + o.dev_dst, h->arena + o.dev_src, (size_t)o.bytes,
                               hipMemcpyDeviceToDevice, s));
         } else {
+          // codes [0, bytes) from dev_src2 when set (shared layers where the
+          // previous slab's copy-in left them)
+          const bool two = o.dev_src2 >= 0 && o.bytes > 0;
           x.ok(oc::launch_decode(h->arena + o.dev_src, p.in.nx, p.in.ny, o.z_hi, o.rate > 0 ? o.rate : p.in.rate,
-                                 (float *)(h->arena + o.dev_dst), s, kt));
+                                 (float *)(h->arena + o.dev_dst), s, kt,
+                                 two ? h->arena + o.dev_src2 : nullptr, two ? o.bytes : 0));
           bdec += blocks_per_layer * (uint64_t)o.z_hi;
         }
         break;

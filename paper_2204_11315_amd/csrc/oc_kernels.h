@@ -27,9 +27,13 @@ inline hipEvent_t kt_stop(KernelTimer *kt) { return kt ? kt->stop : nullptr; }
 hipError_t launch_encode(const float *d_in, int64_t nx, int64_t ny, int64_t nlayers, int rate,
                          void *d_out, hipStream_t s,
                          KernelTimer *kt = nullptr);
+// d_in_lo (optional): the first lo_bytes of the coded input are read from
+// there instead of from d_in (layers a slab shares with the previous one, left
+// in that slab's staging slot); lo_bytes is a multiple of 4.
 hipError_t launch_decode(const void *d_in, int64_t nx, int64_t ny, int64_t nlayers, int rate,
                          float *d_out, hipStream_t s,
-                         KernelTimer *kt = nullptr);
+                         KernelTimer *kt = nullptr, const void *d_in_lo = nullptr,
+                         int64_t lo_bytes = 0);
 // Device address of the codec's sticky error word.
 hipError_t codec_error_word(int **dev_ptr);
 

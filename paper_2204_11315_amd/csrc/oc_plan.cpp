@@ -456,22 +456,46 @@ void build_ops(const Plan &p, int64_t sweeps, int steps_last, int src, int64_t s
     In fin[3];
     const int nin = inputs(x, fin);
     B.wait(S_COMPUTE, B.ev.h2d(x.t & 1, x.j));
+    // region sharing, coded fields with the three-kernel path: the decoder
+    // reads the shared layers where the previous slab's copy-in left them
+    // (that slab's slot, at the field's stride), so no copy precedes it --
+    // unless the next slab shares planes of this one that this slab itself
+    // got from the previous one (slabs thinner than the shared region): those
+    // must then be in this slab's slot, so they are copied there
+    int64_t sh_off[3] = {-1, -1, -1}, sh_bytes[3] = {0, 0, 0};
+    bool sh_after_decode = false;
+    bool read_in_place = !p.fused;
+    if (x.sh > 0 && has_share_copy(g + 1)) {
+      const Geo nx1 = geo(g + 1);
+      if (nx1.sh > 0 && nx1.sh_src < x.loc0 + x.sh) read_in_place = false;
+    }
     if (x.sh > 0) {
       // region sharing: the planes around the common face come from the
-      // previous slab's input (device-to-device moves, raw marker z_hi < 0):
-      // each coded field at its stride in the staging slot, the raw field,
+      // previous slab's input; otherwise by device-to-device moves (raw
+      // marker z_hi < 0): each coded field (fused codec kernel, or planes the
+      // next slab needs) at its stride in the staging slot, the raw field,
       // the raw c0 slab
-      int nsh = 0;
+      int nsh = 0, deferred = 0;
       for (int f = 0; f < nin; f++) {
         if (!shared_in(fin[f], f)) continue;
         Op o = B.blank(OP_DEC, S_COMPUTE);
         if (fin[f].coded) {
           const size_t lb = lb_in(x.t);   // the previous slab is of the same sweep
-          o.dev_src = (int64_t)(p.off_stage[x.pq] + (size_t)nsh * (size_t)(x.pv_planes / 4) * lb +
-                                (size_t)(x.sh_src / 4) * lb);
+          const int64_t from = (int64_t)(p.off_stage[x.pq] + (size_t)nsh * (size_t)(x.pv_planes / 4) * lb +
+                                         (size_t)(x.sh_src / 4) * lb);
+          const int64_t nbytes = (int64_t)((size_t)(x.sh / 4) * lb);
+          if (read_in_place) {
+            sh_off[nsh] = from;
+            sh_bytes[nsh] = nbytes;
+            nsh++;
+            deferred++;
+            continue;
+          }
+          // a device-to-device move into this slab's slot
+          o.dev_src = from;
           o.dev_dst = (int64_t)(p.off_stage[x.q] + (size_t)nsh * (size_t)(x.sl->planes / 4) * lb +
                                 (size_t)(x.loc0 / 4) * lb);
-          o.bytes = (int64_t)((size_t)(x.sh / 4) * lb);
+          o.bytes = nbytes;
           nsh++;
         } else if (stash && fin[f].buf != bv) {
           // a pressure field of an uncompressed wave run: from the stash
@@ -492,7 +516,10 @@ void build_ops(const Plan &p, int64_t sweeps, int steps_last, int src, int64_t s
         o.sweep = x.t;
         B.push(o);
       }
-      B.rec(S_COMPUTE, B.ev.shr(x.pq));
+      // the previous slot's shared planes are consumed once the moves are
+      // done, or, when decodes read them there, once the decodes are
+      sh_after_decode = deferred > 0;
+      if (!sh_after_decode) B.rec(S_COMPUTE, B.ev.shr(x.pq));
     }
     if (p.fused) {
       // one kernel: the slot's codes in, the interior's codes out past them
@@ -521,6 +548,8 @@ void build_ops(const Plan &p, int64_t sweeps, int steps_last, int src, int64_t s
         o.dev_src = (int64_t)(p.off_stage[x.q] + (size_t)ncoded * (size_t)(x.sl->planes / 4) * lb +
                               (size_t)(x.loc0 / 4) * lb);
         o.dev_dst = (int64_t)(B.work(x.q, fin[f].buf) + (size_t)x.loc0 * p.plane_bytes);
+        o.dev_src2 = sh_off[ncoded];
+        o.bytes = sh_bytes[ncoded];
         o.z_hi = x.nload / 4;
         o.planes = x.nload;
         o.slab = x.j;
@@ -539,6 +568,7 @@ void build_ops(const Plan &p, int64_t sweeps, int steps_last, int src, int64_t s
         B.push(o);
       }
     }
+    if (sh_after_decode) B.rec(S_COMPUTE, B.ev.shr(x.pq));
     if (stash && has_share_copy(g + 1)) {
       // set the planes the next slab shares aside before the leapfrog
       // overwrites them
@@ -1035,8 +1065,9 @@ std::string dump_ops(const std::vector<Op> &ops) {
       snprintf(line, sizeof line, "%zu s%d %s ev=%d\n", i, o.stream, names[o.type], o.ev);
     else
       snprintf(line, sizeof line,
-               "%zu s%d %s sweep=%d slab=%d src=%lld dst=%lld host=%d off=%lld bytes=%lld z=[%lld,%lld) lv=%d rate=%d\n",
-               i, o.stream, names[o.type], o.sweep, o.slab, (long long)o.dev_src, (long long)o.dev_dst,
+               "%zu s%d %s sweep=%d slab=%d src=%lld src2=%lld dst=%lld host=%d off=%lld bytes=%lld z=[%lld,%lld) lv=%d rate=%d\n",
+               i, o.stream, names[o.type], o.sweep, o.slab, (long long)o.dev_src, (long long)o.dev_src2,
+               (long long)o.dev_dst,
                o.host_id, (long long)o.host_off, (long long)o.bytes, (long long)o.z_lo, (long long)o.z_hi,
                (int)o.levels, (int)o.rate);
     out += line;
@@ -1074,8 +1105,12 @@ void accesses(const Plan &p, const Op &o, std::vector<Access> *a) {
         dev(o.dev_src, o.bytes, false);
         dev(o.dev_dst, o.bytes, true);
       } else {
+        // codes [0, bytes) from dev_src2 when set (shared layers left in the
+        // previous slab's slot), the rest from dev_src at the same positions
         const size_t lb = o.rate > 0 ? coded_layer_bytes(p.in.nx, p.in.ny, o.rate) : p.layer_bytes;
-        dev(o.dev_src, (int64_t)((size_t)o.z_hi * lb), false);
+        const int64_t lo = o.dev_src2 >= 0 ? o.bytes : 0;
+        if (lo > 0) dev(o.dev_src2, lo, false);
+        dev(o.dev_src + lo, (int64_t)((size_t)o.z_hi * lb) - lo, false);
         dev(o.dev_dst, (int64_t)((size_t)o.z_hi * 4 * p.plane_bytes), true);
       }
       break;
