@@ -367,6 +367,24 @@ void build_ops(const Plan &p, int64_t sweeps, int steps_last, int src, int64_t s
   // slab g's slot is next written by the copy-in of slab g + NQ; the shared
   // planes of slab g are read by slab g + 1's overlap copy
   auto has_share_copy = [&](int64_t g) { return p.share && g >= 0 && g < total && g % ns != 0; };
+  // region sharing, coded fields with the three-kernel path: slab g's decoder
+  // reads the shared layers where slab g - 1's copy-in left them (that slab's
+  // slot, at the field's stride), so no copy precedes it -- unless slab g + 1
+  // shares planes that slab g itself got from slab g - 1 (slabs thinner than
+  // the shared region): those must then be in slab g's slot, so they are
+  // copied there.  The copy-in that next overwrites slab g - 1's slot then
+  // waits for slab g's whole kernel sequence (its "out" event), which the
+  // decode precedes, instead of a separate event after the decode.
+  auto reads_in_place = [&](int64_t g) {
+    if (!p.coded || p.fused || !has_share_copy(g)) return false;
+    const Geo x = geo(g);
+    if (x.sh <= 0) return false;
+    if (has_share_copy(g + 1)) {
+      const Geo nx1 = geo(g + 1);
+      if (nx1.sh > 0 && nx1.sh_src < x.loc0 + x.sh) return false;
+    }
+    return true;
+  };
   // fields copied in: (host store, base offset, working buffer, coded?)
   struct In { int host_id; size_t host_base; int buf; bool coded; };
   auto inputs = [&](const Geo &x, In *fin) {
@@ -411,7 +429,8 @@ void build_ops(const Plan &p, int64_t sweeps, int steps_last, int src, int64_t s
       // that copy if this copy-in overwrites any of them
       const Geo nx1 = geo(g - NQ + 1);
       const int64_t wlo = x.loc0 + x.sh, whi = x.loc0 + x.nload;
-      if (wlo < whi && wlo < nx1.sh_src + nx1.sh && nx1.sh_src < whi) w.push_back(B.ev.shr(x.q));
+      if (wlo < whi && wlo < nx1.sh_src + nx1.sh && nx1.sh_src < whi)
+        w.push_back(reads_in_place(g - NQ + 1) ? B.ev.out(nx1.q) : B.ev.shr(x.q));
     }
     if (x.t > 0) {                                   // planes written by last sweep's copy-backs
       B.writers_of(x.sl->l0, x.sl->l1, &nb);
@@ -456,26 +475,16 @@ void build_ops(const Plan &p, int64_t sweeps, int steps_last, int src, int64_t s
     In fin[3];
     const int nin = inputs(x, fin);
     B.wait(S_COMPUTE, B.ev.h2d(x.t & 1, x.j));
-    // region sharing, coded fields with the three-kernel path: the decoder
-    // reads the shared layers where the previous slab's copy-in left them
-    // (that slab's slot, at the field's stride), so no copy precedes it --
-    // unless the next slab shares planes of this one that this slab itself
-    // got from the previous one (slabs thinner than the shared region): those
-    // must then be in this slab's slot, so they are copied there
+    // coded shared layers read where the previous slab left them, or moved
     int64_t sh_off[3] = {-1, -1, -1}, sh_bytes[3] = {0, 0, 0};
-    bool sh_after_decode = false;
-    bool read_in_place = !p.fused;
-    if (x.sh > 0 && has_share_copy(g + 1)) {
-      const Geo nx1 = geo(g + 1);
-      if (nx1.sh > 0 && nx1.sh_src < x.loc0 + x.sh) read_in_place = false;
-    }
+    const bool read_in_place = reads_in_place(g);
     if (x.sh > 0) {
       // region sharing: the planes around the common face come from the
       // previous slab's input; otherwise by device-to-device moves (raw
       // marker z_hi < 0): each coded field (fused codec kernel, or planes the
       // next slab needs) at its stride in the staging slot, the raw field,
       // the raw c0 slab
-      int nsh = 0, deferred = 0;
+      int nsh = 0;
       for (int f = 0; f < nin; f++) {
         if (!shared_in(fin[f], f)) continue;
         Op o = B.blank(OP_DEC, S_COMPUTE);
@@ -488,7 +497,6 @@ void build_ops(const Plan &p, int64_t sweeps, int steps_last, int src, int64_t s
             sh_off[nsh] = from;
             sh_bytes[nsh] = nbytes;
             nsh++;
-            deferred++;
             continue;
           }
           // a device-to-device move into this slab's slot
@@ -517,9 +525,8 @@ void build_ops(const Plan &p, int64_t sweeps, int steps_last, int src, int64_t s
         B.push(o);
       }
       // the previous slot's shared planes are consumed once the moves are
-      // done, or, when decodes read them there, once the decodes are
-      sh_after_decode = deferred > 0;
-      if (!sh_after_decode) B.rec(S_COMPUTE, B.ev.shr(x.pq));
+      // done (when the decodes read them there, the slab's "out" event marks it)
+      if (!read_in_place) B.rec(S_COMPUTE, B.ev.shr(x.pq));
     }
     if (p.fused) {
       // one kernel: the slot's codes in, the interior's codes out past them
@@ -568,7 +575,6 @@ void build_ops(const Plan &p, int64_t sweeps, int steps_last, int src, int64_t s
         B.push(o);
       }
     }
-    if (sh_after_decode) B.rec(S_COMPUTE, B.ev.shr(x.pq));
     if (stash && has_share_copy(g + 1)) {
       // set the planes the next slab shares aside before the leapfrog
       // overwrites them
