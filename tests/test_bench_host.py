@@ -73,3 +73,22 @@ def test_kernel_roofline_arithmetic(bench):
     assert roof["kernel"] == "stencil"            # the largest total time
     assert roof["frac"] == pytest.approx(roof["achieved"] / roof["peak"])
     assert roof["unit"] == "GB/s" and roof["bound"] == "hbm"
+
+
+def test_kernel_roofline_counts_the_load_rate_sweep(bench):
+    # one sweep of the STEPS / K decodes L-bit codes, the others R-bit codes
+    rate, lr = 3, 8
+    sweeps = bench.STEPS // bench.K
+    st = {"ms_decode": 1.6, "n_decode": 16, "ms_encode": 1.0, "n_encode": 16, "ms_stencil": 3.0,
+          "n_stencil": 16, "ms_fused": 0.0, "n_fused": 0, "blocks_decode": sweeps * 1000,
+          "blocks_encode": sweeps * 900, "bytes_stencil": 16 * 1e6}
+    d = bench.kernel_roofline([st], rate, lr)["decode"]
+    per_launch = ((sweeps - 1) * 1000 * (8 * rate + 256) + 1000 * (8 * lr + 256)) / 16
+    assert d["bytes_per_launch"] == pytest.approx(per_launch)
+    e = bench.kernel_roofline([st], rate, lr)["encode"]
+    assert e["bytes_per_launch"] == pytest.approx(sweeps * 900 * (256 + 8 * rate) / 16)
+
+
+def test_leg_names(bench):
+    assert bench.leg_name(0) == "0" and bench.leg_name(5) == "5"
+    assert bench.leg_name(3, 8) == "3:8"
