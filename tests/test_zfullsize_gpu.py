@@ -56,10 +56,11 @@ def run_full(u0, R, fused=False, load_rate=0):
 
 
 # R = 5 is the smallest uniform rate within 1e-3 over the full grid (6.6e-4,
-# measured by the benchmark; R = 8: 8.3e-5); R = 3 with the load encoded at 6
-# bits: 5.2e-4.  On 12 sampled cells the bar is looser.
+# measured by the benchmark; R = 8: 8.3e-5); R = 3 with the load encoded at 5
+# bits (the fastest leg within the budget): 7.7e-4, at 6 bits: 5.2e-4.  On 12
+# sampled cells the bar is looser.
 @pytest.mark.parametrize("R,L,tol", [(0, 0, 1e-5), (16, 0, 1e-4), (8, 0, 1e-3), (5, 0, 3e-3),
-                                     (3, 6, 3e-3)])
+                                     (3, 5, 3e-3), (3, 6, 3e-3)])
 def test_fullsize_sampled_vs_oracle(u0, R, L, tol):
     got, st = run_full(u0, R, load_rate=L)
     pts = sample_points()
@@ -69,7 +70,8 @@ def test_fullsize_sampled_vs_oracle(u0, R, L, tol):
     assert st["n_slabs"] == 32 and st["slab_visits"] == 32 * 16
     MiB = 1 << 20
     assert st["peak_dev_bytes"] == {(0, 0): 432 * MiB, (16, 0): 252 * MiB, (8, 0): 198 * MiB,
-                                    (5, 0): int(177.75 * MiB), (3, 6): int(184.5 * MiB)}[R, L]
+                                    (5, 0): int(177.75 * MiB), (3, 5): int(177.75 * MiB),
+                                    (3, 6): int(184.5 * MiB)}[R, L]
     if (R, L) in ((5, 0), (8, 0)):
         # the fused codec kernel at full size: the same output, in 63.75 / 102 MiB
         fused, sf = run_full(u0, R, fused=True)
