@@ -215,17 +215,40 @@ __device__ __forceinline__ void fused_plane(FusedState<K, FIELD> &st, float (*ed
     const bool p_in = !MASK || (gz0 + p >= 0 && gz0 + p < nz);
     const float up = edge[par ^ 1][s - 1][wu][1][lane];
     const float dn = edge[par ^ 1][s - 1][wd][0][lane];
+    // star7_point's operation order, with the two x terms as FMAs that read
+    // their first operand through a DPP wave shift (lane - 1, lane + 1; zero
+    // at the wave's ends), for all RY rows in one block: each row's
+    // accumulator is next read RY - 1 instructions after it is written, and
+    // the leading s_nop covers the VALU-write-to-DPP-read distance for the
+    // accumulators and row values written just before the block
+    float v[RY];
+#pragma unroll
+    for (int r = 0; r < RY; r++) v[r] = (FIELD ? st.cw[s - 1][r] : c.c0) * st.win[s - 1][C][r];
+    static_assert(RY == 5, "the DPP block below is written for five rows");
+    asm("s_nop 4\n\t"
+        "v_fmac_f32_dpp %0, %5, %10 wave_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+        "v_fmac_f32_dpp %1, %6, %10 wave_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+        "v_fmac_f32_dpp %2, %7, %10 wave_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+        "v_fmac_f32_dpp %3, %8, %10 wave_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+        "v_fmac_f32_dpp %4, %9, %10 wave_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+        "v_fmac_f32_dpp %0, %5, %11 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+        "v_fmac_f32_dpp %1, %6, %11 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+        "v_fmac_f32_dpp %2, %7, %11 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+        "v_fmac_f32_dpp %3, %8, %11 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+        "v_fmac_f32_dpp %4, %9, %11 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1"
+        : "+v"(v[0]), "+v"(v[1]), "+v"(v[2]), "+v"(v[3]), "+v"(v[4])
+        : "v"(st.win[s - 1][C][0]), "v"(st.win[s - 1][C][1]), "v"(st.win[s - 1][C][2]),
+          "v"(st.win[s - 1][C][3]), "v"(st.win[s - 1][C][4]), "v"(c.cmx), "v"(c.cpx));
     float nv[RY];
 #pragma unroll
     for (int r = 0; r < RY; r++) {
-      const float cur = st.win[s - 1][C][r];
-      const float xm = lane_from_left(cur);
-      const float xp = lane_from_right(cur);
       const float ym = r > 0 ? st.win[s - 1][C][r - 1] : up;
       const float yp = r < RY - 1 ? st.win[s - 1][C][r + 1] : dn;
-      const float c0 = FIELD ? st.cw[s - 1][r] : c.c0;
-      const float v = star7_point(c0, cur, xm, xp, ym, yp, st.win[s - 1][O][r], st.win[s - 1][N][r], c);
-      nv[r] = (!MASK || (p_in && st.row_in[r])) ? v : 0.0f;
+      float w = fmaf(c.cmy, ym, v[r]);
+      w = fmaf(c.cpy, yp, w);
+      w = fmaf(c.cmz, st.win[s - 1][O][r], w);
+      w = fmaf(c.cpz, st.win[s - 1][N][r], w);
+      nv[r] = (!MASK || (p_in && st.row_in[r])) ? w : 0.0f;
     }
     if (s < K) {
 #pragma unroll
