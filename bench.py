@@ -260,8 +260,8 @@ KERNEL_COUNTERS = {
                     "source": "profiles/codec_stencil_kernels_slab_512x512x72_r3.md"},
     ("encode", 3): {"traffic": 1.011, "valu_per_wave": 5120, "active_lanes": 0.78,
                     "source": "profiles/codec_stencil_kernels_slab_512x512x72_r3.md"},
-    ("stencil", None): {"traffic": 1.180,
-                        "source": "profiles/codec_stencil_kernels_slab_512x512x72.md"},
+    ("stencil", None): {"traffic": 1.175,
+                        "source": "profiles/codec_stencil_kernels_slab_512x512x72_r3.md"},
 }
 
 
