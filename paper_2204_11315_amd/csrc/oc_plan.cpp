@@ -480,10 +480,10 @@ void build_ops(const Plan &p, int64_t sweeps, int steps_last, int src, int64_t s
     const bool read_in_place = reads_in_place(g);
     if (x.sh > 0) {
       // region sharing: the planes around the common face come from the
-      // previous slab's input; otherwise by device-to-device moves (raw
-      // marker z_hi < 0): each coded field (fused codec kernel, or planes the
-      // next slab needs) at its stride in the staging slot, the raw field,
-      // the raw c0 slab
+      // previous slab's input -- coded fields read in place by the decoder
+      // (above), otherwise device-to-device moves (raw marker z_hi < 0): a
+      // coded field at its stride in the staging slot (fused codec kernel,
+      // or planes the next slab needs), the raw field, the raw c0 slab
       int nsh = 0;
       for (int f = 0; f < nin; f++) {
         if (!shared_in(fin[f], f)) continue;
