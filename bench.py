@@ -172,6 +172,39 @@ def run_leg(oc, torch, u0, rate, steps, warmup, ref=None, fused=False, keep=Fals
         o.close()
 
 
+def choose_legs(legs, rate_arg, budget, error_mode):
+    """The headline leg and the fused-kernel rate from the measured legs
+    (keyed by leg_name; "0" is the uncompressed leg).  Headline: the rate set
+    on the command line, else the fastest compressed leg whose rel-L2 against
+    FP64 is within `budget`, else (none within it) the largest uniform rate,
+    said so.  The fused codec kernel codes at one rate: the headline's when it
+    is uniform, else the smallest uniform rate within the budget (None: no
+    such rate).  Returns (head, how, budget_met, fused_rate)."""
+    def rel_of(name):
+        e = legs[name]["error_vs_fp64"]
+        return None if e is None else e["rel_l2"]
+
+    def meets(name):
+        return rel_of(name) is not None and rel_of(name) <= budget
+
+    coded = [n for n in legs if n != "0"]
+    uniform = sorted(int(n) for n in coded if ":" not in n)
+    budget_met = None
+    if rate_arg:
+        head = leg_name(rate_arg)
+        how = "rate set on the command line"
+    else:
+        ok = [n for n in coded if meets(n)]
+        budget_met = bool(ok)
+        head = max(ok, key=lambda n: legs[n]["gcell_per_s"]) if ok else str(max(uniform))
+        how = ("fastest leg with %s rel-L2 <= %g" % (error_mode, budget) if ok else
+               "NO candidate leg met rel-L2 <= %g (%s); largest rate shown" % (budget, error_mode))
+    hrate, hload = legs[head]["rate_bits"], legs[head]["load_rate_bits"]
+    within = [r for r in uniform if meets(str(r))]
+    frate = hrate if hload == hrate else (within[0] if within else None)
+    return head, how, budget_met, frate
+
+
 def digest(a):
     """Digest of an array's bytes (equal outputs of two legs)."""
     try:
@@ -842,31 +875,10 @@ def main():
             None if err is None else {k: float("%.3g" % v) for k, v in err.items()},
             st["peak_dev_bytes"] >> 20, mem["torch_peak_allocated_bytes"] >> 20))
 
-    def rel_of(name):
-        e = legs[name]["error_vs_fp64"]
-        return None if e is None else e["rel_l2"]
-
-    def meets(name):
-        return rel_of(name) is not None and rel_of(name) <= args.budget
-
-    budget_met = None
-    if args.rate:
-        head = leg_name(args.rate)
-        how = "rate set on the command line"
-    else:
-        ok = [leg_name(*kl) for kl in keys[1:] if meets(leg_name(*kl))]
-        budget_met = bool(ok)
-        head = max(ok, key=lambda n: legs[n]["gcell_per_s"]) if ok else leg_name(max(cands))
-        how = ("fastest leg with %s rel-L2 <= %g" % (args.error, args.budget) if ok else
-               "NO candidate leg met rel-L2 <= %g (%s); largest rate shown" % (
-                   args.budget, args.error))
+    head, how, budget_met, frate = choose_legs(legs, args.rate, args.budget, args.error)
     main_leg = legs[head]
     hrate, hload = main_leg["rate_bits"], main_leg["load_rate_bits"]
     base_leg = legs["0"]
-    # the fused codec kernel codes at one rate: the smallest uniform rate that
-    # meets the budget (the headline's rate when the headline is uniform)
-    uni = [r for r in sorted(cands) if meets(str(r))]
-    frate = hrate if hload == hrate else (uni[0] if uni else None)
     fused = None
     if not args.no_fused and frate is not None and frate <= 16:
         fused = fused_leg(oc, torch, u0, frate, args, ref, cells, digests[str(frate)])
@@ -907,7 +919,7 @@ def main():
         "speedup_vs_uncompressed": main_leg["gcell_per_s"] / base_leg["gcell_per_s"],
         "end_to_end_ms": main_leg["end_to_end_ms"],
         "uncompressed_end_to_end_ms": base_leg["end_to_end_ms"],
-        "rel_l2_vs_fp64": rel_of(head),
+        "rel_l2_vs_fp64": (main_leg["error_vs_fp64"] or {}).get("rel_l2"),
         "error_vs_fp64": main_leg["error_vs_fp64"],
         "error_reference": args.error,
         "uncompressed_error_vs_fp64": base_leg["error_vs_fp64"],

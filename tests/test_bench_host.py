@@ -92,3 +92,37 @@ def test_kernel_roofline_counts_the_load_rate_sweep(bench):
 def test_leg_names(bench):
     assert bench.leg_name(0) == "0" and bench.leg_name(5) == "5"
     assert bench.leg_name(3, 8) == "3:8"
+
+
+def _legs(spec):
+    # spec: name -> (GCell/s, rel-L2 or None)
+    legs = {}
+    for n, (g, e) in spec.items():
+        r, lr = (int(v) for v in n.split(":")) if ":" in n else (int(n), 0)
+        legs[n] = {"gcell_per_s": g, "error_vs_fp64": None if e is None else {"rel_l2": e},
+                   "rate_bits": r, "load_rate_bits": lr or r}
+    return legs
+
+
+def test_headline_is_the_fastest_leg_within_the_budget(bench):
+    legs = _legs({"0": (34, 1e-6), "4": (290, 1.3e-3), "5": (237, 6.6e-4), "8": (146, 8e-5),
+                  "2:8": (364, 1.2e-3), "3:5": (342, 7.7e-4), "3:6": (335, 5.2e-4)})
+    head, how, met, frate = bench.choose_legs(legs, 0, 1e-3, "full")
+    assert (head, met) == ("3:5", True) and how.startswith("fastest leg")
+    assert frate == 5                      # the smallest uniform rate within the budget
+    # a uniform headline takes the fused kernel at its own rate
+    legs["3:5"]["error_vs_fp64"]["rel_l2"] = 2e-3
+    legs["3:6"]["error_vs_fp64"]["rel_l2"] = 2e-3
+    assert bench.choose_legs(legs, 0, 1e-3, "full")[0::3] == ("5", 5)
+
+
+def test_headline_when_no_leg_meets_the_budget_or_a_rate_is_given(bench):
+    legs = _legs({"0": (34, 1e-6), "4": (290, 1.3e-3), "8": (146, 2e-3), "3:5": (342, 1.5e-3)})
+    head, how, met, frate = bench.choose_legs(legs, 0, 1e-3, "full")
+    assert (head, met, frate) == ("8", False, 8) and how.startswith("NO candidate")
+    head, how, met, frate = bench.choose_legs(legs, 4, 1e-3, "full")
+    assert (head, met, frate) == ("4", None, 4) and how == "rate set on the command line"
+    # no error reference at all: nothing meets the budget
+    legs = _legs({"0": (34, None), "5": (237, None), "3:5": (342, None)})
+    head, _, met, frate = bench.choose_legs(legs, 0, 1e-3, "none")
+    assert (head, met, frate) == ("5", False, 5)
